@@ -1,0 +1,133 @@
+"""Brute-force time-domain TDI (test infrastructure): the definition the fast/slow model approximates.
+
+For tiny cases (M <= 2^18 samples) the TDI X, Y, Z are evaluated at every sample time
+directly from the plane-wave field, with every retardation and delay taken exactly, and
+then transformed with a full-length FFT: x~_k = dt * sum_n x_n e^{-2 pi i k n / M}.
+Nothing here uses the slow series, the N-point DFT or the sinc form of the oracle, and the
+orbits come from the classic first-order heliocentric formula rather than the rigid-triangle
+construction used there.  This module is the independent pin of the oracle's model.
+
+Geometry modes
+  G1 -- every position and arm vector is taken at the TDI output time t (also inside the
+        delayed terms); only the wave's time arguments are retarded.  This is the
+        approximation the fast/slow form makes, so it must agree to rounding when the slow
+        series is exactly band-limited (periodic orbit, fdot = 0, integer f0 T).
+  G2 -- emitter position at the emission time, receiver position at the reception time,
+        each delayed term with its own geometry.  Measures the frozen-arm approximation.
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+C_LIGHT = 299792458.0
+
+
+def orbits(t, P_orb, L, AU):
+    """Spacecraft positions, shape [3, len(t), 3] (m): first-order eccentric heliocentric orbits
+    x_i = R cos a + e R/2 (cos(2a - b_i) - 3 cos b_i), y_i = R sin a + e R/2 (sin(2a - b_i) - 3 sin b_i),
+    z_i = -sqrt3 e R cos(a - b_i), with e = L / (2 sqrt3 R), a = 2 pi t / P, b_i = 2 pi i / 3."""
+    t = np.asarray(t, dtype=np.float64)
+    a = 2.0 * math.pi * t / P_orb
+    e = L / (2.0 * math.sqrt(3.0) * AU)
+    out = np.empty((3,) + t.shape + (3,))
+    for i in range(3):
+        b = 2.0 * math.pi * i / 3.0
+        out[i, ..., 0] = AU * np.cos(a) + 0.5 * e * AU * (np.cos(2 * a - b) - 3.0 * math.cos(b))
+        out[i, ..., 1] = AU * np.sin(a) + 0.5 * e * AU * (np.sin(2 * a - b) - 3.0 * math.sin(b))
+        out[i, ..., 2] = -math.sqrt(3.0) * e * AU * np.cos(a - b)
+    return out
+
+
+def polarisation(theta):
+    """Propagation direction k and the psi-rotated tensors e+, ex (3x3) of one source."""
+    f0, fdot, beta, lam, amp, iota, psi, phi0 = [float(x) for x in theta]
+    k = -np.array([math.cos(beta) * math.cos(lam), math.cos(beta) * math.sin(lam), math.sin(beta)])
+    u = np.array([math.sin(beta) * math.cos(lam), math.sin(beta) * math.sin(lam), -math.cos(beta)])
+    v = np.array([math.sin(lam), -math.cos(lam), 0.0])
+    ep0 = np.outer(u, u) - np.outer(v, v)
+    ec0 = np.outer(u, v) + np.outer(v, u)
+    ep = math.cos(2 * psi) * ep0 + math.sin(2 * psi) * ec0
+    ec = -math.sin(2 * psi) * ep0 + math.cos(2 * psi) * ec0
+    ap = amp * (1.0 + math.cos(iota) ** 2)
+    ac = -2.0 * amp * math.cos(iota)
+    return k, ep, ec, ap, ac
+
+
+def _phase(theta, tau):
+    """Phi(tau) = 2 pi f0 tau + pi fdot tau^2 + phi0, reduced in cycles before the 2 pi."""
+    f0, fdot, phi0 = float(theta[0]), float(theta[1]), float(theta[7])
+    cyc = f0 * tau + 0.5 * fdot * tau * tau
+    cyc = cyc - np.round(cyc)
+    return 2.0 * math.pi * cyc + phi0
+
+
+def _nHn(theta, pol, n, tau):
+    """n . H(tau) . n for arm unit vectors n [..., 3] and times tau [...]:
+    H = A+ cos(Phi) e+ + Ax sin(Phi) ex."""
+    k, ep, ec, ap, ac = pol
+    fp = np.einsum("...i,ij,...j->...", n, ep, n)
+    fc = np.einsum("...i,ij,...j->...", n, ec, n)
+    ph = _phase(theta, tau)
+    return ap * np.cos(ph) * fp + ac * np.sin(ph) * fc
+
+
+def link(theta, pol, t, r, s, delay, P_orb, L, AU, mode="G1"):
+    """y_rs(t - delay L/c): light emitted at s, received at r (0-based spacecraft indices).
+    y = [n.H(t_emit - k.x_s/c).n - n.H(t_recv - k.x_r/c).n] / (2 (1 - k.n)), n = (x_r - x_s)/|.|."""
+    k = pol[0]
+    t_recv = t - delay * L / C_LIGHT
+    t_emit = t_recv - L / C_LIGHT
+    if mode == "G1":
+        x = orbits(t, P_orb, L, AU)
+        xr, xs = x[r], x[s]
+    else:
+        xr = orbits(t_recv, P_orb, L, AU)[r]
+        xs = orbits(t_emit, P_orb, L, AU)[s]
+    sep = xr - xs
+    n = sep / np.linalg.norm(sep, axis=-1, keepdims=True)
+    kn = n @ k
+    h_emit = _nHn(theta, pol, n, t_emit - (xs @ k) / C_LIGHT)
+    h_recv = _nHn(theta, pol, n, t_recv - (xr @ k) / C_LIGHT)
+    return (h_emit - h_recv) / (2.0 * (1.0 - kn))
+
+
+def tdi_xyz(theta, t, P_orb, L, AU, mode="G1"):
+    """First-generation equal-arm Michelson X, Y, Z at times t (arrays).
+    X = y13 + y31(t-L) + y12(t-2L) + y21(t-3L) - y12 - y21(t-L) - y13(t-2L) - y31(t-3L),
+    Y, Z by the cyclic relabelling 1 -> 2 -> 3 -> 1."""
+    pol = polarisation(theta)
+
+    def y(r, s, j):
+        return link(theta, pol, t, r - 1, s - 1, j, P_orb, L, AU, mode)
+
+    def michelson(a, b, c):
+        return (y(a, c, 0) + y(c, a, 1) + y(a, b, 2) + y(b, a, 3)
+                - y(a, b, 0) - y(b, a, 1) - y(a, c, 2) - y(c, a, 3))
+
+    X = michelson(1, 2, 3)
+    Y = michelson(2, 3, 1)
+    Z = michelson(3, 1, 2)
+    return X, Y, Z
+
+
+def tdi_aet(theta, t, P_orb, L, AU, mode="G1"):
+    X, Y, Z = tdi_xyz(theta, t, P_orb, L, AU, mode)
+    A = (Z - X) / math.sqrt(2.0)
+    E = (X - 2.0 * Y + Z) / math.sqrt(6.0)
+    T = (X + Y + Z) / math.sqrt(3.0)
+    return A, E, T
+
+
+def spectrum(theta, M, dt, P_orb, L, AU, mode="G1", chunk=1 << 15):
+    """Full-length spectra x~_k = dt FFT(x) of A, E, T sampled at t_n = n dt, n < M; [3, M]."""
+    series = np.empty((3, M))
+    for a in range(0, M, chunk):
+        t = dt * np.arange(a, min(M, a + chunk), dtype=np.float64)
+        A, E, T = tdi_aet(theta, t, P_orb, L, AU, mode)
+        series[0, a:a + len(t)] = A
+        series[1, a:a + len(t)] = E
+        series[2, a:a + len(t)] = T
+    return dt * np.fft.fft(series, axis=1), series
