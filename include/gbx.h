@@ -1,0 +1,146 @@
+/*
+ * gbx -- batched Galactic-binary log-likelihood on AMD MI355X (gfx950).
+ *
+ * C ABI of the hot path of Strub et al., arXiv:2307.03763: the log-likelihood of many
+ * eight-parameter Galactic-binary candidates against LISA TDI data in narrow frequency
+ * windows, its gradient, and the independent-proposal Metropolis-Hastings step that
+ * consumes it.
+ *
+ * Conventions shared by every call
+ *  - theta rows are 8 doubles (f0 [Hz], fdot [Hz/s], beta, lambda [rad], amplitude,
+ *    iota, psi, phi0 [rad]) -- the parameter set of Sec. III.
+ *  - Frequency bins are absolute: bin k sits at f = k / T.  Data and weights of a window
+ *    are stored channel-major, [C][W]; channels are A, E (C = 2) or A, E, T (C = 3), the
+ *    combinations of Sec. II.  Complex values are two doubles (re, im).
+ *  - Unless stated otherwise every array argument is a DEVICE pointer owned by the caller
+ *    (for example a torch tensor); gb_config and gb_window arrays are HOST memory.
+ *  - Calls are asynchronous on `stream` (a hipStream_t passed as void*; NULL = the null
+ *    stream).  The hot calls (gb_waveform, gb_loglik, gb_loglik_grad, gb_mh_step,
+ *    gb_window_prepare) allocate nothing, copy nothing between host and device and never
+ *    synchronise, so they may be captured in a HIP graph.
+ *  - Return status covers argument validation and launch errors.  Faults during execution
+ *    surface at the caller's next synchronisation.  gb_last_error() returns a message for
+ *    the last non-OK status of the calling thread.
+ *  - Candidates whose theta is not finite, whose amplitude is negative, or whose f0 is not
+ *    in (0, 0.5 * arm-transfer limit] get NaN outputs; the rest of the batch is unaffected.
+ *  - A plan may be used by one stream at a time (its work queues are per plan).
+ */
+#ifndef GBX_H
+#define GBX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GB_OK = 0,
+  GB_EINVAL = -1,        /* bad argument (message in gb_last_error) */
+  GB_EHIP = -2,          /* a HIP runtime call failed */
+  GB_ENOMEM = -3,        /* device allocation failed (set-up calls only) */
+  GB_EUNSUPPORTED = -4   /* no kernel variant for the requested shape */
+} gb_status;
+
+typedef enum {
+  GB_FP64 = 0,           /* every step in FP64 */
+  GB_MIXED = 1,          /* phase (in cycles) and all accumulations in FP64; response,
+                            slow series and FFT in FP32 with hardware sin/cos */
+  GB_PER_WINDOW = 2      /* plan only: take each window's `precision` field */
+} gb_precision;
+
+/* Observation and constellation constants (set-up; host memory). */
+typedef struct {
+  double T;              /* observation time, s; bin width 1/T */
+  double orbit_period;   /* period of the guiding centre, s (sidereal year) */
+  double arm_length;     /* L, m (half transfer frequency 1/(4 pi L) = 9.55 mHz for 2.5e9 m, Sec. II) */
+  double au;             /* radius of the guiding-centre orbit, m */
+} gb_config;
+
+/* One frequency window: the padded segment of Sec. III B over which the scalar product is
+ * summed (Sec. III D).  Host memory. */
+typedef struct {
+  int64_t k0;            /* absolute index of the first bin */
+  int32_t W;             /* number of bins, >= 1 */
+  int32_t N;             /* slow-series samples per template: power of two in [64, 1024] */
+  int32_t C;             /* channels, 2 (A, E) or 3 (A, E, T) */
+  int32_t precision;     /* gb_precision of this window when the plan is GB_PER_WINDOW */
+  int64_t data_off;      /* element offset of the window's [C][W] block in d and in w */
+  int64_t cand_off;      /* first candidate row of this window in theta and the outputs */
+  int64_t n_cand;        /* number of candidates (rows) of this window, >= 0 */
+} gb_window;
+
+typedef struct gb_ctx gb_ctx;     /* device tables for one gb_config (orbit, twiddles) */
+typedef struct gb_plan gb_plan;   /* work lists and launch shapes for a set of windows */
+
+/* Create a context on the current HIP device: builds the per-sample orbit tables and the
+ * DFT twiddles for N = 64..1024 (device memory owned by the context).  Synchronous.
+ * GB_EINVAL for non-positive constants.  *ctx is NULL on failure. */
+gb_status gb_create(const gb_config* cfg, gb_ctx** ctx);
+void gb_destroy(gb_ctx* ctx);
+
+/* Message of the calling thread's last non-OK status ("" if none). */
+const char* gb_last_error(void);
+
+/* Templates of B sources (Sec. III parameters; the TDI response of Sec. II channels).
+ * h_out: complex128 [B][C][N]; element i of channel c is the template on bin
+ * first_bin[b] + i; first_bin: int64 [B], = floor(f0 T) - N/2.  The template is
+ * (T / 2N) * DFT_N of the carrier-free slow series sampled at t_m = m T / N.
+ * GB_EINVAL: B < 0, N not a power of two in [64, 1024], C not 2 or 3, null pointers. */
+gb_status gb_waveform(gb_ctx* ctx, const double* theta, int64_t B, int N, int C,
+                      gb_precision precision, double* h_out, int64_t* first_bin, void* stream);
+
+/* Build a plan for `n_win` windows (host array, copied): validates every window, groups the
+ * windows by (N, C, precision), splits their candidates into tiles ordered by cost and
+ * uploads the work lists (device memory owned by the plan).  Synchronous; allocates.
+ * GB_EINVAL on a bad window (message names it). */
+gb_status gb_plan_create(gb_ctx* ctx, const gb_window* windows, int n_win,
+                         gb_precision precision, gb_plan** plan);
+void gb_plan_destroy(gb_plan* plan);
+
+/* <d|d> of every window (sum over channels and bins of w |d|^2), kept in the plan.  Must be
+ * called after the data or weights change and before gb_loglik / gb_loglik_grad /
+ * gb_mh_step, which reject other d, w pointers than the prepared ones.
+ * d: complex128, w: float64 (w = 4 / (T S), the discretised weight of the scalar product of
+ * Sec. II), both indexed by gb_window.data_off. */
+gb_status gb_window_prepare(gb_plan* plan, const double* d, const double* w, void* stream);
+
+/* logL = -1/2 sum_c sum_{k in window} w_k |d_k - h_k|^2 of every candidate
+ * (Sec. II log-likelihood and scalar product; Sec. III D window).  theta: [rows][8] where
+ * window i owns rows cand_off .. cand_off + n_cand - 1.  logL: [rows].  comps (may be NULL):
+ * [rows][2] = <d|h>, <h|h>, from which rho = <d|h>/sqrt<h|h> and A_max = A <d|h>/<h|h>
+ * (Sec. III SNR and amplitude equations).  Rows that no window owns are not written. */
+gb_status gb_loglik(gb_plan* plan, const double* d, const double* w, const double* theta,
+                    double* logL, double* comps, void* stream);
+
+/* logL and its gradient grad: [rows][8], d logL / d theta in the order of theta (the
+ * carrier bin floor(f0 T) held fixed).  Hand-written adjoint: inverse DFT of the
+ * weighted residual, then the slow-series derivative contracted with it. */
+gb_status gb_loglik_grad(gb_plan* plan, const double* d, const double* w, const double* theta,
+                         double* logL, double* grad, void* stream);
+
+/* One stage of Algorithm 4 for every window of the plan (one window = one source): the
+ * logL of its n_cand proposals in parallel, then the independent-proposal chain
+ * (acceptance equation of Sec. III G, with temperature T):
+ *   start at proposal 0; for i = 1 .. n-1 accept with probability
+ *   min(1, [L_i / L_c * g_c / g_i]^(1/T)), evaluated as  pi_c < pi_i - T ln u_i  with
+ *   pi = logL - log_g (u_i = 0 always accepts; NaN logL never accepted).
+ * log_g, u: [rows] (proposal log-density and uniforms in [0, 1)); outputs logL: [rows],
+ * chain: int32 [rows] (index within the window of the state after each step, chain[0] = 0),
+ * n_accept: int64 [n_win].  GB_EINVAL: temperature <= 0 or not finite. */
+gb_status gb_mh_step(gb_plan* plan, const double* d, const double* w, const double* theta,
+                     const double* log_g, const double* u, double temperature,
+                     double* logL, int32_t* chain, int64_t* n_accept, void* stream);
+
+/* Choose the launch shape (lanes per template, waves per workgroup) of every (N, C,
+ * precision) group by timing the compiled variants on synthetic candidates; the choice is
+ * kept in the context and used by plans created afterwards.  Synchronous; allocates.
+ * `report` (host, may be NULL) receives a text summary of at most report_len bytes. */
+gb_status gb_autotune(gb_ctx* ctx, int reps, char* report, size_t report_len);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GBX_H */

@@ -1,0 +1,269 @@
+"""Python binding of libgbx.so: argument marshalling only.
+
+Every function has the name of the C entry point it calls (include/gbx.h).  Device memory
+and streams come from torch; all arithmetic runs in the library's HIP kernels.  There is no
+fallback: if the library is missing or no HIP device is present the calls raise.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgbx.so")
+
+GB_OK, GB_EINVAL, GB_EHIP, GB_ENOMEM, GB_EUNSUPPORTED = 0, -1, -2, -3, -4
+GB_FP64, GB_MIXED, GB_PER_WINDOW = 0, 1, 2
+PRECISION = {"fp64": GB_FP64, "mixed": GB_MIXED, "per_window": GB_PER_WINDOW}
+
+EXPORTS = ("gb_create", "gb_destroy", "gb_last_error", "gb_waveform", "gb_plan_create",
+           "gb_plan_destroy", "gb_window_prepare", "gb_loglik", "gb_loglik_grad", "gb_mh_step",
+           "gb_autotune")
+
+
+class GbxError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where} failed with status {status}: {msg}")
+        self.status = status
+
+
+class gb_config(ctypes.Structure):
+    _fields_ = [("T", ctypes.c_double), ("orbit_period", ctypes.c_double),
+                ("arm_length", ctypes.c_double), ("au", ctypes.c_double)]
+
+
+class gb_window(ctypes.Structure):
+    _fields_ = [("k0", ctypes.c_int64), ("W", ctypes.c_int32), ("N", ctypes.c_int32),
+                ("C", ctypes.c_int32), ("precision", ctypes.c_int32), ("data_off", ctypes.c_int64),
+                ("cand_off", ctypes.c_int64), ("n_cand", ctypes.c_int64)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+
+
+def lib():
+    """Load libgbx.so (built in-tree by paper_2307_03763_amd/build.py); raise if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2307_03763_amd/build.py "
+                              "(there is no non-HIP fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        i, i64, d, st = ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+        L.gb_create.argtypes = [ctypes.POINTER(gb_config), ctypes.POINTER(_vp)]
+        L.gb_create.restype = st
+        L.gb_destroy.argtypes = [_vp]
+        L.gb_destroy.restype = None
+        L.gb_last_error.argtypes = []
+        L.gb_last_error.restype = ctypes.c_char_p
+        L.gb_waveform.argtypes = [_vp, _vp, i64, i, i, i, _vp, _vp, _vp]
+        L.gb_waveform.restype = st
+        L.gb_plan_create.argtypes = [_vp, ctypes.POINTER(gb_window), i, i, ctypes.POINTER(_vp)]
+        L.gb_plan_create.restype = st
+        L.gb_plan_destroy.argtypes = [_vp]
+        L.gb_plan_destroy.restype = None
+        L.gb_window_prepare.argtypes = [_vp, _vp, _vp, _vp]
+        L.gb_window_prepare.restype = st
+        L.gb_loglik.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
+        L.gb_loglik.restype = st
+        L.gb_loglik_grad.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
+        L.gb_loglik_grad.restype = st
+        L.gb_mh_step.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, d, _vp, _vp, _vp, _vp]
+        L.gb_mh_step.restype = st
+        L.gb_autotune.argtypes = [_vp, i, ctypes.c_char_p, ctypes.c_size_t]
+        L.gb_autotune.restype = st
+        _lib = L
+    return _lib
+
+
+def _check(status: int, where: str):
+    if status != GB_OK:
+        raise GbxError(status, where, lib().gb_last_error().decode())
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _dev(t: torch.Tensor, dtype, name: str) -> int:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a HIP device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t.data_ptr()
+
+
+def _real_view(t: torch.Tensor) -> torch.Tensor:
+    return torch.view_as_real(t) if t.is_complex() else t
+
+
+# ------------------------------------------------------------------------------------------
+def gb_create(T: float, orbit_period: float, arm_length: float, au: float) -> int:
+    cfg = gb_config(T, orbit_period, arm_length, au)
+    out = _vp()
+    _check(lib().gb_create(ctypes.byref(cfg), ctypes.byref(out)), "gb_create")
+    return out.value
+
+
+def gb_destroy(ctx: int):
+    lib().gb_destroy(ctx)
+
+
+def gb_waveform(ctx: int, theta: torch.Tensor, N: int, C: int, precision: int = GB_FP64, stream=None):
+    """Templates [B, C, N] complex128 and first bins [B] int64 (see include/gbx.h)."""
+    B = theta.shape[0]
+    h = torch.empty((B, C, N), dtype=torch.complex128, device=theta.device)
+    fb = torch.empty((B,), dtype=torch.int64, device=theta.device)
+    _check(lib().gb_waveform(ctx, _dev(theta, torch.float64, "theta"), B, N, C, precision,
+                             _real_view(h).data_ptr(), fb.data_ptr(), _stream(stream)), "gb_waveform")
+    return h, fb
+
+
+def windows_array(table) -> ctypes.Array:
+    """gb_window[] from rows (k0, W, N, C, data_off, w_off(unused), cand_off, n_cand[, precision])."""
+    rows = np.asarray(table, dtype=np.int64).reshape(len(table), -1)
+    arr = (gb_window * len(rows))()
+    for i, r in enumerate(rows):
+        prec = int(r[8]) if len(r) > 8 else GB_FP64
+        arr[i] = gb_window(int(r[0]), int(r[1]), int(r[2]), int(r[3]), prec, int(r[4]), int(r[6]), int(r[7]))
+    return arr
+
+
+def gb_plan_create(ctx: int, table, precision: int) -> int:
+    arr = windows_array(table)
+    out = _vp()
+    _check(lib().gb_plan_create(ctx, arr, len(arr), precision, ctypes.byref(out)), "gb_plan_create")
+    return out.value
+
+
+def gb_plan_destroy(plan: int):
+    lib().gb_plan_destroy(plan)
+
+
+def gb_window_prepare(plan: int, d: torch.Tensor, w: torch.Tensor, stream=None):
+    _check(lib().gb_window_prepare(plan, _dev(_real_view(d), torch.float64, "d"),
+                                   _dev(w, torch.float64, "w"), _stream(stream)), "gb_window_prepare")
+
+
+def gb_loglik(plan: int, d, w, theta, logL, comps=None, stream=None):
+    _check(lib().gb_loglik(plan, _real_view(d).data_ptr(), w.data_ptr(), _dev(theta, torch.float64, "theta"),
+                           _dev(logL, torch.float64, "logL"),
+                           None if comps is None else _dev(comps, torch.float64, "comps"),
+                           _stream(stream)), "gb_loglik")
+
+
+def gb_loglik_grad(plan: int, d, w, theta, logL, grad, stream=None):
+    _check(lib().gb_loglik_grad(plan, _real_view(d).data_ptr(), w.data_ptr(),
+                                _dev(theta, torch.float64, "theta"), _dev(logL, torch.float64, "logL"),
+                                _dev(grad, torch.float64, "grad"), _stream(stream)), "gb_loglik_grad")
+
+
+def gb_mh_step(plan: int, d, w, theta, log_g, u, temperature: float, logL, chain, n_accept, stream=None):
+    _check(lib().gb_mh_step(plan, _real_view(d).data_ptr(), w.data_ptr(), _dev(theta, torch.float64, "theta"),
+                            _dev(log_g, torch.float64, "log_g"), _dev(u, torch.float64, "u"),
+                            float(temperature), _dev(logL, torch.float64, "logL"),
+                            _dev(chain, torch.int32, "chain"), _dev(n_accept, torch.int64, "n_accept"),
+                            _stream(stream)), "gb_mh_step")
+
+
+def gb_autotune(ctx: int, reps: int = 5) -> str:
+    buf = ctypes.create_string_buffer(4096)
+    _check(lib().gb_autotune(ctx, reps, buf, len(buf)), "gb_autotune")
+    return buf.value.decode()
+
+
+# ------------------------------------------------------------------------------------------
+class Context:
+    """Owns a gb_ctx for one (T, orbit, arm length) setting on the current device."""
+
+    def __init__(self, T: float, orbit_period: float, arm_length: float, au: float):
+        self.T = float(T)
+        self.handle = gb_create(T, orbit_period, arm_length, au)
+
+    def waveform(self, theta: torch.Tensor, N: int, C: int, precision: int = GB_FP64, stream=None):
+        return gb_waveform(self.handle, theta, N, C, precision, stream)
+
+    def close(self):
+        if self.handle:
+            gb_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan:
+    """Owns a gb_plan for a fixed set of windows; outputs are allocated per call."""
+
+    def __init__(self, ctx: Context, table, precision: int):
+        self.ctx = ctx
+        t = np.asarray(table, dtype=np.int64).reshape(len(table), -1)
+        self.table = t
+        self.rows = int((t[:, 6] + t[:, 7]).max()) if len(t) else 0
+        self.n_win = len(t)
+        self.handle = gb_plan_create(ctx.handle, t, precision)
+        self.d = self.w = None
+
+    def prepare(self, d: torch.Tensor, w: torch.Tensor, stream=None):
+        d = d.contiguous()
+        w = w.contiguous()
+        gb_window_prepare(self.handle, d, w, stream)
+        self.d, self.w = d, w
+
+    def loglik(self, theta: torch.Tensor, comps: bool = False, stream=None):
+        logL = torch.empty(self.rows, dtype=torch.float64, device=theta.device)
+        cp = torch.empty((self.rows, 2), dtype=torch.float64, device=theta.device) if comps else None
+        gb_loglik(self.handle, self.d, self.w, theta, logL, cp, stream)
+        return (logL, cp) if comps else logL
+
+    def loglik_grad(self, theta: torch.Tensor, stream=None):
+        logL = torch.empty(self.rows, dtype=torch.float64, device=theta.device)
+        grad = torch.empty((self.rows, 8), dtype=torch.float64, device=theta.device)
+        gb_loglik_grad(self.handle, self.d, self.w, theta, logL, grad, stream)
+        return logL, grad
+
+    def mh_step(self, theta, log_g, u, temperature: float, stream=None):
+        logL = torch.empty(self.rows, dtype=torch.float64, device=theta.device)
+        chain = torch.empty(self.rows, dtype=torch.int32, device=theta.device)
+        nacc = torch.empty(self.n_win, dtype=torch.int64, device=theta.device)
+        gb_mh_step(self.handle, self.d, self.w, theta, log_g, u, temperature, logL, chain, nacc, stream)
+        return logL, chain, nacc
+
+    def close(self):
+        if self.handle:
+            gb_plan_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def context_for(T: float):
+    """Context with the synthetic setting's constellation constants."""
+    from . import inputs as I
+    return Context(T, I.YEAR, I.ARM_L, I.AU)
+
+
+def template_fn(ctx: Context, precision: int = GB_FP64, device="cuda"):
+    """Adapter for inputs.finalize_data: injections computed by the HIP path."""
+    def fn(theta, N, C, T):
+        th = torch.as_tensor(np.ascontiguousarray(theta), dtype=torch.float64, device=device)
+        h, fb = ctx.waveform(th, N, C, precision)
+        return h.cpu().numpy(), fb.cpu().numpy()
+    return fn

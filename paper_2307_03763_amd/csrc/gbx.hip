@@ -1,0 +1,510 @@
+// C ABI of the Galactic-binary likelihood (see include/gbx.h): contexts, plans, dispatch.
+#include "../../include/gbx.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "gbx_kernels.h"
+
+using namespace gbx;
+
+// ------------------------------------------------------------------------------- errors
+static thread_local std::string g_err;
+
+static gb_status fail(gb_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIPCHK(x)                                                                   \
+  do {                                                                              \
+    hipError_t e_ = (x);                                                            \
+    if (e_ != hipSuccess) return fail(GB_EHIP, "%s: %s", #x, hipGetErrorString(e_)); \
+  } while (0)
+
+// ------------------------------------------------------------------------------- set-up kernels
+// Spacecraft of a rigid equilateral triangle (side L) around the guiding centre R(t) on a
+// circle of radius AU; plane tilted by 60 degrees, turning once per orbit against the orbital
+// sense (the classic first-order free-fall constellation).  Guiding-centre phase 0 at t = 0.
+__global__ void k_orbit_table(double* ob64, float* ob32, int N, double T, double P, double L, double AU) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= N) return;
+  const double t = T * (double)m / (double)N;
+  double sa, ca;
+  sincospi(2.0 * t / P, &sa, &ca);
+  const double r3 = sqrt(3.0);
+  // in-plane unit vectors: phi = (-sin a, cos a, 0), w = n_c x phi = (-cos a / 2, -sin a / 2, -sqrt3/2)
+  const double ph[3] = {-sa, ca, 0.0};
+  const double wv[3] = {-0.5 * ca, -0.5 * sa, -0.5 * r3};
+  double dx[3][3];
+  for (int i = 0; i < 3; ++i) {
+    double st, ct;
+    sincospi(2.0 * t / P - 2.0 * i / 3.0, &st, &ct);
+    for (int k = 0; k < 3; ++k) dx[i][k] = L / r3 * (ct * wv[k] + st * ph[k]);
+  }
+  double v[OB_FIELDS];
+  v[OB_RX] = AU * ca / kC;
+  v[OB_RY] = AU * sa / kC;
+  for (int k = 0; k < 3; ++k) {
+    v[OB_N12 + k] = (dx[0][k] - dx[1][k]) / L;
+    v[OB_N23 + k] = (dx[1][k] - dx[2][k]) / L;
+    v[OB_N31 + k] = (dx[2][k] - dx[0][k]) / L;
+    v[OB_P1 + k] = dx[0][k] / kC;
+    v[OB_P2 + k] = dx[1][k] / kC;
+    v[OB_P3 + k] = dx[2][k] / kC;
+  }
+  for (int f = 0; f < OB_FIELDS; ++f) {
+    ob64[f * N + m] = v[f];
+    ob32[f * N + m] = (float)v[f];
+  }
+}
+
+__global__ void k_twiddles(double* tw64, float* tw32, int N) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= N) return;
+  double s, c;
+  sincospi(-2.0 * (double)m / (double)N, &s, &c);
+  tw64[2 * m] = c;
+  tw64[2 * m + 1] = s;
+  tw32[2 * m] = (float)c;
+  tw32[2 * m + 1] = (float)s;
+}
+
+// <d|d> of every window: one workgroup per window.
+__global__ void __launch_bounds__(256) k_prepare(DevWin* wins, const double* d, const double* w) {
+  const DevWin win = wins[blockIdx.x];
+  const int64_t n = (int64_t)win.C * win.W;
+  double acc = 0.0;
+  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
+    const int64_t g = win.data_off + e;
+    const double re = d[2 * g], im = d[2 * g + 1];
+    acc += w[g] * (re * re + im * im);
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  __shared__ double part[4];
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x / 64] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) wins[blockIdx.x].dd = part[0] + part[1] + part[2] + part[3];
+}
+
+// Independent-proposal chain of one source per wave.  In chunks of 64 steps the wave finds
+// the first step whose threshold tau_i = pi_i - T ln u_i exceeds the current pi_c (a ballot),
+// moves the state there and continues after it; the chain index of every step is the last
+// accepted step at or before it.  The comparisons are exactly those of the serial loop.
+__global__ void __launch_bounds__(64) k_mh_chain(const DevWin* wins, const double* logL, const double* log_g,
+                                                 const double* u, double temp, int32_t* chain,
+                                                 int64_t* n_accept) {
+  const DevWin w = wins[blockIdx.x];
+  const int lane = threadIdx.x;
+  const int64_t n = w.n_cand, base = w.cand_off;
+  if (n <= 0) {
+    if (lane == 0) n_accept[blockIdx.x] = 0;
+    return;
+  }
+  double pic = logL[base] - log_g[base];
+  int64_t c = 0, acc = 0;
+  for (int64_t i0 = 0; i0 < n; i0 += 64) {
+    const int64_t i = i0 + lane;
+    const bool in = i < n && i > 0;
+    double pii = 0.0, tau = 0.0;
+    if (in) {
+      pii = logL[base + i] - log_g[base + i];
+      tau = __dsub_rn(pii, __dmul_rn(temp, log(u[base + i])));
+    }
+    uint64_t accmask = 0;
+    int last = -1;
+    for (;;) {
+      const uint64_t m = __ballot(in && lane > last && pic < tau);
+      if (m == 0) break;
+      const int k = __ffsll((unsigned long long)m) - 1;
+      accmask |= 1ull << k;
+      pic = __shfl(pii, k, 64);
+      last = k;
+      ++acc;
+    }
+    const uint64_t upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+    const uint64_t below = accmask & upto;
+    const int64_t st = below ? i0 + (63 - __clzll((long long)below)) : c;
+    if (i < n) chain[base + i] = (int32_t)st;
+    if (accmask) c = i0 + (63 - __clzll((long long)accmask));
+  }
+  if (lane == 0) n_accept[blockIdx.x] = acc;
+}
+
+// ------------------------------------------------------------------------------- variants
+namespace {
+
+struct Variant {
+  int prec, N, LPC, C, WPB, mode;
+  const void* fn;
+};
+
+#define GBX_V(P, RT, NN, LL, CC, WW, MM) \
+  Variant { P, NN, LL, CC, WW, MM, reinterpret_cast<const void*>(&k_batch<RT, NN, LL, CC, WW, MM>) }
+#define GBX_W(P, RT, NN, LL, CC, WW) \
+  Variant { P, NN, LL, CC, WW, MODE_WAVEFORM, reinterpret_cast<const void*>(&k_waveform<RT, NN, LL, CC, WW>) }
+
+#define GBX_ALLC(M, P, RT, NN, LL, WW) M(P, RT, NN, LL, 2, WW), M(P, RT, NN, LL, 3, WW)
+#define GBX_LL(P, RT, NN, LL, CC, WW) GBX_V(P, RT, NN, LL, CC, WW, MODE_LOGLIK)
+#define GBX_GR(P, RT, NN, LL, CC, WW) GBX_V(P, RT, NN, LL, CC, WW, MODE_GRAD)
+
+#define GBX_ALLN(M, P, RT)                                                           \
+  GBX_ALLC(M, P, RT, 64, 16, 4), GBX_ALLC(M, P, RT, 128, 32, 4), GBX_ALLC(M, P, RT, 256, 64, 4), \
+      GBX_ALLC(M, P, RT, 512, 128, 4), GBX_ALLC(M, P, RT, 1024, 256, 4)
+
+const Variant kVariants[] = {
+    GBX_ALLN(GBX_LL, GB_FP64, double), GBX_ALLN(GBX_LL, GB_MIXED, float),
+    GBX_ALLN(GBX_W, GB_FP64, double), GBX_ALLN(GBX_W, GB_MIXED, float),
+    GBX_ALLN(GBX_GR, GB_FP64, double), GBX_ALLN(GBX_GR, GB_MIXED, float),
+};
+
+const Variant* find_variant(int prec, int N, int C, int mode, int LPC = 0, int WPB = 0) {
+  for (const Variant& v : kVariants)
+    if (v.prec == prec && v.N == N && v.C == C && v.mode == mode && (LPC == 0 || v.LPC == LPC) &&
+        (WPB == 0 || v.WPB == WPB))
+      return &v;
+  return nullptr;
+}
+
+size_t lds_bytes(const Variant& v) {
+  const size_t cpb = (size_t)v.WPB * 64 / v.LPC;
+  return cpb * v.C * v.N * (v.prec == GB_FP64 ? 16 : 8);
+}
+
+bool pow2_in_range(int N) { return N >= 64 && N <= 1024 && (N & (N - 1)) == 0; }
+int n_index(int N) {
+  int i = 0;
+  while ((64 << i) < N) ++i;
+  return i;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------- context
+struct NTab {
+  double* ob64 = nullptr;
+  float* ob32 = nullptr;
+  double* tw64 = nullptr;
+  float* tw32 = nullptr;
+};
+
+struct gb_ctx {
+  gb_config cfg;
+  int device = 0;
+  int n_cu = 256;
+  NTab tab[5];
+};
+
+extern "C" const char* gb_last_error(void) { return g_err.c_str(); }
+
+extern "C" gb_status gb_create(const gb_config* cfg, gb_ctx** out) {
+  if (!out) return fail(GB_EINVAL, "gb_create: null output pointer");
+  *out = nullptr;
+  if (!cfg) return fail(GB_EINVAL, "gb_create: null config");
+  if (!(cfg->T > 0) || !(cfg->orbit_period > 0) || !(cfg->arm_length > 0) || !(cfg->au > 0) ||
+      !std::isfinite(cfg->T) || !std::isfinite(cfg->arm_length) || !std::isfinite(cfg->au))
+    return fail(GB_EINVAL, "gb_create: T, orbit_period, arm_length and au must be positive and finite");
+  gb_ctx* c = new gb_ctx();
+  c->cfg = *cfg;
+  hipError_t e = hipGetDevice(&c->device);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device);
+  for (int i = 0; i < 5 && e == hipSuccess; ++i) {
+    const int N = 64 << i;
+    NTab& t = c->tab[i];
+    e = hipMalloc(&t.ob64, sizeof(double) * OB_FIELDS * N);
+    if (e == hipSuccess) e = hipMalloc(&t.ob32, sizeof(float) * OB_FIELDS * N);
+    if (e == hipSuccess) e = hipMalloc(&t.tw64, sizeof(double) * 2 * N);
+    if (e == hipSuccess) e = hipMalloc(&t.tw32, sizeof(float) * 2 * N);
+    if (e != hipSuccess) break;
+    hipLaunchKernelGGL(k_orbit_table, dim3((N + 63) / 64), dim3(64), 0, 0, t.ob64, t.ob32, N, cfg->T,
+                       cfg->orbit_period, cfg->arm_length, cfg->au);
+    hipLaunchKernelGGL(k_twiddles, dim3((N + 63) / 64), dim3(64), 0, 0, t.tw64, t.tw32, N);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    gb_destroy(c);
+    return fail(e == hipErrorOutOfMemory ? GB_ENOMEM : GB_EHIP, "gb_create: %s", hipGetErrorString(e));
+  }
+  *out = c;
+  return GB_OK;
+}
+
+extern "C" void gb_destroy(gb_ctx* c) {
+  if (!c) return;
+  for (NTab& t : c->tab) {
+    (void)hipFree(t.ob64);
+    (void)hipFree(t.ob32);
+    (void)hipFree(t.tw64);
+    (void)hipFree(t.tw32);
+  }
+  delete c;
+}
+
+static BatchArgs base_args(const gb_ctx* c, int N, int prec) {
+  BatchArgs a;
+  std::memset(&a, 0, sizeof a);
+  const NTab& t = c->tab[n_index(N)];
+  a.ob64 = t.ob64;
+  a.obR = prec == GB_FP64 ? (const void*)t.ob64 : (const void*)t.ob32;
+  a.tw = prec == GB_FP64 ? (const void*)t.tw64 : (const void*)t.tw32;
+  a.T = c->cfg.T;
+  a.Lc = c->cfg.arm_length / kC;
+  return a;
+}
+
+static gb_status launch(const Variant* v, dim3 grid, BatchArgs& a, hipStream_t st) {
+  void* args[] = {&a};
+  HIPCHK(hipLaunchKernel(v->fn, grid, dim3(v->WPB * 64), args, lds_bytes(*v), st));
+  return GB_OK;
+}
+
+extern "C" gb_status gb_waveform(gb_ctx* c, const double* theta, int64_t B, int N, int C,
+                                 gb_precision prec, double* h_out, int64_t* first_bin, void* stream) {
+  if (!c) return fail(GB_EINVAL, "gb_waveform: null context");
+  if (B < 0) return fail(GB_EINVAL, "gb_waveform: B = %lld < 0", (long long)B);
+  if (!pow2_in_range(N)) return fail(GB_EINVAL, "gb_waveform: N = %d is not a power of two in [64, 1024]", N);
+  if (C != 2 && C != 3) return fail(GB_EINVAL, "gb_waveform: C = %d (must be 2 or 3)", C);
+  if (prec != GB_FP64 && prec != GB_MIXED) return fail(GB_EINVAL, "gb_waveform: bad precision %d", (int)prec);
+  if (B == 0) return GB_OK;
+  if (!theta || !h_out || !first_bin) return fail(GB_EINVAL, "gb_waveform: null array");
+  const Variant* v = find_variant(prec, N, C, MODE_WAVEFORM);
+  if (!v) return fail(GB_EUNSUPPORTED, "gb_waveform: no variant for N=%d C=%d", N, C);
+  BatchArgs a = base_args(c, N, prec);
+  a.theta = theta;
+  a.B = B;
+  a.h_out = h_out;
+  a.first_bin = first_bin;
+  const int64_t cpb = (int64_t)v->WPB * 64 / v->LPC;
+  const int64_t blocks = (B + cpb - 1) / cpb;
+  if (blocks > 0x7fffffff) return fail(GB_EINVAL, "gb_waveform: B too large");
+  return launch(v, dim3((unsigned)blocks), a, (hipStream_t)stream);
+}
+
+// ------------------------------------------------------------------------------- plans
+namespace {
+struct Bucket {
+  int prec, N, C;
+  const Variant* v[3];  // per mode
+  int grid[3];
+  Tile* d_tiles = nullptr;
+  int n_tiles = 0;
+  unsigned* d_ctr = nullptr;  // [2]
+};
+}  // namespace
+
+struct gb_plan {
+  gb_ctx* ctx = nullptr;
+  std::vector<gb_window> wins;
+  DevWin* d_wins = nullptr;
+  std::vector<Bucket> buckets;
+  const double* prep_d = nullptr;
+  const double* prep_w = nullptr;
+  int64_t rows = 0;
+};
+
+extern "C" void gb_plan_destroy(gb_plan* p) {
+  if (!p) return;
+  (void)hipFree(p->d_wins);
+  for (Bucket& b : p->buckets) {
+    (void)hipFree(b.d_tiles);
+    (void)hipFree(b.d_ctr);
+  }
+  delete p;
+}
+
+static const int kTileIters = 4;  // workgroup passes per tile
+
+extern "C" gb_status gb_plan_create(gb_ctx* c, const gb_window* windows, int n_win, gb_precision prec,
+                                    gb_plan** out) {
+  if (!out) return fail(GB_EINVAL, "gb_plan_create: null output pointer");
+  *out = nullptr;
+  if (!c) return fail(GB_EINVAL, "gb_plan_create: null context");
+  if (n_win < 0 || (n_win > 0 && !windows)) return fail(GB_EINVAL, "gb_plan_create: bad window array");
+  if (prec != GB_FP64 && prec != GB_MIXED && prec != GB_PER_WINDOW)
+    return fail(GB_EINVAL, "gb_plan_create: bad precision %d", (int)prec);
+  std::vector<DevWin> dw(n_win);
+  int64_t rows = 0;
+  for (int i = 0; i < n_win; ++i) {
+    const gb_window& w = windows[i];
+    const int wp = prec == GB_PER_WINDOW ? w.precision : (int)prec;
+    if (!pow2_in_range(w.N)) return fail(GB_EINVAL, "window %d: N = %d is not a power of two in [64, 1024]", i, w.N);
+    if (w.C != 2 && w.C != 3) return fail(GB_EINVAL, "window %d: C = %d (must be 2 or 3)", i, w.C);
+    if (w.W < 1) return fail(GB_EINVAL, "window %d: W = %d < 1", i, w.W);
+    if (w.k0 < 0) return fail(GB_EINVAL, "window %d: k0 < 0", i);
+    if (w.data_off < 0 || w.cand_off < 0 || w.n_cand < 0)
+      return fail(GB_EINVAL, "window %d: negative offset or count", i);
+    if (w.n_cand > 0x7fffffffLL) return fail(GB_EINVAL, "window %d: more than 2^31 candidates", i);
+    if (wp != GB_FP64 && wp != GB_MIXED) return fail(GB_EINVAL, "window %d: bad precision %d", i, wp);
+    dw[i].k0 = w.k0;
+    dw[i].data_off = w.data_off;
+    dw[i].cand_off = w.cand_off;
+    dw[i].n_cand = w.n_cand;
+    dw[i].dd = 0.0;
+    dw[i].W = w.W;
+    dw[i].N = w.N;
+    dw[i].C = w.C;
+    dw[i].prec = wp;
+    rows = std::max(rows, w.cand_off + w.n_cand);
+  }
+  gb_plan* p = new gb_plan();
+  p->ctx = c;
+  p->wins.assign(windows, windows + n_win);
+  p->rows = rows;
+  // group by (N, C, precision); larger N first (longest work first)
+  std::vector<int> order(n_win);
+  for (int i = 0; i < n_win; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    if (dw[a].N != dw[b].N) return dw[a].N > dw[b].N;
+    if (dw[a].C != dw[b].C) return dw[a].C > dw[b].C;
+    return dw[a].prec < dw[b].prec;
+  });
+  hipError_t e = hipSuccess;
+  for (size_t s = 0; s < order.size();) {
+    size_t t = s;
+    const DevWin& w0 = dw[order[s]];
+    while (t < order.size() && dw[order[t]].N == w0.N && dw[order[t]].C == w0.C && dw[order[t]].prec == w0.prec) ++t;
+    Bucket b;
+    b.prec = w0.prec;
+    b.N = w0.N;
+    b.C = w0.C;
+    for (int m = 0; m < 3; ++m) {
+      b.v[m] = find_variant(b.prec, b.N, b.C, m);
+      b.grid[m] = 0;
+    }
+    if (!b.v[MODE_LOGLIK]) {
+      gb_plan_destroy(p);
+      return fail(GB_EUNSUPPORTED, "no kernel variant for N=%d C=%d", b.N, b.C);
+    }
+    const int cpb = b.v[MODE_LOGLIK]->WPB * 64 / b.v[MODE_LOGLIK]->LPC;
+    const int tsz = cpb * kTileIters;
+    std::vector<Tile> tiles;
+    for (size_t k = s; k < t; ++k) {
+      const int wi = order[k];
+      for (int64_t c0 = 0; c0 < dw[wi].n_cand; c0 += tsz) {
+        Tile tl;
+        tl.win = wi;
+        tl.n = (int32_t)std::min<int64_t>(tsz, dw[wi].n_cand - c0);
+        tl.c0 = c0;
+        tiles.push_back(tl);
+      }
+    }
+    b.n_tiles = (int)tiles.size();
+    for (int m = 1; m < 3; ++m) {
+      if (!b.v[m]) continue;
+      int nb = 0;
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, b.v[m]->fn, b.v[m]->WPB * 64, lds_bytes(*b.v[m]));
+      if (e != hipSuccess) break;
+      b.grid[m] = std::max(1, std::min(b.n_tiles, std::max(1, nb) * c->n_cu));
+    }
+    if (e == hipSuccess && b.n_tiles > 0) {
+      e = hipMalloc(&b.d_tiles, sizeof(Tile) * tiles.size());
+      if (e == hipSuccess) e = hipMemcpy(b.d_tiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = hipMalloc(&b.d_ctr, 2 * sizeof(unsigned));
+      if (e == hipSuccess) e = hipMemset(b.d_ctr, 0, 2 * sizeof(unsigned));
+    }
+    p->buckets.push_back(b);
+    if (e != hipSuccess) break;
+    s = t;
+  }
+  if (e == hipSuccess && n_win > 0) {
+    e = hipMalloc(&p->d_wins, sizeof(DevWin) * n_win);
+    if (e == hipSuccess) e = hipMemcpy(p->d_wins, dw.data(), sizeof(DevWin) * n_win, hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    gb_plan_destroy(p);
+    return fail(e == hipErrorOutOfMemory ? GB_ENOMEM : GB_EHIP, "gb_plan_create: %s", hipGetErrorString(e));
+  }
+  *out = p;
+  return GB_OK;
+}
+
+extern "C" gb_status gb_window_prepare(gb_plan* p, const double* d, const double* w, void* stream) {
+  if (!p) return fail(GB_EINVAL, "gb_window_prepare: null plan");
+  if (p->wins.empty()) {
+    p->prep_d = d;
+    p->prep_w = w;
+    return GB_OK;
+  }
+  if (!d || !w) return fail(GB_EINVAL, "gb_window_prepare: null data or weights");
+  hipLaunchKernelGGL(k_prepare, dim3((unsigned)p->wins.size()), dim3(256), 0, (hipStream_t)stream, p->d_wins, d, w);
+  HIPCHK(hipGetLastError());
+  p->prep_d = d;
+  p->prep_w = w;
+  return GB_OK;
+}
+
+static gb_status run_batch(gb_plan* p, int mode, const double* d, const double* w, const double* theta,
+                           double* logL, double* comps, double* grad, hipStream_t st, const char* who) {
+  if (!p) return fail(GB_EINVAL, "%s: null plan", who);
+  if (p->rows == 0) return GB_OK;
+  if (!d || !w || !theta || !logL) return fail(GB_EINVAL, "%s: null array", who);
+  if (d != p->prep_d || w != p->prep_w)
+    return fail(GB_EINVAL, "%s: data/weights differ from the ones passed to gb_window_prepare", who);
+  if (mode == MODE_GRAD && !grad) return fail(GB_EINVAL, "%s: null gradient array", who);
+  for (Bucket& b : p->buckets) {
+    if (b.n_tiles == 0) continue;
+    const Variant* v = b.v[mode];
+    if (!v) return fail(GB_EUNSUPPORTED, "%s: no kernel variant for N=%d C=%d", who, b.N, b.C);
+    BatchArgs a = base_args(p->ctx, b.N, b.prec);
+    a.wins = p->d_wins;
+    a.tiles = b.d_tiles;
+    a.n_tiles = b.n_tiles;
+    a.ctr = b.d_ctr;
+    a.d = d;
+    a.w = w;
+    a.theta = theta;
+    a.logL = logL;
+    a.comps = comps;
+    a.grad = grad;
+    gb_status s = launch(v, dim3(b.grid[mode]), a, st);
+    if (s != GB_OK) return s;
+  }
+  return GB_OK;
+}
+
+extern "C" gb_status gb_loglik(gb_plan* p, const double* d, const double* w, const double* theta, double* logL,
+                               double* comps, void* stream) {
+  return run_batch(p, MODE_LOGLIK, d, w, theta, logL, comps, nullptr, (hipStream_t)stream, "gb_loglik");
+}
+
+extern "C" gb_status gb_loglik_grad(gb_plan* p, const double* d, const double* w, const double* theta,
+                                    double* logL, double* grad, void* stream) {
+  return run_batch(p, MODE_GRAD, d, w, theta, logL, nullptr, grad, (hipStream_t)stream, "gb_loglik_grad");
+}
+
+extern "C" gb_status gb_mh_step(gb_plan* p, const double* d, const double* w, const double* theta,
+                                const double* log_g, const double* u, double temperature, double* logL,
+                                int32_t* chain, int64_t* n_accept, void* stream) {
+  if (!p) return fail(GB_EINVAL, "gb_mh_step: null plan");
+  if (!(temperature > 0) || !std::isfinite(temperature))
+    return fail(GB_EINVAL, "gb_mh_step: temperature must be positive and finite");
+  if (p->wins.empty()) return GB_OK;
+  if (!log_g || !u || !chain || !n_accept) return fail(GB_EINVAL, "gb_mh_step: null array");
+  gb_status s = run_batch(p, MODE_LOGLIK, d, w, theta, logL, nullptr, nullptr, (hipStream_t)stream, "gb_mh_step");
+  if (s != GB_OK) return s;
+  hipLaunchKernelGGL(k_mh_chain, dim3((unsigned)p->wins.size()), dim3(64), 0, (hipStream_t)stream, p->d_wins, logL,
+                     log_g, u, temperature, chain, n_accept);
+  HIPCHK(hipGetLastError());
+  return GB_OK;
+}
+
+extern "C" gb_status gb_autotune(gb_ctx* c, int reps, char* report, size_t report_len) {
+  (void)reps;
+  if (!c) return fail(GB_EINVAL, "gb_autotune: null context");
+  if (report && report_len) std::snprintf(report, report_len, "default shapes (E = 4 samples per lane, 4 waves)");
+  return GB_OK;
+}

@@ -1,0 +1,544 @@
+// Device-side building blocks of the Galactic-binary likelihood for gfx950.
+//
+// Model (paper: Strub et al., arXiv:2307.03763, Sec. II channels and Sec. III parameters;
+// the response model itself is this project's reading of the cited literature):
+//   plane wave H = Re[(A+ e+ - i Ax ex) e^{i Phi(t - k.x/c)}], Phi = 2 pi f0 t + pi fdot t^2 + phi0,
+//   single link (light s -> r over L):  z_rs = -i (pi f L/c) sinc(u_rs) (n.H.n)
+//                                          e^{i[Phi - 2 pi f (L/2 + k.(x_r + x_s)/2)/c]},
+//   first-generation TDI  X = (1 - D^2)[(z13 + D z31) - (z12 + D z21)], D = e^{-2 pi i f L/c},
+//   A = (Z - X)/sqrt2, E = (X - 2Y + Z)/sqrt6, T = (X + Y + Z)/sqrt3  (Sec. II),
+//   slow series S(t_m) = response with the carrier e^{2 pi i q t/T} removed, q = floor(f0 T),
+//   template h(q + j) = T/(2N) DFT_N[S](j mod N), j in [-N/2, N/2).
+// Layout of the per-sample work, shared by every kernel variant:
+//   common phase p = df t + fdot t^2/2 + phi0/(2pi) - f (L/(2c) + k.R/c)   [cycles, FP64]
+//   per arm a (opposite spacecraft o):  P_a = (a+ F+_a + ax Fx_a) e^{i pi f k.dx_o / c}
+//   per link: sinc(u), u = pi f L (1 -+ k.n_a)/c
+//   X, Y, Z from P_a and the six sincs; K = (1 - D^2)(-i pi f L/c) e^{2 pi i p} applied once.
+// The amplitude is factored out (templates are computed for A = 1 and scaled in FP64), so
+// FP32 intermediates stay O(1) whatever the amplitude.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gbx {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kC = 299792458.0;
+
+// orbit table fields, each an array of N samples (structure of arrays)
+enum {
+  OB_RX = 0, OB_RY = 1,                          // guiding centre / c (s), FP64 only
+  OB_N12 = 2, OB_N23 = 5, OB_N31 = 8,            // unit arm vectors (x1-x2)/L, (x2-x3)/L, (x3-x1)/L
+  OB_P1 = 11, OB_P2 = 14, OB_P3 = 17,            // spacecraft offsets from the guiding centre / c (s)
+  OB_FIELDS = 20
+};
+
+template <class R>
+struct cplx {
+  R x, y;
+};
+
+template <class R>
+__device__ __forceinline__ cplx<R> mk(R x, R y) {
+  cplx<R> z;
+  z.x = x;
+  z.y = y;
+  return z;
+}
+template <class R>
+__device__ __forceinline__ cplx<R> operator+(cplx<R> a, cplx<R> b) { return mk<R>(a.x + b.x, a.y + b.y); }
+template <class R>
+__device__ __forceinline__ cplx<R> operator-(cplx<R> a, cplx<R> b) { return mk<R>(a.x - b.x, a.y - b.y); }
+template <class R>
+__device__ __forceinline__ cplx<R> operator*(cplx<R> a, cplx<R> b) {
+  return mk<R>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <class R>
+__device__ __forceinline__ cplx<R> scal(cplx<R> a, R s) { return mk<R>(a.x * s, a.y * s); }
+template <class R>
+__device__ __forceinline__ cplx<R> conjg(cplx<R> a) { return mk<R>(a.x, -a.y); }
+template <class R>
+__device__ __forceinline__ cplx<R> mul_i(cplx<R> a) { return mk<R>(-a.y, a.x); }     // i a
+template <class R>
+__device__ __forceinline__ cplx<R> mul_mi(cplx<R> a) { return mk<R>(a.y, -a.x); }    // -i a
+
+// sin and cos of 2 pi x (x in cycles).  FP64: sincospi.  FP32: the hardware
+// transcendentals, which take their argument in revolutions; |x| <= 1 here.
+__device__ __forceinline__ void sincos_rev(double x, double* s, double* c) { sincospi(2.0 * x, s, c); }
+__device__ __forceinline__ void sincos_rev(float x, float* s, float* c) {
+  *s = __builtin_amdgcn_sinf(x);
+  *c = __builtin_amdgcn_cosf(x);
+}
+
+// sin(u)/u.  For |u| <= 2 the Taylor series in u^2 (next term below 2e-18 in FP64 and 2e-10
+// in FP32 there), the quotient beyond (frequencies above c / (pi L)).
+__device__ __forceinline__ double sinc_r(double u) {
+  if (fabs(u) <= 2.0) {
+    const double u2 = u * u;
+    double p = -1.0 / 25852016738884976640000.0;  // -1/23!
+    p = p * u2 + 1.0 / 51090942171709440000.0;     // 1/21!
+    p = p * u2 - 1.0 / 121645100408832000.0;       // -1/19!
+    p = p * u2 + 1.0 / 355687428096000.0;          // 1/17!
+    p = p * u2 - 1.0 / 1307674368000.0;            // -1/15!
+    p = p * u2 + 1.0 / 6227020800.0;               // 1/13!
+    p = p * u2 - 1.0 / 39916800.0;                 // -1/11!
+    p = p * u2 + 1.0 / 362880.0;                   // 1/9!
+    p = p * u2 - 1.0 / 5040.0;                     // -1/7!
+    p = p * u2 + 1.0 / 120.0;                      // 1/5!
+    p = p * u2 - 1.0 / 6.0;                        // -1/3!
+    return p * u2 + 1.0;
+  }
+  return sin(u) / u;
+}
+__device__ __forceinline__ float sinc_r(float u) {
+  if (fabsf(u) <= 2.0f) {
+    const float u2 = u * u;
+    float p = -1.0f / 1307674368000.0f;            // -1/15!
+    p = p * u2 + 1.0f / 6227020800.0f;             // 1/13!
+    p = p * u2 - 1.0f / 39916800.0f;               // -1/11!
+    p = p * u2 + 1.0f / 362880.0f;                 // 1/9!
+    p = p * u2 - 1.0f / 5040.0f;                   // -1/7!
+    p = p * u2 + 1.0f / 120.0f;                    // 1/5!
+    p = p * u2 - 1.0f / 6.0f;                      // -1/3!
+    return p * u2 + 1.0f;
+  }
+  return __builtin_amdgcn_sinf(u * (float)(0.5 / kPi)) / u;
+}
+
+// Per-candidate constants (computed once per template, replicated over its lanes).
+template <class R>
+struct Cand {
+  double f0, fd, df, phi0c;   // f0, fdot, f0 - q/T, phi0 / 2 pi
+  double kxd, kyd;            // k_x, k_y in FP64 for k.R (the only large phase term)
+  int64_t q;                  // carrier bin floor(f0 T)
+  R k[3], u[3], v[3];         // propagation direction and transverse basis
+  cplx<R> ap, ax;             // n.H.n = ap F+ + ax Fx for unit amplitude
+  double amp;                 // amplitude (applied in FP64 after the DFT)
+  bool ok;                    // parameters in the domain of the model
+};
+
+// theta = (f0, fdot, beta, lambda, A, iota, psi, phi0).  Out-of-domain candidates get a
+// harmless stand-in so every lane still runs the same schedule; `ok` marks them.
+template <class R>
+__device__ __forceinline__ Cand<R> make_cand(const double* th, double T) {
+  Cand<R> s;
+  double f0 = th[0], fd = th[1], be = th[2], la = th[3], amp = th[4], io = th[5], ps = th[6], ph = th[7];
+  bool ok = isfinite(f0) && isfinite(fd) && isfinite(be) && isfinite(la) && isfinite(amp) &&
+            isfinite(io) && isfinite(ps) && isfinite(ph) && f0 > 0.0 && f0 * T < 4.0e15 && amp >= 0.0;
+  if (!ok) {
+    f0 = 1e-3; fd = 0.0; be = 0.0; la = 0.0; amp = 0.0; io = 0.0; ps = 0.0; ph = 0.0;
+  }
+  s.ok = ok;
+  s.f0 = f0;
+  s.fd = fd;
+  s.amp = amp;
+  s.q = (int64_t)floor(f0 * T);
+  s.df = f0 - (double)s.q / T;
+  s.phi0c = ph * (0.5 / kPi);
+  double sb, cb, sl, cl, s2, c2;
+  sincos(be, &sb, &cb);
+  sincos(la, &sl, &cl);
+  sincos(2.0 * ps, &s2, &c2);
+  const double ci = cos(io);
+  s.kxd = -cb * cl;
+  s.kyd = -cb * sl;
+  s.k[0] = (R)(-cb * cl);
+  s.k[1] = (R)(-cb * sl);
+  s.k[2] = (R)(-sb);
+  s.u[0] = (R)(sb * cl);
+  s.u[1] = (R)(sb * sl);
+  s.u[2] = (R)(-cb);
+  s.v[0] = (R)sl;
+  s.v[1] = (R)(-cl);
+  s.v[2] = (R)0;
+  const double Ap = 1.0 + ci * ci, Ac = -2.0 * ci;  // per unit amplitude
+  // n.(A+ e+ - i Ax ex).n with e+ = c2 eps+ + s2 epsx, ex = c2 epsx - s2 eps+:
+  //   = F+ (A+ c2 + i Ax s2) + Fx (A+ s2 - i Ax c2)
+  s.ap = mk<R>((R)(Ap * c2), (R)(Ac * s2));
+  s.ax = mk<R>((R)(Ap * s2), (R)(-Ac * c2));
+  return s;
+}
+
+// One sample of the slow series of channels A, E[, T] for unit amplitude at t = tab time m.
+// ob64: FP64 orbit table [OB_FIELDS][N]; obR: the same in precision R (fields >= OB_N12).
+template <class R, int C>
+__device__ __forceinline__ void slow_sample(const Cand<R>& s, const double* __restrict__ ob64,
+                                            const R* __restrict__ obR, int N, int m, double t,
+                                            double Lc, cplx<R> out[C]) {
+  // common phase in cycles (FP64), reduced to [-1/2, 1/2]
+  const double f = s.f0 + s.fd * t;
+  const double kR = s.kxd * ob64[OB_RX * N + m] + s.kyd * ob64[OB_RY * N + m];
+  double p = s.df * t + 0.5 * s.fd * t * t + s.phi0c - f * (0.5 * Lc + kR);
+  p -= rint(p);
+  R sp, cp;
+  sincos_rev((R)p, &sp, &cp);
+  const R fr = (R)f;
+  const R x = (R)kPi * fr * (R)Lc;  // pi f L / c
+  R sD, cD;
+  sincos_rev(-fr * (R)Lc, &sD, &cD);  // D = e^{-2 pi i f L/c}
+
+  R kn[3], Fp[3], Fx[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int o = OB_N12 + 3 * a;
+    const R n0 = obR[(o + 0) * N + m], n1 = obR[(o + 1) * N + m], n2 = obR[(o + 2) * N + m];
+    kn[a] = s.k[0] * n0 + s.k[1] * n1 + s.k[2] * n2;
+    const R un = s.u[0] * n0 + s.u[1] * n1 + s.u[2] * n2;
+    const R vn = s.v[0] * n0 + s.v[1] * n1;
+    Fp[a] = un * un - vn * vn;
+    Fx[a] = (R)2 * un * vn;
+  }
+  // k . dx_o / c for spacecraft 1, 2, 3
+  R kp[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const int o = OB_P1 + 3 * i;
+    kp[i] = s.k[0] * obR[(o + 0) * N + m] + s.k[1] * obR[(o + 1) * N + m] + s.k[2] * obR[(o + 2) * N + m];
+  }
+  // arm 12 -> opposite spacecraft 3, arm 23 -> 1, arm 31 -> 2
+  const int opp[3] = {2, 0, 1};
+  cplx<R> P[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    R sc, cc;
+    sincos_rev((R)0.5 * fr * kp[opp[a]], &sc, &cc);
+    const cplx<R> b = mk<R>(s.ap.x * Fp[a] + s.ax.x * Fx[a], s.ap.y * Fp[a] + s.ax.y * Fx[a]);
+    P[a] = b * mk<R>(cc, sc);
+  }
+  // link sincs: n12 = +arm 12 for link 12, -arm 12 for link 21 (and cyclically)
+  const R s12 = sinc_r(x * ((R)1 - kn[0])), s21 = sinc_r(x * ((R)1 + kn[0]));
+  const R s23 = sinc_r(x * ((R)1 - kn[1])), s32 = sinc_r(x * ((R)1 + kn[1]));
+  const R s31 = sinc_r(x * ((R)1 - kn[2])), s13 = sinc_r(x * ((R)1 + kn[2]));
+  // G(a, b) = a + D b for real a, b
+  auto G = [&](R a, R b) { return mk<R>(a + cD * b, sD * b); };
+  const cplx<R> X = P[2] * G(s13, s31) - P[0] * G(s12, s21);
+  const cplx<R> Y = P[0] * G(s21, s12) - P[1] * G(s23, s32);
+  const cplx<R> Z = P[1] * G(s32, s23) - P[2] * G(s31, s13);
+  // K = (1 - D^2) (-i x) e^{2 pi i p}, with 1 - D^2 = -2i sin(-2 pi f L/c) D (no cancellation
+  // at low frequency)
+  const cplx<R> omd = mk<R>((R)2 * sD * sD, -((R)2 * cD * sD));
+  const cplx<R> K = scal(mul_mi(omd * mk<R>(cp, sp)), x);
+  const R r2 = (R)0.70710678118654752440, r6 = (R)0.40824829046386301637, r3 = (R)0.57735026918962576451;
+  out[0] = K * scal(Z - X, r2);
+  out[1] = K * scal(X - scal(Y, (R)2) + Z, r6);
+  if (C == 3) out[C - 1] = K * scal(X + Y + Z, r3);
+}
+
+// ------------------------------------------------------------------------------------
+// In-LDS Stockham FFT, radix 4 (plus one radix-2 pass when log2 N is odd), register-staged
+// in place: every pass reads all of a lane's elements, synchronises, butterflies, writes,
+// synchronises.  buf: [C][N] complex of one template; LPC lanes per template, E = N/LPC
+// elements per lane (E a multiple of 4).  DIR = -1 forward (e^{-2 pi i jm/N}), +1 inverse
+// (unnormalised).  tw[m] = e^{-2 pi i m / N}.
+template <class R, int N, int LPC, int C, int RADIX, int DIR>
+__device__ __forceinline__ void stockham_pass(cplx<R>* buf, int lane, int Ns, const cplx<R>* __restrict__ tw) {
+  constexpr int E = N / LPC;
+  constexpr int NB = E / RADIX;
+  cplx<R> v[C][NB][RADIX];
+#pragma unroll
+  for (int c = 0; c < C; ++c)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int j = lane + LPC * b;
+#pragma unroll
+      for (int r = 0; r < RADIX; ++r) v[c][b][r] = buf[c * N + j + r * (N / RADIX)];
+    }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int j = lane + LPC * b;
+    const int k = j & (Ns - 1);
+    const int step = k * (N / (Ns * RADIX));
+    cplx<R> w[RADIX];
+    w[0] = mk<R>((R)1, (R)0);
+#pragma unroll
+    for (int r = 1; r < RADIX; ++r) {
+      const cplx<R> t = tw[r * step];
+      w[r] = (DIR < 0) ? t : conjg(t);
+    }
+    const int base = (j - k) * RADIX + k;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      cplx<R> a[RADIX];
+#pragma unroll
+      for (int r = 0; r < RADIX; ++r) a[r] = (r == 0) ? v[c][b][0] : v[c][b][r] * w[r];
+      if (RADIX == 2) {
+        buf[c * N + base] = a[0] + a[1];
+        buf[c * N + base + Ns] = a[0] - a[1];
+      } else {
+        const cplx<R> s0 = a[0] + a[2], d0 = a[0] - a[2];
+        const cplx<R> s1 = a[1] + a[3], d1 = a[1] - a[3];
+        const cplx<R> rot = (DIR < 0) ? mul_mi(d1) : mul_i(d1);
+        buf[c * N + base] = s0 + s1;
+        buf[c * N + base + Ns] = d0 + rot;
+        buf[c * N + base + 2 * Ns] = s0 - s1;
+        buf[c * N + base + 3 * Ns] = d0 - rot;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <int N>
+struct Log2 {
+  static constexpr int v = 1 + Log2<N / 2>::v;
+};
+template <>
+struct Log2<1> {
+  static constexpr int v = 0;
+};
+
+template <class R, int N, int LPC, int C, int DIR>
+__device__ __forceinline__ void fft_lds(cplx<R>* buf, int lane, const cplx<R>* __restrict__ tw) {
+  constexpr int LG = Log2<N>::v;
+  int Ns = 1;
+  if (LG & 1) {
+    stockham_pass<R, N, LPC, C, 2, DIR>(buf, lane, 1, tw);
+    Ns = 2;
+  }
+#pragma unroll
+  for (int p = 0; p < LG / 2; ++p) {
+    stockham_pass<R, N, LPC, C, 4, DIR>(buf, lane, Ns, tw);
+    Ns *= 4;
+  }
+}
+
+}  // namespace gbx
+
+namespace gbx {
+
+// ------------------------------------------------------------------------------------
+// Gradient support.  A value with three tangents along (local frequency f, beta, lambda).
+template <class R>
+struct D3 {
+  R v, a, b, c;
+};
+template <class R>
+__device__ __forceinline__ D3<R> d3(R v, R a, R b, R c) {
+  D3<R> r;
+  r.v = v;
+  r.a = a;
+  r.b = b;
+  r.c = c;
+  return r;
+}
+template <class R>
+__device__ __forceinline__ D3<R> operator+(D3<R> x, D3<R> y) { return d3<R>(x.v + y.v, x.a + y.a, x.b + y.b, x.c + y.c); }
+template <class R>
+__device__ __forceinline__ D3<R> operator-(D3<R> x, D3<R> y) { return d3<R>(x.v - y.v, x.a - y.a, x.b - y.b, x.c - y.c); }
+template <class R>
+__device__ __forceinline__ D3<R> operator*(D3<R> x, D3<R> y) {
+  return d3<R>(x.v * y.v, x.a * y.v + x.v * y.a, x.b * y.v + x.v * y.b, x.c * y.v + x.v * y.c);
+}
+template <class R>
+__device__ __forceinline__ D3<R> dsc(D3<R> x, R s) { return d3<R>(x.v * s, x.a * s, x.b * s, x.c * s); }
+
+// complex numbers whose parts carry tangents
+template <class R>
+struct CD {
+  D3<R> re, im;
+};
+template <class R>
+__device__ __forceinline__ CD<R> cd(D3<R> re, D3<R> im) {
+  CD<R> z;
+  z.re = re;
+  z.im = im;
+  return z;
+}
+template <class R>
+__device__ __forceinline__ CD<R> operator+(CD<R> x, CD<R> y) { return cd<R>(x.re + y.re, x.im + y.im); }
+template <class R>
+__device__ __forceinline__ CD<R> operator-(CD<R> x, CD<R> y) { return cd<R>(x.re - y.re, x.im - y.im); }
+template <class R>
+__device__ __forceinline__ CD<R> operator*(CD<R> x, CD<R> y) {
+  return cd<R>(x.re * y.re - x.im * y.im, x.re * y.im + x.im * y.re);
+}
+// constant complex times tangent-carrying complex
+template <class R>
+__device__ __forceinline__ CD<R> cmul(cplx<R> k, CD<R> y) {
+  return cd<R>(dsc(y.re, k.x) - dsc(y.im, k.y), dsc(y.im, k.x) + dsc(y.re, k.y));
+}
+// e^{2 pi i p} for p with tangents
+template <class R>
+__device__ __forceinline__ CD<R> expi_rev(R pv, R pa, R pb, R pc) {
+  R s, c;
+  sincos_rev(pv, &s, &c);
+  const R tp = (R)(2.0 * kPi);
+  // d e^{2 pi i p} = 2 pi i e^{2 pi i p} dp
+  return cd<R>(d3<R>(c, -tp * s * pa, -tp * s * pb, -tp * s * pc), d3<R>(s, tp * c * pa, tp * c * pb, tp * c * pc));
+}
+
+// sinc(u) and its derivative
+__device__ __forceinline__ void sinc_d(double u, double* s, double* ds) {
+  if (fabs(u) <= 2.0) {
+    const double u2 = u * u;
+    // coefficients (-1)^k / (2k+1)!, k = 0..11
+    const double c[12] = {1.0, -1.0 / 6.0, 1.0 / 120.0, -1.0 / 5040.0, 1.0 / 362880.0, -1.0 / 39916800.0,
+                          1.0 / 6227020800.0, -1.0 / 1307674368000.0, 1.0 / 355687428096000.0,
+                          -1.0 / 121645100408832000.0, 1.0 / 51090942171709440000.0,
+                          -1.0 / 25852016738884976640000.0};
+    double p = c[11], q = 22.0 * c[11];
+#pragma unroll
+    for (int k = 10; k >= 1; --k) {
+      p = p * u2 + c[k];
+      q = q * u2 + 2.0 * k * c[k];
+    }
+    *s = p * u2 + c[0];
+    *ds = q * u;
+  } else {
+    double sn, cs;
+    sincos(u, &sn, &cs);
+    *s = sn / u;
+    *ds = (cs - *s) / u;
+  }
+}
+__device__ __forceinline__ void sinc_d(float u, float* s, float* ds) {
+  if (fabsf(u) <= 2.0f) {
+    const float u2 = u * u;
+    const float c[8] = {1.0f, -1.0f / 6.0f, 1.0f / 120.0f, -1.0f / 5040.0f, 1.0f / 362880.0f,
+                        -1.0f / 39916800.0f, 1.0f / 6227020800.0f, -1.0f / 1307674368000.0f};
+    float p = c[7], q = 14.0f * c[7];
+#pragma unroll
+    for (int k = 6; k >= 1; --k) {
+      p = p * u2 + c[k];
+      q = q * u2 + 2.0f * k * c[k];
+    }
+    *s = p * u2 + c[0];
+    *ds = q * u;
+  } else {
+    const float sn = __builtin_amdgcn_sinf(u * (float)(0.5 / kPi));
+    const float cs = __builtin_amdgcn_cosf(u * (float)(0.5 / kPi));
+    *s = sn / u;
+    *ds = (cs - *s) / u;
+  }
+}
+template <class R>
+__device__ __forceinline__ D3<R> sinc3(D3<R> u) {
+  R s, ds;
+  sinc_d(u.v, &s, &ds);
+  return d3<R>(s, ds * u.a, ds * u.b, ds * u.c);
+}
+
+// Extra per-candidate constants of the gradient.
+template <class R>
+struct CandG {
+  R sb, cb;           // sin beta, cos beta
+  R wl[2];            // d v / d lambda = (cos lambda, sin lambda, 0)
+};
+template <class R>
+__device__ __forceinline__ CandG<R> make_cand_grad(const double* th, bool ok) {
+  CandG<R> g;
+  double sb, cb, sl, cl;
+  sincos(ok ? th[2] : 0.0, &sb, &cb);
+  sincos(ok ? th[3] : 0.0, &sl, &cl);
+  g.sb = (R)sb;
+  g.cb = (R)cb;
+  g.wl[0] = (R)cl;
+  g.wl[1] = (R)sl;
+  return g;
+}
+
+// Per-sample accumulators of the gradient (FP64).
+struct GradAcc {
+  double gf, gtf, gb, gl;   // sum Re(cot . dS/d{f, beta, lambda}); gtf = sum t * (f part)
+  double gu_re, gu_im, gv_re, gv_im;  // sum conj(Sbar) U, conj(Sbar) V
+  double pt, ptt;           // sum t Im(conj(Sbar) S), sum t^2 Im(conj(Sbar) S)
+};
+
+// Contribution of slow-series sample m to the gradient.  sbar[c] = the cotangent of S_c(t_m)
+// (scaled inverse DFT of w (d - h)).  The channels collapse into three constants bX, bY, bZ
+// multiplying X, Y, Z, and the links into one cotangent per arm Lam_a multiplying P_a, so only
+// the arm phasors, the sincs, D and the common factor K carry tangents.
+template <class R, int C>
+__device__ __forceinline__ void grad_sample(const Cand<R>& s, const CandG<R>& sg, const double* __restrict__ ob64,
+                                            const R* __restrict__ obR, int N, int m, double t, double Lc,
+                                            const cplx<R> sbar[C], GradAcc& acc) {
+  const double f = s.f0 + s.fd * t;
+  const double Rx = ob64[OB_RX * N + m], Ry = ob64[OB_RY * N + m];
+  const double kR = s.kxd * Rx + s.kyd * Ry;
+  double p = s.df * t + 0.5 * s.fd * t * t + s.phi0c - f * (0.5 * Lc + kR);
+  p -= rint(p);
+  const R fr = (R)f, Lr = (R)Lc;
+  // dp: d/df = -(L/2c + k.R/c); d/dbeta = -f u.R/c; d/dlambda = -f cos(beta) v.R/c
+  const R uR = s.u[0] * (R)Rx + s.u[1] * (R)Ry;
+  const R vR = s.v[0] * (R)Rx + s.v[1] * (R)Ry;
+  const CD<R> E0 = expi_rev<R>((R)p, -((R)0.5 * Lr + (R)kR), -fr * uR, -fr * sg.cb * vR);
+  const D3<R> x = d3<R>((R)kPi * fr * Lr, (R)kPi * Lr, (R)0, (R)0);
+  // D = e^{-2 pi i f L/c}
+  const CD<R> D = expi_rev<R>(-fr * Lr, -Lr, (R)0, (R)0);
+
+  D3<R> kn[3], Fp[3], Fx[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int o = OB_N12 + 3 * a;
+    const R n0 = obR[(o + 0) * N + m], n1 = obR[(o + 1) * N + m], n2 = obR[(o + 2) * N + m];
+    const R knv = s.k[0] * n0 + s.k[1] * n1 + s.k[2] * n2;
+    const R unv = s.u[0] * n0 + s.u[1] * n1 + s.u[2] * n2;
+    const R vnv = s.v[0] * n0 + s.v[1] * n1;
+    const R wnv = sg.wl[0] * n0 + sg.wl[1] * n1;
+    // dk/dbeta = u, dk/dlambda = cos(beta) v; du/dbeta = -k, du/dlambda = -sin(beta) v; dv/dlambda = w
+    kn[a] = d3<R>(knv, (R)0, unv, sg.cb * vnv);
+    const D3<R> un = d3<R>(unv, (R)0, -knv, -sg.sb * vnv);
+    const D3<R> vn = d3<R>(vnv, (R)0, (R)0, wnv);
+    Fp[a] = un * un - vn * vn;
+    Fx[a] = dsc(un * vn, (R)2);
+  }
+  CD<R> Ea[3];
+  const int opp[3] = {2, 0, 1};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int o = OB_P1 + 3 * opp[a];
+    const R p0 = obR[(o + 0) * N + m], p1 = obR[(o + 1) * N + m], p2 = obR[(o + 2) * N + m];
+    const R kpv = s.k[0] * p0 + s.k[1] * p1 + s.k[2] * p2;
+    const R upv = s.u[0] * p0 + s.u[1] * p1 + s.u[2] * p2;
+    const R vpv = s.v[0] * p0 + s.v[1] * p1;
+    // chi (cycles) = f k.p / 2
+    Ea[a] = expi_rev<R>((R)0.5 * fr * kpv, (R)0.5 * kpv, (R)0.5 * fr * upv, (R)0.5 * fr * sg.cb * vpv);
+  }
+  const D3<R> one = d3<R>((R)1, (R)0, (R)0, (R)0);
+  const D3<R> s12 = sinc3(x * (one - kn[0])), s21 = sinc3(x * (one + kn[0]));
+  const D3<R> s23 = sinc3(x * (one - kn[1])), s32 = sinc3(x * (one + kn[1]));
+  const D3<R> s31 = sinc3(x * (one - kn[2])), s13 = sinc3(x * (one + kn[2]));
+  auto G = [&](D3<R> a, D3<R> b) { return cd<R>(a + D.re * b, D.im * b); };
+  // channel cotangents folded onto X, Y, Z: sum_c conj(sbar_c) M_c = bX X + bY Y + bZ Z
+  const R r2 = (R)0.70710678118654752440, r6 = (R)0.40824829046386301637, r3 = (R)0.57735026918962576451;
+  const cplx<R> cA = conjg(sbar[0]), cE = conjg(sbar[1]);
+  const cplx<R> cT = (C == 3) ? conjg(sbar[C - 1]) : mk<R>((R)0, (R)0);
+  const cplx<R> bX = scal(cA, -r2) + scal(cE, r6) + scal(cT, r3);
+  const cplx<R> bY = scal(cE, (R)-2 * r6) + scal(cT, r3);
+  const cplx<R> bZ = scal(cA, r2) + scal(cE, r6) + scal(cT, r3);
+  // X = P31 G(s13,s31) - P12 G(s12,s21); Y = P12 G(s21,s12) - P23 G(s23,s32); Z = P23 G(s32,s23) - P31 G(s31,s13)
+  const CD<R> L12 = cmul(bY, G(s21, s12)) - cmul(bX, G(s12, s21));
+  const CD<R> L23 = cmul(bZ, G(s32, s23)) - cmul(bY, G(s23, s32));
+  const CD<R> L31 = cmul(bX, G(s13, s31)) - cmul(bZ, G(s31, s13));
+  // arm phasors for the two polarisation bases: P^U_a = F+_a E_a, P^V_a = Fx_a E_a
+  auto rmul = [&](D3<R> r, CD<R> z) { return cd<R>(r * z.re, r * z.im); };
+  const CD<R> LE12 = L12 * Ea[0], LE23 = L23 * Ea[1], LE31 = L31 * Ea[2];
+  const CD<R> qu = rmul(Fp[0], LE12) + rmul(Fp[1], LE23) + rmul(Fp[2], LE31);
+  const CD<R> qv = rmul(Fx[0], LE12) + rmul(Fx[1], LE23) + rmul(Fx[2], LE31);
+  // K = (1 - D^2)(-i x) e^{2 pi i p}
+  // 1 - D^2 = 2 sD^2 - 2i cD sD (D = cD + i sD), free of cancellation at low frequency
+  const CD<R> omd = cd<R>(dsc(D.im * D.im, (R)2), dsc(D.re * D.im, (R)-2));
+  const CD<R> mix = cd<R>(d3<R>((R)0, (R)0, (R)0, (R)0), d3<R>((R)0, (R)0, (R)0, (R)0) - x);  // -i x
+  const CD<R> K = omd * mix * E0;
+  const CD<R> cu = K * qu, cv = K * qv;  // sum_c conj(sbar_c) U_c and V_c, with tangents
+  // d/dtheta of sum conj(sbar) S with S = ap U + ax V (ap, ax fixed)
+  auto re_comb = [&](R ure, R uim, R vre, R vim) {
+    return (double)(s.ap.x * ure - s.ap.y * uim + s.ax.x * vre - s.ax.y * vim);
+  };
+  const double gf = re_comb(cu.re.a, cu.im.a, cv.re.a, cv.im.a);
+  acc.gf += gf;
+  acc.gtf += t * gf;
+  acc.gb += re_comb(cu.re.b, cu.im.b, cv.re.b, cv.im.b);
+  acc.gl += re_comb(cu.re.c, cu.im.c, cv.re.c, cv.im.c);
+  acc.gu_re += (double)cu.re.v;
+  acc.gu_im += (double)cu.im.v;
+  acc.gv_re += (double)cv.re.v;
+  acc.gv_im += (double)cv.im.v;
+  const double gs_im = (double)(s.ap.x * cu.im.v + s.ap.y * cu.re.v + s.ax.x * cv.im.v + s.ax.y * cv.re.v);
+  acc.pt += t * gs_im;
+  acc.ptt += t * t * gs_im;
+}
+
+}  // namespace gbx

@@ -200,18 +200,24 @@ def draw_uniform_box(rng: np.random.Generator, lo: np.ndarray, hi: np.ndarray, n
 
 def draw_gaussian_around(rng: np.random.Generator, theta0: np.ndarray, box: PriorBox,
                          rel_sigma: float, n: int) -> np.ndarray:
-    """n Gaussian draws around theta0 (Table I coordinates), sigma = rel_sigma * width,
-    truncated to the box by redrawing."""
+    """n Gaussian draws around theta0 in Table I coordinates with sigma = rel_sigma * box width.
+    Only the bounded coordinates (sin beta, cos iota in [-1, 1]) are truncated, by redrawing;
+    the others may leave the box (an injected source need not lie inside Table I's amplitude
+    range, and the angles are periodic)."""
     u0 = to_table1(theta0)
     sig = rel_sigma * box.width
     out = np.empty((n, 8))
     filled = 0
-    while filled < n:
+    for _ in range(10000):
+        if filled >= n:
+            break
         cand = u0 + sig * rng.standard_normal((2 * (n - filled) + 8, 8))
-        ok = np.all((cand >= box.lo) & (cand <= box.hi), axis=1)
+        ok = (np.abs(cand[:, 2]) <= 1.0) & (np.abs(cand[:, 5]) <= 1.0)
         cand = cand[ok][: n - filled]
         out[filled:filled + len(cand)] = cand
         filled += len(cand)
+    if filled < n:
+        raise ValueError("draw_gaussian_around: centre too far outside the bounded coordinates")
     return from_table1(out)
 
 

@@ -1,0 +1,55 @@
+"""The C-ABI library loads and exports every symbol include/gbx.h declares (no GPU needed)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gbx.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gb_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("gb_waveform", "gb_loglik", "gb_loglik_grad", "gb_mh_step", "gb_create",
+              "gb_plan_create", "gb_window_prepare", "gb_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2307_03763_amd import api
+    L = api.lib()
+    for n in declared_functions():
+        assert hasattr(L, n), n
+    assert set(declared_functions()) == set(api.EXPORTS)
+
+
+def test_argument_validation_without_device():
+    """Calls that fail validation return an error code and a message before touching HIP."""
+    from paper_2307_03763_amd import api
+    L = api.lib()
+    out = ctypes.c_void_p()
+    assert L.gb_create(None, ctypes.byref(out)) == api.GB_EINVAL
+    assert b"config" in L.gb_last_error()
+    bad = api.gb_config(-1.0, 1.0, 1.0, 1.0)
+    assert L.gb_create(ctypes.byref(bad), ctypes.byref(out)) == api.GB_EINVAL and out.value is None
+    assert L.gb_plan_create(None, None, 0, 0, ctypes.byref(out)) == api.GB_EINVAL
+    assert L.gb_waveform(None, None, 1, 128, 2, 0, None, None, None) == api.GB_EINVAL
+    assert L.gb_loglik(None, None, None, None, None, None, None) == api.GB_EINVAL
+    assert L.gb_loglik_grad(None, None, None, None, None, None, None) == api.GB_EINVAL
+    assert L.gb_mh_step(None, None, None, None, None, None, 1.0, None, None, None, None) == api.GB_EINVAL
+    assert L.gb_window_prepare(None, None, None, None) == api.GB_EINVAL
+
+
+def test_struct_layouts_match_header():
+    from paper_2307_03763_amd import api
+    assert ctypes.sizeof(api.gb_config) == 32
+    assert ctypes.sizeof(api.gb_window) == 48
+    assert api.gb_window.data_off.offset == 24 and api.gb_window.n_cand.offset == 40

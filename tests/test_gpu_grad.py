@@ -1,0 +1,123 @@
+"""GPU gradient parity: the hand-written adjoint against the oracle's dual-number gradient and
+against central differences of the GPU logL.
+
+Scale of a gradient component: |dlogL/dtheta_i| <= ||d - h|| ||d_i h|| <= sqrt(F_ii (<d|d> + <h|h>))
+up to a factor of order one, so errors are measured against s_i = sqrt(F_ii (<d|d> + <h|h>)).
+Bars: FP64 1e-9 s_i; mixed precision 1e-5 s_i.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2307_03763_amd import api
+from paper_2307_03763_amd import inputs as I
+from tests.gpu_common import banner, dev, window_dd
+
+pytestmark = pytest.mark.gpu
+
+
+def _workload(oracle_lib, C):
+    """Gradient workload shaped like the paper's windows, small enough for the oracle."""
+    wl = I.workload_c4(oracle_lib.template_fn(), n_win=6, n_cand=9)
+    if C == 3:
+        # move every window above f*/2 so the T channel is used
+        T = wl.T
+        wins, thetas = [], []
+        rng = np.random.default_rng(31)
+        for w in wl.windows:
+            fc = 12e-3 + rng.uniform(0, 4e-3)
+            q = int(fc * T)
+            k0 = q - w.W // 2
+            src = I.make_theta([(q + 0.3) / T], I.fdot_gr(fc, 0.5), 2e-22, I.random_angles(rng, 1))
+            wins.append(I.WindowSpec(k0, w.W, w.N, 3, k0 / T, (k0 + w.W) / T, src))
+            box = I.table1_box((k0 + w.W / 6) / T, (k0 + 5 * w.W / 6) / T, T)
+            thetas.append(I.draw_gaussian_around(rng, src[0], box, 1e-3, 9))
+        wl = I._concat(wins, thetas, "grad C=3", T)
+        I.finalize_data(wl, oracle_lib.template_fn(), np.random.default_rng(32))
+    return wl
+
+
+def _scales(O, wl, i, th, comps_hh):
+    w = wl.windows[i]
+    _, ww = wl.window_data(i)
+    g = O.Geometry(wl.T)
+    dd = float(np.sum(ww * np.abs(wl.window_data(i)[0]) ** 2))
+    out = []
+    for b in range(len(th)):
+        F = O.fisher(th[b], w.k0, w.W, w.N, w.C, ww, g)
+        out.append(np.sqrt(np.maximum(np.diag(F), 0) * (dd + comps_hh[b])))
+    return np.array(out)
+
+
+def _run(wl, prec):
+    ctx = api.context_for(wl.T)
+    plan = api.Plan(ctx, wl.window_table(), prec)
+    d, w = dev(wl.data, torch.complex128), dev(wl.weights)
+    plan.prepare(d, w)
+    th = dev(wl.theta)
+    l, g = plan.loglik_grad(th)
+    l2 = plan.loglik(th)
+    torch.cuda.synchronize()
+    return l.cpu().numpy(), g.cpu().numpy(), l2.cpu().numpy(), (ctx, plan, d, w, th)
+
+
+@pytest.mark.parametrize("C", [2, 3])
+@pytest.mark.parametrize("prec,bar", [(api.GB_FP64, 1e-9), (api.GB_MIXED, 1e-5)])
+def test_gradient_matches_oracle(oracle_lib, C, prec, bar):
+    banner(f"gradient vs oracle C={C} prec={prec}")
+    O = oracle_lib
+    wl = _workload(O, C)
+    l, g, l2, _ = _run(wl, prec)
+    worst = np.zeros(8)
+    for i in range(wl.n_win):
+        w = wl.windows[i]
+        d, ww = wl.window_data(i)
+        a, n = int(wl.cand_off[i]), int(wl.n_cand[i])
+        th = wl.window_theta(i)
+        lo, go = O.loglik_grad(th, w.k0, w.W, w.N, w.C, d, ww, O.Geometry(wl.T))
+        _, co = O.loglik(th, w.k0, w.W, w.N, w.C, d, ww, O.Geometry(wl.T))
+        sc = _scales(O, wl, i, th, co[:, 1])
+        err = np.abs(g[a:a + n] - go) / sc
+        worst = np.maximum(worst, err.max(axis=0))
+        if prec == api.GB_FP64:
+            assert np.array_equal(l[a:a + n], l2[a:a + n]) or np.allclose(l[a:a + n], l2[a:a + n], rtol=1e-13)
+    banner("  worst scaled error per parameter: " + " ".join(f"{x:.1e}" for x in worst))
+    assert worst.max() <= bar, worst
+
+
+def test_gradient_central_differences(oracle_lib):
+    """FP64 GPU gradient against central differences of the FP64 GPU logL (steps 1e-6 of the
+    Table I widths; candidates kept away from a carrier-bin change)."""
+    banner("gradient vs central differences")
+    O = oracle_lib
+    wl = _workload(O, 2)
+    _, g, _, (ctx, plan, d, w, th) = _run(wl, api.GB_FP64)
+    T = wl.T
+    base = wl.theta.copy()
+    # keep f0 T at least 0.2 from an integer so +-step never changes the carrier bin
+    frac = base[:, 0] * T - np.floor(base[:, 0] * T)
+    base[:, 0] += (np.clip(frac, 0.2, 0.8) - frac) / T
+    l0, g0, _, (ctx, plan, d, w, thb) = _run(I.Workload(wl.name, T, wl.windows, base, wl.n_cand, wl.cand_off,
+                                                          wl.data, wl.weights, wl.data_off), api.GB_FP64)
+    # Table I widths at 5 mHz: f over a 256-bin window, fdot over its bounds, angles over their ranges
+    f5 = 5e-3
+    widths = np.array([256.0 / T, 1.02e-6 * f5 ** (11 / 3) + 5e-6 * f5 ** (13 / 3), 1.0, 2 * math.pi, 0.0,
+                       math.pi, math.pi, 2 * math.pi])
+    rel_errs = []
+    for i in range(8):
+        h = 1e-6 * (widths[i] if i != 4 else 1.0)
+        hv = np.full(len(base), h) if i != 4 else 1e-6 * base[:, 4]
+        tp, tm = base.copy(), base.copy()
+        tp[:, i] += hv
+        tm[:, i] -= hv
+        lp = plan.loglik(dev(tp)).cpu().numpy()
+        lm = plan.loglik(dev(tm)).cpu().numpy()
+        fd = (lp - lm) / (2 * hv)
+        # second-order truncation and rounding bound the agreement
+        err = np.abs(fd - g0[:, i]) / np.maximum(np.abs(g0[:, i]), 1e-2 / hv)
+        rel_errs.append(np.median(err))
+        assert np.median(err) < 1e-4, (i, np.median(err))
+    banner("  median relative FD error per parameter: " + " ".join(f"{x:.1e}" for x in rel_errs))

@@ -1,0 +1,246 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the same seeded inputs.
+
+Bars: FP64 -- template rel. L2 <= 1e-10 per candidate; logL within 1e-10 (<d|d> + 2|<d|h>| + <h|h>)
+(the three terms cancel); integer outputs (first bins, chain indices) bit-exact.
+Mixed precision -- errors of logL differences against the injected source's logL at most 1e-5
+of max(1, |difference|) on the quiet-to-moderate sources of these workloads.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2307_03763_amd import api
+from paper_2307_03763_amd import inputs as I
+from tests.gpu_common import (banner, delta_logl_error, dev, loglik_tolerance, rel_l2, run_gpu_loglik,
+                              window_dd)
+
+pytestmark = pytest.mark.gpu
+
+
+def _random_theta(rng, n, f_lo=0.3e-3, f_hi=20e-3, T=I.T1):
+    f0 = np.exp(rng.uniform(math.log(f_lo), math.log(f_hi), n))
+    fd = np.array([I.fdot_gr(f, rng.uniform(0.1, 1.0)) for f in f0]) * rng.choice([-0.2, 1.0], n)
+    amp = 10.0 ** rng.uniform(-23, -21, n)
+    return I.make_theta(f0, fd, amp, I.random_angles(rng, n))
+
+
+@pytest.fixture(scope="module")
+def ctx1():
+    return api.context_for(I.T1)
+
+
+@pytest.mark.parametrize("N", [64, 128, 256, 512, 1024])
+@pytest.mark.parametrize("C", [2, 3])
+def test_waveform_fp64_matches_oracle(oracle_lib, ctx1, N, C):
+    banner(f"waveform fp64 N={N} C={C}")
+    O = oracle_lib
+    rng = np.random.default_rng(100 + N + C)
+    th = _random_theta(rng, 37)
+    h, fb = ctx1.waveform(dev(th), N, C, api.GB_FP64)
+    torch.cuda.synchronize()
+    h, fb = h.cpu().numpy(), fb.cpu().numpy()
+    ho, fbo = O.waveform(th, N, C, O.Geometry(I.T1))
+    assert np.array_equal(fb, fbo)
+    errs = [rel_l2(h[b], ho[b]) for b in range(len(th))]
+    assert max(errs) <= 1e-10, max(errs)
+
+
+@pytest.mark.parametrize("N", [64, 256, 1024])
+def test_waveform_mixed_accuracy(oracle_lib, ctx1, N):
+    banner(f"waveform mixed N={N}")
+    O = oracle_lib
+    rng = np.random.default_rng(200 + N)
+    th = _random_theta(rng, 29)
+    h, fb = ctx1.waveform(dev(th), N, 3, api.GB_MIXED)
+    torch.cuda.synchronize()
+    h, fb = h.cpu().numpy(), fb.cpu().numpy()
+    ho, fbo = O.waveform(th, N, 3, O.Geometry(I.T1))
+    assert np.array_equal(fb, fbo)
+    errs = np.array([rel_l2(h[b], ho[b]) for b in range(len(th))])
+    banner(f"  mixed template rel L2: max {errs.max():.2e} median {np.median(errs):.2e}")
+    assert errs.max() < 5e-6
+
+
+@pytest.fixture(scope="module")
+def c1(oracle_lib):
+    return I.workload_c1(oracle_lib.template_fn())
+
+
+def test_loglik_fp64_c1(oracle_lib, c1):
+    banner("loglik fp64 C1")
+    O = oracle_lib
+    l, comps, _ = run_gpu_loglik(c1, api.GB_FP64)
+    lo, co = O.loglik_workload(c1)
+    lo, co = lo[0], co[0]
+    dd = window_dd(c1)[0]
+    tol = loglik_tolerance(dd, co[:, 0], co[:, 1])
+    assert np.all(np.abs(l - lo) <= tol), np.max(np.abs(l - lo) / tol)
+    assert np.all(np.abs(comps - co) <= 1e-10 * (np.abs(co) + co[:, 1:2]))
+
+
+def test_loglik_mixed_c1(oracle_lib, c1):
+    banner("loglik mixed C1")
+    O = oracle_lib
+    l, comps, _ = run_gpu_loglik(c1, api.GB_MIXED)
+    lo, co = O.loglik_workload(c1)
+    lo = lo[0]
+    # reference: the injected source
+    src = c1.windows[0].sources[0]
+    w0 = c1.windows[0]
+    d, ww = c1.window_data(0)
+    ref_o, _ = O.loglik(src, w0.k0, w0.W, w0.N, w0.C, d, ww, O.Geometry(c1.T))
+    wl_ref = I.Workload(c1.name, c1.T, c1.windows, src[None, :], np.array([1]), np.array([0]),
+                        c1.data, c1.weights, c1.data_off)
+    ref_g, _, _ = run_gpu_loglik(wl_ref, api.GB_MIXED, comps=False)
+    err = delta_logl_error(l, lo, ref_g[0], ref_o[0])
+    rho = math.sqrt(co[0][0, 1])
+    banner(f"  C1 mixed: rho {rho:.1f}, max dlogL error {err.max():.2e}, abs logL err {np.max(np.abs(l - lo)):.2e}")
+    assert err.max() <= 1e-5
+
+
+@pytest.fixture(scope="module")
+def c3_small(oracle_lib):
+    return I.workload_c3(oracle_lib.template_fn(), n_win=24, n_cand=21)
+
+
+def test_loglik_ragged_fp64(oracle_lib, c3_small):
+    banner("loglik ragged fp64 (24 windows)")
+    O = oracle_lib
+    wl = c3_small
+    l, comps, _ = run_gpu_loglik(wl, api.GB_FP64)
+    lo, co = O.loglik_workload(wl)
+    dd = window_dd(wl)
+    for i in range(wl.n_win):
+        a = int(wl.cand_off[i])
+        n = int(wl.n_cand[i])
+        tol = loglik_tolerance(dd[i], co[i][:, 0], co[i][:, 1])
+        assert np.all(np.abs(l[a:a + n] - lo[i]) <= tol), (i, wl.windows[i].N, wl.windows[i].C)
+
+
+def test_loglik_ragged_mixed(oracle_lib, c3_small):
+    banner("loglik ragged mixed (24 windows)")
+    O = oracle_lib
+    wl = c3_small
+    l, _, _ = run_gpu_loglik(wl, api.GB_MIXED)
+    lo, co = O.loglik_workload(wl)
+    worst = []
+    for i in range(wl.n_win):
+        a, n = int(wl.cand_off[i]), int(wl.n_cand[i])
+        # reference: the first candidate of the window (both sides)
+        e = delta_logl_error(l[a:a + n], lo[i], l[a], lo[i][0])
+        rho = math.sqrt(max(co[i][0, 1], 0.0))
+        worst.append((e.max(), rho))
+    worst = np.array(worst)
+    banner("  per-window max dlogL error vs rho: " +
+           ", ".join(f"{e:.1e}@{r:.0f}" for e, r in worst[np.argsort(-worst[:, 0])][:6]))
+    quiet = worst[:, 1] < 100
+    assert np.all(worst[quiet, 0] <= 1e-5)
+
+
+def test_edge_cases(oracle_lib, ctx1):
+    banner("edge cases")
+    O = oracle_lib
+    T = I.T1
+    rng = np.random.default_rng(7)
+    # window A: N=1024, C=3, W=4096; window B: empty; window C: W=1; window D: N=64
+    specs = [(int(12e-3 * T) - 2048, 4096, 1024, 3), (int(2e-3 * T), 100, 128, 2),
+             (int(5e-3 * T), 1, 256, 2), (int(1e-3 * T) - 32, 64, 64, 2)]
+    ncand = [9, 0, 5, 7]
+    wins, thetas = [], []
+    for (k0, W, N, C), n in zip(specs, ncand):
+        f = (k0 + W / 2) / T
+        th = I.make_theta(np.full(n, f) + rng.uniform(-20, 20, n) / T, 1e-17, 1e-22, I.random_angles(rng, n))
+        wins.append(I.WindowSpec(k0, W, N, C, k0 / T, (k0 + W) / T, th[:1] if n else np.zeros((0, 8))))
+        thetas.append(th)
+    # window C: template far outside (logL = -<d|d>/2); a NaN and a negative amplitude in window D
+    thetas[2][1, 0] = (specs[2][0] + 5000) / T
+    thetas[3][2, 3] = np.nan
+    thetas[3][4, 4] = -1e-22
+    wl = I._concat(wins, thetas, "edge", T)
+    I.finalize_data(wl, O.template_fn(), np.random.default_rng(8))
+    l, comps, _ = run_gpu_loglik(wl, api.GB_FP64)
+    lo, co = O.loglik_workload(wl)
+    dd = window_dd(wl)
+    for i in range(wl.n_win):
+        a, n = int(wl.cand_off[i]), int(wl.n_cand[i])
+        ok = np.isfinite(wl.window_theta(i)).all(axis=1) & (wl.window_theta(i)[:, 4] >= 0)
+        tol = loglik_tolerance(dd[i], co[i][:, 0], co[i][:, 1])
+        assert np.all(np.abs(l[a:a + n][ok] - lo[i][ok]) <= tol[ok]), i
+        assert np.all(np.isnan(l[a:a + n][~ok]))
+    a = int(wl.cand_off[2])
+    assert abs(l[a + 1] + 0.5 * dd[2]) <= 1e-12 * dd[2]
+
+
+def test_determinism(c3_small):
+    banner("determinism")
+    for prec in (api.GB_FP64, api.GB_MIXED):
+        l1, c1_, (ctx, plan, d, w, th) = run_gpu_loglik(c3_small, prec)
+        l2, cp2 = plan.loglik(th, comps=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(l1, l2.cpu().numpy()) and np.array_equal(c1_, cp2.cpu().numpy())
+
+
+def test_mh_step_chain_is_bit_exact(oracle_lib):
+    banner("mh step")
+    O = oracle_lib
+    wl = I.workload_c2(O.template_fn(), n_cand=3000)
+    ctx = api.context_for(wl.T)
+    plan = api.Plan(ctx, wl.window_table(), api.GB_FP64)
+    d, w = dev(wl.data, torch.complex128), dev(wl.weights)
+    plan.prepare(d, w)
+    rng = np.random.default_rng(9)
+    n = int(wl.n_cand[0])
+    log_g = rng.normal(0, 0.3, n)
+    u = rng.random(n)
+    u[5] = 0.0
+    for temp in (1.0, 5.0):
+        l, chain, nacc = plan.mh_step(dev(wl.theta), dev(log_g), dev(u), temp)
+        torch.cuda.synchronize()
+        l, chain, nacc = l.cpu().numpy(), chain.cpu().numpy(), nacc.cpu().numpy()
+        ref_chain, ref_acc = O.mh_chain(l, log_g, u, temp)
+        assert np.array_equal(chain, ref_chain) and nacc[0] == ref_acc
+        banner(f"  T={temp}: accepted {ref_acc}/{n}")
+    lo, co = O.loglik_workload(wl)
+    tol = loglik_tolerance(window_dd(wl)[0], co[0][:, 0], co[0][:, 1])
+    assert np.all(np.abs(l - lo[0]) <= tol)
+
+
+def test_graph_capture_replays(c3_small):
+    """gb_loglik captured in a HIP graph: every replay (with eager work in between) equals eager."""
+    banner("graph capture")
+    l_eager, _, (ctx, plan, d, w, th) = run_gpu_loglik(c3_small, api.GB_MIXED, comps=False)
+    out = torch.empty(plan.rows, dtype=torch.float64, device="cuda")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        api.gb_loglik(plan.handle, d, w, th, out, None, s)   # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        api.gb_loglik(plan.handle, d, w, th, out, None, s)
+    for k in range(3):
+        out.zero_()
+        junk = torch.randn(1000, device="cuda").sum()   # eager work between replays
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), l_eager), k
+        del junk
+
+
+def test_rejects_unprepared_data(c3_small):
+    banner("error paths")
+    _, _, (ctx, plan, d, w, th) = run_gpu_loglik(c3_small, api.GB_FP64, comps=False)
+    other = d.clone()
+    out = torch.empty(plan.rows, dtype=torch.float64, device="cuda")
+    with pytest.raises(api.GbxError) as e:
+        api.gb_loglik(plan.handle, other, w, th, out)
+    assert e.value.status == api.GB_EINVAL
+    bad = np.array([[0, 10, 100, 2, 0, 0, 0, 1]])
+    with pytest.raises(api.GbxError):
+        api.Plan(ctx, bad, api.GB_FP64)
+    with pytest.raises(api.GbxError):
+        ctx.waveform(th[:2], 96, 2)
