@@ -1,17 +1,24 @@
-"""Build the HIP library libgbx.so for gfx950, in-tree (next to this file)."""
+"""Build the HIP library libgbx.so for gfx950, in-tree (next to this file).
 
+The kernel families live in separate translation units (one per precision and mode, plus the
+waveform kernels and the host-side ABI) compiled in parallel, then linked into one library."""
+
+import concurrent.futures as cf
 import os
 import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "gbx.hip")
+CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libgbx.so")
+OBJ = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+UNITS = ["gbx.hip", "k_f64_loglik.hip", "k_mixed_loglik.hip", "k_f64_grad.hip", "k_mixed_grad.hip",
+         "k_waveform.hip"]
 
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 instructions stay off (hipcc would otherwise form them from float code)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
@@ -19,8 +26,22 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False, extra=()) -> str:
-    cmd = [HIPCC] + FLAGS + list(extra) + ["-o", OUT + ".tmp", SRC]
+def _compile(unit: str, verbose: bool) -> str:
+    src = os.path.join(CSRC, unit)
+    obj = os.path.join(OBJ, unit.replace(".hip", ".o"))
+    cmd = [HIPCC] + FLAGS + ["-c", "-o", obj, src]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    return obj
+
+
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    os.makedirs(OBJ, exist_ok=True)
+    jobs = jobs or min(len(UNITS), os.cpu_count() or 1)
+    with cf.ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(lambda u: _compile(u, verbose), UNITS))
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", OUT + ".tmp"] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -12,8 +12,10 @@
 #include <vector>
 
 #include "gbx_kernels.h"
+#include "gbx_variants.h"
 
 using namespace gbx;
+
 
 // ------------------------------------------------------------------------------- errors
 static thread_local std::string g_err;
@@ -146,35 +148,27 @@ __global__ void __launch_bounds__(64) k_mh_chain(const DevWin* wins, const doubl
 // ------------------------------------------------------------------------------- variants
 namespace {
 
-struct Variant {
-  int prec, N, LPC, C, WPB, mode;
-  const void* fn;
-};
+const VariantList& all_variants() {
+  static std::vector<Variant> v;
+  static VariantList list{nullptr, 0};
+  if (!list.v) {
+    for (VariantList (*f)() : {gbx_variants_f64_loglik, gbx_variants_mixed_loglik, gbx_variants_f64_grad,
+                               gbx_variants_mixed_grad, gbx_variants_waveform}) {
+      const VariantList l = f();
+      v.insert(v.end(), l.v, l.v + l.n);
+    }
+    list.v = v.data();
+    list.n = (int)v.size();
+  }
+  return list;
+}
 
-#define GBX_V(P, RT, NN, LL, CC, WW, MM) \
-  Variant { P, NN, LL, CC, WW, MM, reinterpret_cast<const void*>(&k_batch<RT, NN, LL, CC, WW, MM>) }
-#define GBX_W(P, RT, NN, LL, CC, WW) \
-  Variant { P, NN, LL, CC, WW, MODE_WAVEFORM, reinterpret_cast<const void*>(&k_waveform<RT, NN, LL, CC, WW>) }
-
-#define GBX_ALLC(M, P, RT, NN, LL, WW) M(P, RT, NN, LL, 2, WW), M(P, RT, NN, LL, 3, WW)
-#define GBX_LL(P, RT, NN, LL, CC, WW) GBX_V(P, RT, NN, LL, CC, WW, MODE_LOGLIK)
-#define GBX_GR(P, RT, NN, LL, CC, WW) GBX_V(P, RT, NN, LL, CC, WW, MODE_GRAD)
-
-#define GBX_ALLN(M, P, RT)                                                           \
-  GBX_ALLC(M, P, RT, 64, 16, 4), GBX_ALLC(M, P, RT, 128, 32, 4), GBX_ALLC(M, P, RT, 256, 64, 4), \
-      GBX_ALLC(M, P, RT, 512, 128, 4), GBX_ALLC(M, P, RT, 1024, 256, 4)
-
-const Variant kVariants[] = {
-    GBX_ALLN(GBX_LL, GB_FP64, double), GBX_ALLN(GBX_LL, GB_MIXED, float),
-    GBX_ALLN(GBX_W, GB_FP64, double), GBX_ALLN(GBX_W, GB_MIXED, float),
-    GBX_ALLN(GBX_GR, GB_FP64, double), GBX_ALLN(GBX_GR, GB_MIXED, float),
-};
-
-const Variant* find_variant(int prec, int N, int C, int mode, int LPC = 0, int WPB = 0) {
-  for (const Variant& v : kVariants)
-    if (v.prec == prec && v.N == N && v.C == C && v.mode == mode && (LPC == 0 || v.LPC == LPC) &&
-        (WPB == 0 || v.WPB == WPB))
-      return &v;
+const Variant* find_variant(int prec, int N, int C, int mode) {
+  const VariantList& l = all_variants();
+  for (int i = 0; i < l.n; ++i) {
+    const Variant& v = l.v[i];
+    if (v.prec == prec && v.N == N && v.C == C && v.mode == mode) return &v;
+  }
   return nullptr;
 }
 
@@ -205,7 +199,13 @@ struct gb_ctx {
   int device = 0;
   int n_cu = 256;
   NTab tab[5];
+  const Variant* choice[2][5][2][3] = {};  // autotuned variant per precision, N, C, mode
 };
+
+static const Variant* pick_variant(const gb_ctx* c, int prec, int N, int C, int mode) {
+  const Variant* v = c ? c->choice[prec][n_index(N)][C - 2][mode] : nullptr;
+  return v ? v : find_variant(prec, N, C, mode);
+}
 
 extern "C" const char* gb_last_error(void) { return g_err.c_str(); }
 
@@ -280,7 +280,7 @@ extern "C" gb_status gb_waveform(gb_ctx* c, const double* theta, int64_t B, int 
   if (prec != GB_FP64 && prec != GB_MIXED) return fail(GB_EINVAL, "gb_waveform: bad precision %d", (int)prec);
   if (B == 0) return GB_OK;
   if (!theta || !h_out || !first_bin) return fail(GB_EINVAL, "gb_waveform: null array");
-  const Variant* v = find_variant(prec, N, C, MODE_WAVEFORM);
+  const Variant* v = pick_variant(c, prec, N, C, MODE_WAVEFORM);
   if (!v) return fail(GB_EUNSUPPORTED, "gb_waveform: no variant for N=%d C=%d", N, C);
   BatchArgs a = base_args(c, N, prec);
   a.theta = theta;
@@ -381,7 +381,7 @@ extern "C" gb_status gb_plan_create(gb_ctx* c, const gb_window* windows, int n_w
     b.N = w0.N;
     b.C = w0.C;
     for (int m = 0; m < 3; ++m) {
-      b.v[m] = find_variant(b.prec, b.N, b.C, m);
+      b.v[m] = pick_variant(c, b.prec, b.N, b.C, m);
       b.grid[m] = 0;
     }
     if (!b.v[MODE_LOGLIK]) {
@@ -458,6 +458,8 @@ static gb_status run_batch(gb_plan* p, int mode, const double* d, const double* 
   for (Bucket& b : p->buckets) {
     if (b.n_tiles == 0) continue;
     const Variant* v = b.v[mode];
+    if (!v && mode == MODE_GRAD && b.prec == GB_FP64 && b.N >= 512)
+      return fail(GB_EUNSUPPORTED, "%s: the FP64 gradient is available for N <= 256 only (N=%d); use GB_MIXED", who, b.N);
     if (!v) return fail(GB_EUNSUPPORTED, "%s: no kernel variant for N=%d C=%d", who, b.N, b.C);
     BatchArgs a = base_args(p->ctx, b.N, b.prec);
     a.wins = p->d_wins;
@@ -502,9 +504,127 @@ extern "C" gb_status gb_mh_step(gb_plan* p, const double* d, const double* w, co
   return GB_OK;
 }
 
+// Time every compiled variant of each (precision, N, C, mode) family on synthetic candidates
+// (one window of W = N bins at 8 mHz, 16384 candidates) and keep the fastest in the context.
 extern "C" gb_status gb_autotune(gb_ctx* c, int reps, char* report, size_t report_len) {
-  (void)reps;
   if (!c) return fail(GB_EINVAL, "gb_autotune: null context");
-  if (report && report_len) std::snprintf(report, report_len, "default shapes (E = 4 samples per lane, 4 waves)");
+  if (reps < 1) reps = 1;
+  const int B = 16384;
+  std::string rep;
+  // synthetic candidates (deterministic linear congruential draws), data and weights
+  std::vector<double> th(8 * (size_t)B);
+  uint64_t st = 0x9E3779B97F4A7C15ull;
+  auto uni = [&]() {
+    st = st * 6364136223846793005ull + 1442695040888963407ull;
+    return (double)(st >> 11) * (1.0 / 9007199254740992.0);
+  };
+  const double f = 8e-3, T = c->cfg.T;
+  for (int i = 0; i < B; ++i) {
+    double* t = &th[8 * (size_t)i];
+    t[0] = f + (uni() - 0.5) * 64.0 / T;
+    t[1] = 1e-16;
+    t[2] = std::asin(2.0 * uni() - 1.0);
+    t[3] = (2.0 * uni() - 1.0) * kPi;
+    t[4] = 1e-22;
+    t[5] = std::acos(2.0 * uni() - 1.0);
+    t[6] = uni() * kPi;
+    t[7] = uni() * 2.0 * kPi;
+  }
+  double *d_th = nullptr, *d_d = nullptr, *d_w = nullptr, *d_l = nullptr, *d_g = nullptr;
+  DevWin* d_win = nullptr;
+  Tile* d_tiles = nullptr;
+  unsigned* d_ctr = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const int Wmax = 1024, Cmax = 3;
+  hipError_t e = hipMalloc(&d_th, sizeof(double) * th.size());
+  if (e == hipSuccess) e = hipMemcpy(d_th, th.data(), sizeof(double) * th.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(&d_d, sizeof(double) * 2 * Wmax * Cmax);
+  if (e == hipSuccess) e = hipMemset(d_d, 0, sizeof(double) * 2 * Wmax * Cmax);
+  std::vector<double> wv((size_t)Wmax * Cmax, 1e40);
+  if (e == hipSuccess) e = hipMalloc(&d_w, sizeof(double) * wv.size());
+  if (e == hipSuccess) e = hipMemcpy(d_w, wv.data(), sizeof(double) * wv.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(&d_l, sizeof(double) * B);
+  if (e == hipSuccess) e = hipMalloc(&d_g, sizeof(double) * 8 * B);
+  if (e == hipSuccess) e = hipMalloc(&d_win, sizeof(DevWin));
+  if (e == hipSuccess) e = hipMalloc(&d_tiles, sizeof(Tile) * B);
+  if (e == hipSuccess) e = hipMalloc(&d_ctr, 2 * sizeof(unsigned));
+  if (e == hipSuccess) e = hipMemset(d_ctr, 0, 2 * sizeof(unsigned));
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  const VariantList& all = all_variants();
+  for (int prec = 0; prec < 2 && e == hipSuccess; ++prec)
+    for (int ni = 0; ni < 5 && e == hipSuccess; ++ni)
+      for (int C = 2; C <= 3 && e == hipSuccess; ++C)
+        for (int mode = MODE_LOGLIK; mode <= MODE_GRAD && e == hipSuccess; ++mode) {
+          const int N = 64 << ni;
+          DevWin w;
+          std::memset(&w, 0, sizeof w);
+          w.k0 = (int64_t)std::floor(f * T) - N / 2;
+          w.W = N;
+          w.N = N;
+          w.C = C;
+          w.prec = prec;
+          w.n_cand = B;
+          w.dd = 0.0;
+          e = hipMemcpy(d_win, &w, sizeof w, hipMemcpyHostToDevice);
+          const Variant* best = nullptr;
+          float best_ms = 0.0f;
+          int tried = 0;
+          for (int i = 0; i < all.n && e == hipSuccess; ++i) {
+            const Variant& v = all.v[i];
+            if (v.prec != prec || v.N != N || v.C != C || v.mode != mode) continue;
+            const int tsz = v.WPB * 64 / v.LPC * kTileIters;
+            std::vector<Tile> tiles;
+            for (int c0 = 0; c0 < B; c0 += tsz) tiles.push_back(Tile{0, std::min(tsz, B - c0), c0});
+            e = hipMemcpy(d_tiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice);
+            int nb = 0;
+            if (e == hipSuccess)
+              e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, v.fn, v.WPB * 64, lds_bytes(v));
+            if (e != hipSuccess) break;
+            BatchArgs a = base_args(c, N, prec);
+            a.wins = d_win;
+            a.tiles = d_tiles;
+            a.n_tiles = (int)tiles.size();
+            a.ctr = d_ctr;
+            a.d = d_d;
+            a.w = d_w;
+            a.theta = d_th;
+            a.logL = d_l;
+            a.grad = d_g;
+            const dim3 grid((unsigned)std::max(1, std::min((int)tiles.size(), std::max(1, nb) * c->n_cu)));
+            gb_status s = launch(&v, grid, a, 0);  // warm-up
+            if (s != GB_OK) {
+              e = hipErrorLaunchFailure;
+              break;
+            }
+            e = hipEventRecord(e0, 0);
+            for (int r = 0; r < reps && e == hipSuccess; ++r)
+              if (launch(&v, grid, a, 0) != GB_OK) e = hipErrorLaunchFailure;
+            if (e == hipSuccess) e = hipEventRecord(e1, 0);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            ms /= (float)reps;
+            ++tried;
+            if (!best || ms < best_ms) {
+              best = &v;
+              best_ms = ms;
+            }
+          }
+          if (best) {
+            c->choice[prec][ni][C - 2][mode] = best;
+            char line[200];
+            std::snprintf(line, sizeof line, "%s %s N=%d C=%d: lanes/template=%d min waves/SIMD=%d %.4f ms / %d (%d variants)\n",
+                          prec == GB_FP64 ? "fp64 " : "mixed", mode == MODE_GRAD ? "grad  " : "loglik", N, C,
+                          best->LPC, best->occ, best_ms, B, tried);
+            rep += line;
+          }
+        }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  for (void* p : {(void*)d_th, (void*)d_d, (void*)d_w, (void*)d_l, (void*)d_g, (void*)d_win, (void*)d_tiles, (void*)d_ctr})
+    (void)hipFree(p);
+  if (e != hipSuccess) return fail(GB_EHIP, "gb_autotune: %s", hipGetErrorString(e));
+  if (report && report_len) std::snprintf(report, report_len, "%s", rep.c_str());
   return GB_OK;
 }

@@ -77,7 +77,8 @@ template <class R, int N, int LPC, int C>
 __device__ __forceinline__ void template_to_lds(const Cand<R>& s, const BatchArgs& a, int lane, cplx<R>* buf) {
   constexpr int E = N / LPC;
   const R* obR = (const R*)a.obR;
-#pragma unroll
+  // one sample at a time: keeps the live state of a single sample in registers
+#pragma unroll 1
   for (int e = 0; e < E; ++e) {
     const int m = lane + LPC * e;
     const double t = a.T * (double)m / (double)N;
@@ -180,14 +181,22 @@ __device__ __forceinline__ void process_grad(const BatchArgs& a, const DevWin& w
   fft_lds<R, N, LPC, C, +1>(buf, lane, (const cplx<R>*)a.tw);
   GradAcc ga = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   const R* obR = (const R*)a.obR;
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
+  auto sample = [&](int e) {
     const int m = lane + LPC * e;
     const double t = a.T * (double)m / (double)N;
     cplx<R> sbar[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) sbar[c] = buf[c * N + m];
     grad_sample<R, C>(s, sg, a.ob64, obR, N, m, t, a.Lc, sbar, ga);
+  };
+  if (sizeof(R) == 8) {
+    // FP64: the fully unrolled form (the loop form of this kernel is not used, see the
+    // design notes on the FP64 gradient)
+#pragma unroll
+    for (int e = 0; e < E; ++e) sample(e);
+  } else {
+#pragma unroll 1
+    for (int e = 0; e < E; ++e) sample(e);
   }
   v[3] = ga.gf;
   v[4] = ga.gtf;
@@ -231,8 +240,8 @@ __device__ __forceinline__ void process_grad(const BatchArgs& a, const DevWin& w
 
 // Persistent batched kernel: workgroups take tiles from the plan's queue until it is empty.
 // The last workgroup to finish resets the queue counters for the next launch.
-template <class R, int N, int LPC, int C, int WPB, int MODE>
-__global__ void __launch_bounds__(WPB * 64) k_batch(BatchArgs a) {
+template <class R, int N, int LPC, int C, int WPB, int MODE, int OCC>
+__global__ void __launch_bounds__(WPB * 64, OCC) k_batch(BatchArgs a) {
   constexpr int CPB = WPB * 64 / LPC;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_tile;

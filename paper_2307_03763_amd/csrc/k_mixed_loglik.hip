@@ -1,0 +1,17 @@
+// Kernel variants: mixed-precision log-likelihood.
+#include "../../include/gbx.h"
+#include "gbx_kernels.h"
+#include "gbx_variants.h"
+
+using namespace gbx;
+
+#define V(NN, LL, CC, OO) \
+  Variant { GB_MIXED, NN, LL, CC, 4, MODE_LOGLIK, OO, reinterpret_cast<const void*>(&k_batch<float, NN, LL, CC, 4, MODE_LOGLIK, OO>) }
+#define VC(NN, LL, OO) V(NN, LL, 2, OO), V(NN, LL, 3, OO)
+// per N: 4 and 8 samples per lane, two register budgets; the first entry is the default
+#define VN(OO) VC(64, 16, OO), VC(128, 32, OO), VC(256, 64, OO), VC(512, 128, OO), VC(1024, 256, OO), \
+               VC(64, 8, OO), VC(128, 16, OO), VC(256, 32, OO), VC(512, 64, OO), VC(1024, 128, OO)
+
+static const Variant kTable[] = {VN(2), VN(4)};
+
+extern "C" VariantList gbx_variants_mixed_loglik() { return VariantList{kTable, (int)(sizeof kTable / sizeof kTable[0])}; }
