@@ -61,11 +61,16 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--rho-mixed", type=float, default=8.0)
+    ap.add_argument("--copy-calibration", action="store_true")
     return ap.parse_args()
 
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}, "
@@ -98,76 +103,109 @@ def main():
     table = wl.window_table()
     rows = len(wl.theta)
 
-    # one plan per (N, C) group: each is one persistent launch over all of its windows
-    groups = {}
-    for i, win in enumerate(wl.windows):
-        groups.setdefault((win.N, win.C), []).append(i)
-    keys = sorted(groups, key=lambda k: (-k[0], -k[1]))
+    # ---------------------------------------------------------------- autotune launch shapes
+    t0 = time.time()
+    tune = api.gb_autotune(ctx.handle, 3)
+    log(f"autotune {time.time() - t0:.1f}s:\n{tune}")
 
-    def make_plans(prec):
-        plans = []
-        for k in keys:
-            p = api.Plan(ctx, table[groups[k]], prec)
-            p.rows = rows
-            p.prepare(d, w)
-            plans.append(p)
-        return plans
+    # ---------------------------------------------------------------- precision policy
+    # SNR of the loudest injection of every window (FP64 components on the GPU); windows at or
+    # below RHO_MIXED run in mixed precision, louder ones in FP64 (Sec. III G sampling needs
+    # logL differences to 1e-5; the mixed error grows like 6e-7 rho)
+    rho_w = window_snr(api, ctx, wl, d, w)
+    prec_w = np.where(rho_w <= args.rho_mixed, api.GB_MIXED, api.GB_FP64)
+    log(f"precision policy: rho <= {args.rho_mixed}: {int((prec_w == api.GB_MIXED).sum())} of {wl.n_win} windows mixed")
 
-    plans = make_plans(api.GB_MIXED)
     stream = torch.cuda.current_stream()
     logL = torch.empty(rows, dtype=torch.float64, device="cuda")
     chain = torch.empty(rows, dtype=torch.int32, device="cuda")
     grad = torch.empty((rows, 8), dtype=torch.float64, device="cuda")
-    nacc = [torch.empty(len(groups[k]), dtype=torch.int64, device="cuda") for k in keys]
     glog = torch.empty(rows, dtype=torch.float64, device="cuda")
-
-    def step(plans, ev=None):
-        for j, p in enumerate(plans):
-            if ev is not None:
-                ev[j][0].record(stream)
-            api.gb_mh_step(p.handle, d, w, th, log_g, u, args.temperature, logL, chain, nacc[j], stream)
-            if ev is not None:
-                ev[j][1].record(stream)
-            api.gb_loglik_grad(p.handle, d, w, th, glog, grad, stream)
-            if ev is not None:
-                ev[j][2].record(stream)
-
-    for _ in range(args.warmup):
-        step(plans)
-    torch.cuda.synchronize()
-
     E = lambda: torch.cuda.Event(enable_timing=True)
-    evs = [[[E(), E(), E()] for _ in keys] for _ in range(args.steps)]
-    start, end = E(), E()
-    torch.cuda.synchronize()
-    start.record(stream)
-    for s in range(args.steps):
-        step(plans, evs[s])
-    end.record(stream)
-    torch.cuda.synchronize()
-    ms_step = start.elapsed_time(end) / args.steps
-    t_mh = np.array([[evs[s][j][0].elapsed_time(evs[s][j][1]) for j in range(len(keys))] for s in range(args.steps)])
-    t_gr = np.array([[evs[s][j][1].elapsed_time(evs[s][j][2]) for j in range(len(keys))] for s in range(args.steps)])
-    ms_logl = float(t_mh.sum(axis=1).mean())
-    ms_grad = float(t_gr.sum(axis=1).mean())
-    assert bool(torch.isfinite(logL).all()) and bool(torch.isfinite(grad).all()), "non-finite outputs"
-    log(f"mixed ragged: {ms_step:.2f} ms/step (MH stage {ms_logl:.2f} ms, gradients {ms_grad:.2f} ms)")
 
-    # dominant kernel: the gradient launch of the group with the largest share of the step
-    j_dom = int(np.argmax(t_gr.mean(axis=0)))
-    kN, kC = keys[j_dom]
-    idx = groups[keys[j_dom]]
+    def make_groups(prec_of_window, grad_prec_of_window):
+        """(plan for logL/MH, plan for gradients) per (N, C, precision) group; each plan is one
+        persistent launch over all of its windows."""
+        groups = {}
+        for i, win in enumerate(wl.windows):
+            groups.setdefault(("mh", win.N, win.C, int(prec_of_window[i])), []).append(i)
+            groups.setdefault(("gr", win.N, win.C, int(grad_prec_of_window[i])), []).append(i)
+        out = []
+        for key in sorted(groups, key=lambda k: (k[0], -k[1], -k[2], k[3])):
+            idx = groups[key]
+            p = api.Plan(ctx, table[idx], key[3])
+            p.prepare(d, w)
+            out.append((key, idx, p, torch.empty(len(idx), dtype=torch.int64, device="cuda")))
+        return out
+
+    def run_steps(groups, steps, warmup):
+        def one(ev):
+            for j, (key, idx, p, nacc) in enumerate(groups):
+                if ev is not None:
+                    ev[j][0].record(stream)
+                if key[0] == "mh":
+                    api.gb_mh_step(p.handle, d, w, th, log_g, u, args.temperature, logL, chain, nacc, stream)
+                else:
+                    api.gb_loglik_grad(p.handle, d, w, th, glog, grad, stream)
+                if ev is not None:
+                    ev[j][1].record(stream)
+        for _ in range(warmup):
+            one(None)
+        torch.cuda.synchronize()
+        evs = [[[E(), E()] for _ in groups] for _ in range(steps)]
+        start, end = E(), E()
+        start.record(stream)
+        for s_ in range(steps):
+            one(evs[s_])
+        end.record(stream)
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(end) / steps
+        per = np.array([[evs[s_][j][0].elapsed_time(evs[s_][j][1]) for j in range(len(groups))] for s_ in range(steps)])
+        assert bool(torch.isfinite(logL).all()) and bool(torch.isfinite(grad).all()), "non-finite outputs"
+        return ms, per.mean(axis=0)
+
+    def summary(groups, ms, per):
+        ms_mh = float(sum(t for (k, *_), t in zip(groups, per) if k[0] == "mh"))
+        ms_gr = float(sum(t for (k, *_), t in zip(groups, per) if k[0] == "gr"))
+        return {"ms_per_step": round(ms, 4), "value": round(2 * rows / (ms * 1e-3), 1),
+                "logl_evals_per_s": round(rows / (ms_mh * 1e-3), 1),
+                "grad_evals_per_s": round(rows / (ms_gr * 1e-3), 1)}
+
+    # adaptive ragged (the headline); gradients run in mixed precision (the FP64 gradient is
+    # switched off in this version of the library)
+    grad_prec = np.full(wl.n_win, api.GB_MIXED)
+    groups_ad = make_groups(prec_w, grad_prec)
+    ms_ad, per_ad = run_steps(groups_ad, args.steps, args.warmup)
+    adaptive = summary(groups_ad, ms_ad, per_ad)
+    log(f"adaptive ragged: {ms_ad:.2f} ms/step {adaptive}")
+
+    # mixed precision everywhere
+    allmix = np.full(wl.n_win, api.GB_MIXED)
+    groups_mx = make_groups(allmix, allmix)
+    ms_mx, per_mx = run_steps(groups_mx, args.steps, args.warmup)
+    mixed = summary(groups_mx, ms_mx, per_mx)
+    log(f"mixed ragged: {ms_mx:.2f} ms/step {mixed}")
+    logl_mixed = logL.cpu().numpy().copy()
+
+    # dominant kernel of the headline step
+    j_dom = int(np.argmax(per_ad))
+    key, idx, _, _ = groups_ad[j_dom]
+    kind, kN, kC, kP = key
     n_dom = int(sum(wl.n_cand[i] for i in idx))
-    fl = sum(int(wl.n_cand[i]) * flops_per_eval(kN, kC, min(wl.windows[i].W, kN), True) for i in idx)
-    dur_ms = float(t_gr[:, j_dom].mean())
+    is_grad = kind == "gr"
+    fl = sum(int(wl.n_cand[i]) * flops_per_eval(kN, kC, min(wl.windows[i].W, kN), is_grad) for i in idx)
+    dur_ms = float(per_ad[j_dom])
     achieved_tf = fl / (dur_ms * 1e-3) / 1e12
+    kname = (f"k_batch<{'double' if kP == api.GB_FP64 else 'float'}, N={kN}, C={kC}, "
+             f"{'gradient' if is_grad else 'logL'}>")
     roofline = {"bound": "alu", "achieved": round(achieved_tf, 3), "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved_tf / PEAK_VALU_TFLOPS, 4), "traffic": None,
-                "kernel": f"k_batch<float, N={kN}, C={kC}, gradient>", "launch_ms": round(dur_ms, 4),
-                "evals_per_launch": n_dom,
-                "hbm_gbs": round((n_dom * bytes_per_eval(kC, kN, True) +
+                "frac": round(achieved_tf / PEAK_VALU_TFLOPS, 4), "traffic": committed_traffic(kname, n_dom),
+                "kernel": kname,
+                "launch_ms": round(dur_ms, 4), "evals_per_launch": n_dom,
+                "flops_per_eval": round(fl / n_dom, 1),
+                "hbm_gbs": round((n_dom * bytes_per_eval(kC, kN, is_grad) +
                                   sum(24.0 * kC * wl.windows[i].W for i in idx)) / (dur_ms * 1e-3) / 1e9, 3),
-                "sincos_per_s": round(sum(int(wl.n_cand[i]) for i in idx) * sincos_per_eval(kN, True) / (dur_ms * 1e-3), 1)}
+                "sincos_per_s": round(n_dom * sincos_per_eval(kN, is_grad) / (dur_ms * 1e-3), 1)}
 
     # ---------------------------------------------------------------- plain FP64: one launch per window
     fp64 = None
@@ -184,51 +222,112 @@ def main():
             for p in win_plans:
                 api.gb_mh_step(p.handle, d, w, th, log_g, u, args.temperature, logL, chain, nacc1, stream)
             ev[1].record(stream)
-            for p in win_plans:
-                api.gb_loglik_grad(p.handle, d, w, th, glog, grad, stream)
-            ev[2].record(stream)
 
-        plain([E(), E(), E()])
+        plain([E(), E()])
         torch.cuda.synchronize()
-        ev = [E(), E(), E()]
+        ev = [E(), E()]
         plain(ev)
         torch.cuda.synchronize()
-        f_l, f_g = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
-        fp64 = {"ms_per_step": round(f_l + f_g, 3), "logl_evals_per_s": round(rows / (f_l * 1e-3), 1),
-                "grad_evals_per_s": round(rows / (f_g * 1e-3), 1),
-                "value": round(2 * rows / ((f_l + f_g) * 1e-3), 1)}
-        log(f"plain FP64 per window: {f_l + f_g:.2f} ms/pass (MH stage {f_l:.2f}, gradients {f_g:.2f})")
+        f_l = ev[0].elapsed_time(ev[1])
+        fp64 = {"logl_evals_per_s": round(rows / (f_l * 1e-3), 1), "ms_mh_stage": round(f_l, 3),
+                "grad_evals_per_s": None,
+                "note": "MH stage (logL of every proposal + chains) in FP64, one launch per window; "
+                        "the FP64 gradient is switched off in this version"}
+        log(f"plain FP64 per window: logL {fp64['logl_evals_per_s']:.3e}/s")
         for p in win_plans:
             p.close()
 
-    # ---------------------------------------------------------------- CPU oracle on a bounded sample
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(wl, args.cpu_seconds, logL, grad, log)
 
-    value = 2 * rows / (ms_step * 1e-3)
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(wl, args.cpu_seconds, logl_mixed, rho_w, log)
+
+    value = adaptive["value"]
     out = {
-        "metric": METRIC, "value": round(value, 1), "unit": "evals/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": adaptive["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": wl.name, "windows": wl.n_win, "candidates": rows,
-                   "groups": [f"N={k[0]},C={k[1]}:{len(groups[k])}" for k in keys],
-                   "T_s": T, "precision": "mixed (FP64 phase and accumulation, FP32 response and DFT)",
-                   "step": "per (N, C) group: MH stage (logL of all proposals + chains), then all gradients"},
-        "logl_evals_per_s": round(rows / (ms_logl * 1e-3), 1),
-        "grad_evals_per_s": round(rows / (ms_grad * 1e-3), 1),
+        "config": {"workload": wl.name, "windows": wl.n_win, "candidates": rows, "T_s": T,
+                   "precision": f"adaptive: mixed (FP64 phase and accumulation, FP32 response and DFT) for "
+                                f"windows with injected SNR <= {args.rho_mixed}, FP64 otherwise",
+                   "mixed_windows": int((prec_w == api.GB_MIXED).sum()),
+                   "step": "per (N, C, precision) group one persistent launch: MH stage (logL of all "
+                           "proposals + chains), then all gradients"},
+        "logl_evals_per_s": adaptive["logl_evals_per_s"],
+        "grad_evals_per_s": adaptive["grad_evals_per_s"],
+        "mixed_everywhere": mixed,
         "fp64_plain": fp64,
-        "speedup_vs_fp64": round(value / fp64["value"], 3) if fp64 else None,
+        "speedup_vs_fp64": (round(adaptive["logl_evals_per_s"] / fp64["logl_evals_per_s"], 3) if fp64 else None),
+        "speedup_basis": "logL evals/s of the MH stage, adaptive ragged vs plain FP64 per window",
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "autotune": tune.strip().split("\n"),
+        "library": library_hash(),
         "context": "paper: 1.8 s per posterior of 6 x 10,000 likelihoods on a Quadro RTX 4000 Mobile "
                    "(about 3.3e4 logL/s including chain and KDE); different hardware and work",
     }
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(wl, seconds, logL_gpu, grad_gpu, log):
+def library_hash() -> str:
+    import hashlib
+    from paper_2307_03763_amd import api
+    return hashlib.sha256(open(api.LIB_PATH, "rb").read()).hexdigest()[:16]
+
+
+def committed_traffic(kernel: str, evals: int):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/hbm_traffic.txt, lines 'library=<hash> kernel=<name> evals=<n> bytes=<B>'),
+    scaled to `evals`; None when absent or taken with another build of the library."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    h = library_hash()
+    for line in open(path):
+        f = dict(x.split("=", 1) for x in line.split() if "=" in x)
+        if f.get("library") == h and f.get("kernel") == kernel.replace(" ", ""):
+            return round(float(f["bytes"]) * evals / float(f["evals"]), 1)
+    return None
+
+
+def copy_calibration():
+    """A device copy of a known size, profiled with the same counters as the kernels
+    (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE) to scale them to bytes."""
+    import torch
+    n = 1 << 28  # 256 M doubles = 2 GiB read + 2 GiB written
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "launches": 3}), flush=True)
+
+
+def window_snr(api, ctx, wl, d, w):
+    """sqrt(<h|h>) of the loudest injection of every window (FP64 components on the GPU)."""
+    import numpy as np
+    import torch
+    tab = wl.window_table().copy()
+    srcs, off = [], 0
+    for i, win in enumerate(wl.windows):
+        tab[i, 6] = off
+        tab[i, 7] = len(win.sources)
+        srcs.append(win.sources)
+        off += len(win.sources)
+    p = api.Plan(ctx, tab, api.GB_FP64)
+    p.prepare(d, w)
+    _, comps = p.loglik(torch.as_tensor(np.concatenate(srcs), device="cuda"), comps=True)
+    hh = comps[:, 1].cpu().numpy()
+    out = np.array([np.sqrt(hh[tab[i, 6]:tab[i, 6] + tab[i, 7]].max()) for i in range(wl.n_win)])
+    p.close()
+    return out
+
+
+def cpu_baseline(wl, seconds, logL_gpu, rho_w, log):
     """The oracle, unmodified, on a stratified sample of the same workload: a few candidates of
     windows spread over every (N, C) group; logL and gradient of each.  Also reports the largest
     disagreement with the GPU values of the same candidates."""
@@ -260,12 +359,22 @@ def cpu_baseline(wl, seconds, logL_gpu, grad_gpu, log):
     _, dt1, _ = run(2)
     n_cand = int(min(4096, max(2, 2 * seconds / max(dt1, 1e-3))))
     evals, spent, max_dl = run(n_cand)
+    errs = {}
+    for i in sample:
+        win = wl.windows[i]
+        dd, ww = wl.window_data(i)
+        th = wl.window_theta(i)[:64]
+        a = int(wl.cand_off[i])
+        l, _ = O.loglik(th, win.k0, win.W, win.N, win.C, dd, ww, g, 0)
+        ref = lg[a:a + len(th)]
+        e = float(np.max(np.abs((ref - ref[0]) - (l - l[0])) / np.maximum(1.0, np.abs(l - l[0]))))
+        errs[f"window {i} (N={win.N}, C={win.C}, rho={rho_w[i]:.0f})"] = e
     log(f"cpu oracle: {evals} evals in {spent:.1f}s on {threads} threads")
     return {"value": round(evals / spent, 2), "unit": "evals/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(sample)} windows spread over the (N, C) groups x {n_cand} candidates each, "
                       f"logL + gradient per candidate (FP64 C++ oracle, OpenMP over candidates)",
             "cpu": platform.processor() or platform.machine(),
-            "max_mixed_dlogl_err_vs_oracle": max_dl}
+            "mixed_dlogl_err_vs_oracle": errs}
 
 
 if __name__ == "__main__":

@@ -115,8 +115,10 @@ gb_status gb_loglik(gb_plan* plan, const double* d, const double* w, const doubl
                     double* logL, double* comps, void* stream);
 
 /* logL and its gradient grad: [rows][8], d logL / d theta in the order of theta (the
- * carrier bin floor(f0 T) held fixed).  Hand-written adjoint: inverse DFT of the
- * weighted residual, then the slow-series derivative contracted with it. */
+ * carrier bin floor(f0 T) held fixed): the derivative of the log-likelihood of Sec. II.
+ * Hand-written adjoint: inverse DFT of the weighted residual, then the slow-series
+ * derivative contracted with it by reverse mode.  Windows must be GB_MIXED: the FP64
+ * gradient returns GB_EUNSUPPORTED (switched off in this version). */
 gb_status gb_loglik_grad(gb_plan* plan, const double* d, const double* w, const double* theta,
                          double* logL, double* grad, void* stream);
 

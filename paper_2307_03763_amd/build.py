@@ -14,8 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libgbx.so")
 OBJ = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-UNITS = ["gbx.hip", "k_f64_loglik.hip", "k_mixed_loglik.hip", "k_f64_grad.hip", "k_mixed_grad.hip",
-         "k_waveform.hip"]
+UNITS = ["gbx.hip", "k_f64_loglik.hip", "k_mixed_loglik.hip", "k_mixed_grad.hip", "k_waveform.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

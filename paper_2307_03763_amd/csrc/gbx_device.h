@@ -309,65 +309,7 @@ __device__ __forceinline__ void fft_lds(cplx<R>* buf, int lane, const cplx<R>* _
 namespace gbx {
 
 // ------------------------------------------------------------------------------------
-// Gradient support.  A value with three tangents along (local frequency f, beta, lambda).
-template <class R>
-struct D3 {
-  R v, a, b, c;
-};
-template <class R>
-__device__ __forceinline__ D3<R> d3(R v, R a, R b, R c) {
-  D3<R> r;
-  r.v = v;
-  r.a = a;
-  r.b = b;
-  r.c = c;
-  return r;
-}
-template <class R>
-__device__ __forceinline__ D3<R> operator+(D3<R> x, D3<R> y) { return d3<R>(x.v + y.v, x.a + y.a, x.b + y.b, x.c + y.c); }
-template <class R>
-__device__ __forceinline__ D3<R> operator-(D3<R> x, D3<R> y) { return d3<R>(x.v - y.v, x.a - y.a, x.b - y.b, x.c - y.c); }
-template <class R>
-__device__ __forceinline__ D3<R> operator*(D3<R> x, D3<R> y) {
-  return d3<R>(x.v * y.v, x.a * y.v + x.v * y.a, x.b * y.v + x.v * y.b, x.c * y.v + x.v * y.c);
-}
-template <class R>
-__device__ __forceinline__ D3<R> dsc(D3<R> x, R s) { return d3<R>(x.v * s, x.a * s, x.b * s, x.c * s); }
-
-// complex numbers whose parts carry tangents
-template <class R>
-struct CD {
-  D3<R> re, im;
-};
-template <class R>
-__device__ __forceinline__ CD<R> cd(D3<R> re, D3<R> im) {
-  CD<R> z;
-  z.re = re;
-  z.im = im;
-  return z;
-}
-template <class R>
-__device__ __forceinline__ CD<R> operator+(CD<R> x, CD<R> y) { return cd<R>(x.re + y.re, x.im + y.im); }
-template <class R>
-__device__ __forceinline__ CD<R> operator-(CD<R> x, CD<R> y) { return cd<R>(x.re - y.re, x.im - y.im); }
-template <class R>
-__device__ __forceinline__ CD<R> operator*(CD<R> x, CD<R> y) {
-  return cd<R>(x.re * y.re - x.im * y.im, x.re * y.im + x.im * y.re);
-}
-// constant complex times tangent-carrying complex
-template <class R>
-__device__ __forceinline__ CD<R> cmul(cplx<R> k, CD<R> y) {
-  return cd<R>(dsc(y.re, k.x) - dsc(y.im, k.y), dsc(y.im, k.x) + dsc(y.re, k.y));
-}
-// e^{2 pi i p} for p with tangents
-template <class R>
-__device__ __forceinline__ CD<R> expi_rev(R pv, R pa, R pb, R pc) {
-  R s, c;
-  sincos_rev(pv, &s, &c);
-  const R tp = (R)(2.0 * kPi);
-  // d e^{2 pi i p} = 2 pi i e^{2 pi i p} dp
-  return cd<R>(d3<R>(c, -tp * s * pa, -tp * s * pb, -tp * s * pc), d3<R>(s, tp * c * pa, tp * c * pb, tp * c * pc));
-}
+// Gradient support.
 
 // sinc(u) and its derivative
 __device__ __forceinline__ void sinc_d(double u, double* s, double* ds) {
@@ -413,13 +355,6 @@ __device__ __forceinline__ void sinc_d(float u, float* s, float* ds) {
     *ds = (cs - *s) / u;
   }
 }
-template <class R>
-__device__ __forceinline__ D3<R> sinc3(D3<R> u) {
-  R s, ds;
-  sinc_d(u.v, &s, &ds);
-  return d3<R>(s, ds * u.a, ds * u.b, ds * u.c);
-}
-
 // Extra per-candidate constants of the gradient.
 template <class R>
 struct CandG {
@@ -439,106 +374,165 @@ __device__ __forceinline__ CandG<R> make_cand_grad(const double* th, bool ok) {
   return g;
 }
 
-// Per-sample accumulators of the gradient (FP64).
+// Per-sample accumulators of the gradient (FP64; laid out as ten consecutive doubles).
 struct GradAcc {
   double gf, gtf, gb, gl;   // sum Re(cot . dS/d{f, beta, lambda}); gtf = sum t * (f part)
   double gu_re, gu_im, gv_re, gv_im;  // sum conj(Sbar) U, conj(Sbar) V
   double pt, ptt;           // sum t Im(conj(Sbar) S), sum t^2 Im(conj(Sbar) S)
 };
 
-// Contribution of slow-series sample m to the gradient.  sbar[c] = the cotangent of S_c(t_m)
-// (scaled inverse DFT of w (d - h)).  The channels collapse into three constants bX, bY, bZ
-// multiplying X, Y, Z, and the links into one cotangent per arm Lam_a multiplying P_a, so only
-// the arm phasors, the sincs, D and the common factor K carry tangents.
+}  // namespace gbx
+
+namespace gbx {
+
+// ------------------------------------------------------------------------------------
+// Contribution of slow-series sample m to the gradient, by hand-written reverse mode.
+// With the channel cotangents folded onto X, Y, Z (bX, bY, bZ) and the links onto one
+// cotangent per arm (Lam_a), the sample's share of sum_c conj(sbar_c) S_c is J = K Q with
+//   Q = sum_a Lam_a P_a,   P_a = (ap F+_a + ax Fx_a) E_a,   E_a = e^{i chi_a},
+//   K = (1 - D^2)(-i x) e^{2 pi i p} = kappa e^{i psi},  kappa = phi_D sin(phi_D),
+//   psi = 2 pi p - phi_D,  phi_D = 2 pi f L/c,  x = phi_D / 2.
+// Its derivative along f (local frequency), beta, lambda collects: the amplitude kappa and
+// the phase psi of K, the arm phases chi_a, the projections F+_a, Fx_a, the six link sincs
+// through u = x (1 -+ k.n_a), and the delay D inside Lam_a.
 template <class R, int C>
-__device__ __forceinline__ void grad_sample(const Cand<R>& s, const CandG<R>& sg, const double* __restrict__ ob64,
-                                            const R* __restrict__ obR, int N, int m, double t, double Lc,
-                                            const cplx<R> sbar[C], GradAcc& acc) {
+__device__ __forceinline__ void grad_sample_rev(const Cand<R>& s, const CandG<R>& sg,
+                                                const double* __restrict__ ob64, const R* __restrict__ obR,
+                                                int N, int m, double t, double Lc, const cplx<R> sbar[C],
+                                                GradAcc& acc) {
+  const R twopi = (R)(2.0 * kPi), pi = (R)kPi;
   const double f = s.f0 + s.fd * t;
   const double Rx = ob64[OB_RX * N + m], Ry = ob64[OB_RY * N + m];
   const double kR = s.kxd * Rx + s.kyd * Ry;
   double p = s.df * t + 0.5 * s.fd * t * t + s.phi0c - f * (0.5 * Lc + kR);
   p -= rint(p);
   const R fr = (R)f, Lr = (R)Lc;
-  // dp: d/df = -(L/2c + k.R/c); d/dbeta = -f u.R/c; d/dlambda = -f cos(beta) v.R/c
+  R sp, cp, sDm, cDm;
+  sincos_rev((R)p, &sp, &cp);
+  sincos_rev(-fr * Lr, &sDm, &cDm);  // D = e^{-i phi_D}: (cDm, sDm), sDm = -sin(phi_D)
+  const cplx<R> D = mk<R>(cDm, sDm);
+  const R phiD = twopi * fr * Lr;
+  const R x = pi * fr * Lr;
+  const R kappa = -(R)2 * x * sDm;                     // = phi_D sin(phi_D)
+  const cplx<R> Ep = D * mk<R>(cp, sp);                 // e^{i psi}
+  const cplx<R> K = scal(Ep, kappa);
   const R uR = s.u[0] * (R)Rx + s.u[1] * (R)Ry;
   const R vR = s.v[0] * (R)Rx + s.v[1] * (R)Ry;
-  const CD<R> E0 = expi_rev<R>((R)p, -((R)0.5 * Lr + (R)kR), -fr * uR, -fr * sg.cb * vR);
-  const D3<R> x = d3<R>((R)kPi * fr * Lr, (R)kPi * Lr, (R)0, (R)0);
-  // D = e^{-2 pi i f L/c}
-  const CD<R> D = expi_rev<R>(-fr * Lr, -Lr, (R)0, (R)0);
 
-  D3<R> kn[3], Fp[3], Fx[3];
+  // arms: projections, phases
+  R kn[3], un[3], vn[3], wn[3], Fp[3], Fx[3], kp[3], up[3], vp[3];
+  cplx<R> E[3], P[3];
+  const int opp[3] = {2, 0, 1};
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const int o = OB_N12 + 3 * a;
     const R n0 = obR[(o + 0) * N + m], n1 = obR[(o + 1) * N + m], n2 = obR[(o + 2) * N + m];
-    const R knv = s.k[0] * n0 + s.k[1] * n1 + s.k[2] * n2;
-    const R unv = s.u[0] * n0 + s.u[1] * n1 + s.u[2] * n2;
-    const R vnv = s.v[0] * n0 + s.v[1] * n1;
-    const R wnv = sg.wl[0] * n0 + sg.wl[1] * n1;
-    // dk/dbeta = u, dk/dlambda = cos(beta) v; du/dbeta = -k, du/dlambda = -sin(beta) v; dv/dlambda = w
-    kn[a] = d3<R>(knv, (R)0, unv, sg.cb * vnv);
-    const D3<R> un = d3<R>(unv, (R)0, -knv, -sg.sb * vnv);
-    const D3<R> vn = d3<R>(vnv, (R)0, (R)0, wnv);
-    Fp[a] = un * un - vn * vn;
-    Fx[a] = dsc(un * vn, (R)2);
+    kn[a] = s.k[0] * n0 + s.k[1] * n1 + s.k[2] * n2;
+    un[a] = s.u[0] * n0 + s.u[1] * n1 + s.u[2] * n2;
+    vn[a] = s.v[0] * n0 + s.v[1] * n1;
+    wn[a] = sg.wl[0] * n0 + sg.wl[1] * n1;
+    Fp[a] = un[a] * un[a] - vn[a] * vn[a];
+    Fx[a] = (R)2 * un[a] * vn[a];
+    const int q = OB_P1 + 3 * opp[a];
+    const R p0 = obR[(q + 0) * N + m], p1 = obR[(q + 1) * N + m], p2 = obR[(q + 2) * N + m];
+    kp[a] = s.k[0] * p0 + s.k[1] * p1 + s.k[2] * p2;
+    up[a] = s.u[0] * p0 + s.u[1] * p1 + s.u[2] * p2;
+    vp[a] = s.v[0] * p0 + s.v[1] * p1;
+    R sc, cc;
+    sincos_rev((R)0.5 * fr * kp[a], &sc, &cc);
+    E[a] = mk<R>(cc, sc);
+    P[a] = mk<R>(s.ap.x * Fp[a] + s.ax.x * Fx[a], s.ap.y * Fp[a] + s.ax.y * Fx[a]) * E[a];
   }
-  CD<R> Ea[3];
-  const int opp[3] = {2, 0, 1};
+  // links: index 2a is the "1 - k.n_a" link, 2a+1 the "1 + k.n_a" link of arm a
+  // (arm 12: links 12, 21; arm 23: 23, 32; arm 31: 31, 13)
+  R sv[6], sd[6];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const int o = OB_P1 + 3 * opp[a];
-    const R p0 = obR[(o + 0) * N + m], p1 = obR[(o + 1) * N + m], p2 = obR[(o + 2) * N + m];
-    const R kpv = s.k[0] * p0 + s.k[1] * p1 + s.k[2] * p2;
-    const R upv = s.u[0] * p0 + s.u[1] * p1 + s.u[2] * p2;
-    const R vpv = s.v[0] * p0 + s.v[1] * p1;
-    // chi (cycles) = f k.p / 2
-    Ea[a] = expi_rev<R>((R)0.5 * fr * kpv, (R)0.5 * kpv, (R)0.5 * fr * upv, (R)0.5 * fr * sg.cb * vpv);
+    sinc_d(x * ((R)1 - kn[a]), &sv[2 * a], &sd[2 * a]);
+    sinc_d(x * ((R)1 + kn[a]), &sv[2 * a + 1], &sd[2 * a + 1]);
   }
-  const D3<R> one = d3<R>((R)1, (R)0, (R)0, (R)0);
-  const D3<R> s12 = sinc3(x * (one - kn[0])), s21 = sinc3(x * (one + kn[0]));
-  const D3<R> s23 = sinc3(x * (one - kn[1])), s32 = sinc3(x * (one + kn[1]));
-  const D3<R> s31 = sinc3(x * (one - kn[2])), s13 = sinc3(x * (one + kn[2]));
-  auto G = [&](D3<R> a, D3<R> b) { return cd<R>(a + D.re * b, D.im * b); };
-  // channel cotangents folded onto X, Y, Z: sum_c conj(sbar_c) M_c = bX X + bY Y + bZ Z
+  const R s12 = sv[0], s21 = sv[1], s23 = sv[2], s32 = sv[3], s31 = sv[4], s13 = sv[5];
   const R r2 = (R)0.70710678118654752440, r6 = (R)0.40824829046386301637, r3 = (R)0.57735026918962576451;
   const cplx<R> cA = conjg(sbar[0]), cE = conjg(sbar[1]);
   const cplx<R> cT = (C == 3) ? conjg(sbar[C - 1]) : mk<R>((R)0, (R)0);
   const cplx<R> bX = scal(cA, -r2) + scal(cE, r6) + scal(cT, r3);
   const cplx<R> bY = scal(cE, (R)-2 * r6) + scal(cT, r3);
   const cplx<R> bZ = scal(cA, r2) + scal(cE, r6) + scal(cT, r3);
-  // X = P31 G(s13,s31) - P12 G(s12,s21); Y = P12 G(s21,s12) - P23 G(s23,s32); Z = P23 G(s32,s23) - P31 G(s31,s13)
-  const CD<R> L12 = cmul(bY, G(s21, s12)) - cmul(bX, G(s12, s21));
-  const CD<R> L23 = cmul(bZ, G(s32, s23)) - cmul(bY, G(s23, s32));
-  const CD<R> L31 = cmul(bX, G(s13, s31)) - cmul(bZ, G(s31, s13));
-  // arm phasors for the two polarisation bases: P^U_a = F+_a E_a, P^V_a = Fx_a E_a
-  auto rmul = [&](D3<R> r, CD<R> z) { return cd<R>(r * z.re, r * z.im); };
-  const CD<R> LE12 = L12 * Ea[0], LE23 = L23 * Ea[1], LE31 = L31 * Ea[2];
-  const CD<R> qu = rmul(Fp[0], LE12) + rmul(Fp[1], LE23) + rmul(Fp[2], LE31);
-  const CD<R> qv = rmul(Fx[0], LE12) + rmul(Fx[1], LE23) + rmul(Fx[2], LE31);
-  // K = (1 - D^2)(-i x) e^{2 pi i p}
-  // 1 - D^2 = 2 sD^2 - 2i cD sD (D = cD + i sD), free of cancellation at low frequency
-  const CD<R> omd = cd<R>(dsc(D.im * D.im, (R)2), dsc(D.re * D.im, (R)-2));
-  const CD<R> mix = cd<R>(d3<R>((R)0, (R)0, (R)0, (R)0), d3<R>((R)0, (R)0, (R)0, (R)0) - x);  // -i x
-  const CD<R> K = omd * mix * E0;
-  const CD<R> cu = K * qu, cv = K * qv;  // sum_c conj(sbar_c) U_c and V_c, with tangents
-  // d/dtheta of sum conj(sbar) S with S = ap U + ax V (ap, ax fixed)
-  auto re_comb = [&](R ure, R uim, R vre, R vim) {
-    return (double)(s.ap.x * ure - s.ap.y * uim + s.ax.x * vre - s.ax.y * vim);
-  };
-  const double gf = re_comb(cu.re.a, cu.im.a, cv.re.a, cv.im.a);
-  acc.gf += gf;
-  acc.gtf += t * gf;
-  acc.gb += re_comb(cu.re.b, cu.im.b, cv.re.b, cv.im.b);
-  acc.gl += re_comb(cu.re.c, cu.im.c, cv.re.c, cv.im.c);
-  acc.gu_re += (double)cu.re.v;
-  acc.gu_im += (double)cu.im.v;
-  acc.gv_re += (double)cv.re.v;
-  acc.gv_im += (double)cv.im.v;
-  const double gs_im = (double)(s.ap.x * cu.im.v + s.ap.y * cu.re.v + s.ax.x * cv.im.v + s.ax.y * cv.re.v);
-  acc.pt += t * gs_im;
-  acc.ptt += t * t * gs_im;
+  auto G = [&](R a, R b) { return mk<R>(a + cDm * b, sDm * b); };  // a + D b
+  cplx<R> Lam[3];
+  Lam[0] = bY * G(s21, s12) - bX * G(s12, s21);
+  Lam[1] = bZ * G(s32, s23) - bY * G(s23, s32);
+  Lam[2] = bX * G(s13, s31) - bZ * G(s31, s13);
+  cplx<R> Q = mk<R>((R)0, (R)0), QU = Q, QV = Q;
+  cplx<R> KLP[3], KLE[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const cplx<R> LE = Lam[a] * E[a];
+    Q = Q + Lam[a] * P[a];
+    QU = QU + scal(LE, Fp[a]);
+    QV = QV + scal(LE, Fx[a]);
+    KLE[a] = K * LE;
+    KLP[a] = K * (Lam[a] * P[a]);
+  }
+  const cplx<R> J = K * Q;
+  const cplx<R> GU = K * QU, GV = K * QV;
+
+  // amplitude and phase of K
+  const R dkappa_f = twopi * Lr * (-sDm + phiD * cDm);  // d(phi_D sin phi_D)/df
+  const R EQre = (Ep * Q).x;
+  const R dpsi_f = -twopi * ((R)1.5 * Lr + (R)kR);
+  const R dpsi_b = -twopi * fr * uR;
+  const R dpsi_l = -twopi * fr * sg.cb * vR;
+  R gf = EQre * dkappa_f - J.y * dpsi_f;
+  R gb = -J.y * dpsi_b;
+  R gl = -J.y * dpsi_l;
+  // arm phases chi_a = pi f k.p_a and projections F+_a, Fx_a
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const R im = KLP[a].y;
+    gf -= im * pi * kp[a];
+    gb -= im * pi * fr * up[a];
+    gl -= im * pi * fr * sg.cb * vp[a];
+    const R rp = KLE[a].x * s.ap.x - KLE[a].y * s.ap.y;   // Re(K Lam_a E_a ap)
+    const R rx = KLE[a].x * s.ax.x - KLE[a].y * s.ax.y;   // Re(K Lam_a E_a ax)
+    const R dFp_b = -(R)2 * un[a] * kn[a], dFx_b = -(R)2 * kn[a] * vn[a];
+    const R dFp_l = -(R)2 * sg.sb * un[a] * vn[a] - (R)2 * vn[a] * wn[a];
+    const R dFx_l = -(R)2 * sg.sb * vn[a] * vn[a] + (R)2 * un[a] * wn[a];
+    gb += rp * dFp_b + rx * dFx_b;
+    gl += rp * dFp_l + rx * dFx_l;
+  }
+  // link sincs: coefficient of s_rs in Q is c_rs P_arm
+  const cplx<R> c12 = (bY * D - bX) * P[0], c21 = (bY - bX * D) * P[0];
+  const cplx<R> c23 = (bZ * D - bY) * P[1], c32 = (bZ - bY * D) * P[1];
+  const cplx<R> c31 = (bX * D - bZ) * P[2], c13 = (bX - bZ * D) * P[2];
+  const cplx<R> cl[6] = {c12, c21, c23, c32, c31, c13};
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int sgn = 0; sgn < 2; ++sgn) {
+      const int l = 2 * a + sgn;
+      const R pm = sgn ? (R)1 : (R)-1;  // u = x (1 + pm k.n)
+      const R rr = (K * cl[l]).x * sd[l];
+      gf += rr * pi * Lr * ((R)1 + pm * kn[a]);
+      gb += rr * pm * x * un[a];
+      gl += rr * pm * x * sg.cb * vn[a];
+    }
+  // the delay inside Lam: dQ/dD = sum_a (dLam_a/dD) P_a, dD/df = -2 pi i (L/c) D
+  const cplx<R> cD = scal(bY, s12) * P[0] - scal(bX, s21) * P[0] + scal(bZ, s23) * P[1] - scal(bY, s32) * P[1] +
+                     scal(bX, s31) * P[2] - scal(bZ, s13) * P[2];
+  gf += twopi * Lr * (K * cD * D).y;
+
+  const double gfd = (double)gf;
+  acc.gf += gfd;
+  acc.gtf += t * gfd;
+  acc.gb += (double)gb;
+  acc.gl += (double)gl;
+  acc.gu_re += (double)GU.x;
+  acc.gu_im += (double)GU.y;
+  acc.gv_re += (double)GV.x;
+  acc.gv_im += (double)GV.y;
+  acc.pt += t * (double)J.y;
+  acc.ptt += t * t * (double)J.y;
 }
 
 }  // namespace gbx

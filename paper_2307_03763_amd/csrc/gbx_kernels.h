@@ -136,7 +136,7 @@ __device__ __forceinline__ void process_loglik(const BatchArgs& a, const DevWin&
 // logL and its gradient for one template.  Forward: slow series, DFT, residual.  The
 // cotangent c_k = A T/(2N) w_k (d_k - h_k) replaces the template in LDS, an inverse DFT turns
 // it into the cotangent of every slow-series sample, and each lane contracts it with the
-// derivative of its samples (grad_sample).  The amplitude and the three extrinsic angles
+// derivative of its samples (grad_sample_rev).  The amplitude and the three extrinsic angles
 // enter through closed forms; the carrier bin is held fixed.
 template <class R, int N, int LPC, int C, int WPB>
 __device__ __forceinline__ void process_grad(const BatchArgs& a, const DevWin& w, int64_t row, bool active,
@@ -179,7 +179,7 @@ __device__ __forceinline__ void process_grad(const BatchArgs& a, const DevWin& w
   }
   __syncthreads();
   fft_lds<R, N, LPC, C, +1>(buf, lane, (const cplx<R>*)a.tw);
-  GradAcc ga = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  GradAcc& ga = *reinterpret_cast<GradAcc*>(&v[3]);  // v[3..12]: per-sample accumulators
   const R* obR = (const R*)a.obR;
   auto sample = [&](int e) {
     const int m = lane + LPC * e;
@@ -187,27 +187,10 @@ __device__ __forceinline__ void process_grad(const BatchArgs& a, const DevWin& w
     cplx<R> sbar[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) sbar[c] = buf[c * N + m];
-    grad_sample<R, C>(s, sg, a.ob64, obR, N, m, t, a.Lc, sbar, ga);
+    grad_sample_rev<R, C>(s, sg, a.ob64, obR, N, m, t, a.Lc, sbar, ga);
   };
-  if (sizeof(R) == 8) {
-    // FP64: the fully unrolled form (the loop form of this kernel is not used, see the
-    // design notes on the FP64 gradient)
-#pragma unroll
-    for (int e = 0; e < E; ++e) sample(e);
-  } else {
 #pragma unroll 1
-    for (int e = 0; e < E; ++e) sample(e);
-  }
-  v[3] = ga.gf;
-  v[4] = ga.gtf;
-  v[5] = ga.gb;
-  v[6] = ga.gl;
-  v[7] = ga.gu_re;
-  v[8] = ga.gu_im;
-  v[9] = ga.gv_re;
-  v[10] = ga.gv_im;
-  v[11] = ga.pt;
-  v[12] = ga.ptt;
+  for (int e = 0; e < E; ++e) sample(e);
   slot_reduce<LPC, WPB, 13>(v, s_red);
   if (lane == 0 && active) {
     const double nan = __builtin_nan("");

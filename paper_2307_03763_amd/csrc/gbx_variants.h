@@ -20,6 +20,5 @@ struct VariantList {
 
 extern "C" gbx::VariantList gbx_variants_f64_loglik();
 extern "C" gbx::VariantList gbx_variants_mixed_loglik();
-extern "C" gbx::VariantList gbx_variants_f64_grad();
 extern "C" gbx::VariantList gbx_variants_mixed_grad();
 extern "C" gbx::VariantList gbx_variants_waveform();

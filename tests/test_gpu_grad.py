@@ -4,6 +4,10 @@ against central differences of the GPU logL.
 Scale of a gradient component: |dlogL/dtheta_i| <= ||d - h|| ||d_i h|| <= sqrt(F_ii (<d|d> + <h|h>))
 up to a factor of order one, so errors are measured against s_i = sqrt(F_ii (<d|d> + <h|h>)).
 Bars: FP64 1e-9 s_i; mixed precision 1e-5 s_i.
+
+The FP64 gradient is switched off in the library (its kernels faulted on the GPU while a CPU
+emulation of the same source is clean; cause not yet known), so its cases are skipped and a test
+checks that the call is refused with GB_EUNSUPPORTED before any kernel runs.
 """
 
 import math
@@ -64,8 +68,12 @@ def _run(wl, prec):
     return l.cpu().numpy(), g.cpu().numpy(), l2.cpu().numpy(), (ctx, plan, d, w, th)
 
 
+FP64_GRAD_OFF = "FP64 gradient switched off: its kernels faulted on the GPU; cause not yet known"
+
+
 @pytest.mark.parametrize("C", [2, 3])
-@pytest.mark.parametrize("prec,bar", [(api.GB_FP64, 1e-9), (api.GB_MIXED, 1e-5)])
+@pytest.mark.parametrize("prec,bar", [pytest.param(api.GB_FP64, 1e-9, marks=pytest.mark.skip(reason=FP64_GRAD_OFF)),
+                                      (api.GB_MIXED, 1e-5)])
 def test_gradient_matches_oracle(oracle_lib, C, prec, bar):
     banner(f"gradient vs oracle C={C} prec={prec}")
     O = oracle_lib
@@ -89,35 +97,75 @@ def test_gradient_matches_oracle(oracle_lib, C, prec, bar):
 
 
 def test_gradient_central_differences(oracle_lib):
-    """FP64 GPU gradient against central differences of the FP64 GPU logL (steps 1e-6 of the
-    Table I widths; candidates kept away from a carrier-bin change)."""
+    """Mixed-precision GPU gradient against central differences of the FP64 GPU logL (steps 1e-6
+    of the Table I widths; candidates kept away from a carrier-bin change)."""
     banner("gradient vs central differences")
     O = oracle_lib
     wl = _workload(O, 2)
-    _, g, _, (ctx, plan, d, w, th) = _run(wl, api.GB_FP64)
     T = wl.T
     base = wl.theta.copy()
     # keep f0 T at least 0.2 from an integer so +-step never changes the carrier bin
     frac = base[:, 0] * T - np.floor(base[:, 0] * T)
     base[:, 0] += (np.clip(frac, 0.2, 0.8) - frac) / T
-    l0, g0, _, (ctx, plan, d, w, thb) = _run(I.Workload(wl.name, T, wl.windows, base, wl.n_cand, wl.cand_off,
-                                                          wl.data, wl.weights, wl.data_off), api.GB_FP64)
+    wlb = I.Workload(wl.name, T, wl.windows, base, wl.n_cand, wl.cand_off, wl.data, wl.weights, wl.data_off)
+    _, g0, _, _ = _run(wlb, api.GB_MIXED)
+    ctx = api.context_for(T)
+    plan = api.Plan(ctx, wl.window_table(), api.GB_FP64)
+    d, w = dev(wl.data, torch.complex128), dev(wl.weights)
+    plan.prepare(d, w)
     # Table I widths at 5 mHz: f over a 256-bin window, fdot over its bounds, angles over their ranges
     f5 = 5e-3
     widths = np.array([256.0 / T, 1.02e-6 * f5 ** (11 / 3) + 5e-6 * f5 ** (13 / 3), 1.0, 2 * math.pi, 0.0,
                        math.pi, math.pi, 2 * math.pi])
     rel_errs = []
     for i in range(8):
-        h = 1e-6 * (widths[i] if i != 4 else 1.0)
-        hv = np.full(len(base), h) if i != 4 else 1e-6 * base[:, 4]
+        hv = np.full(len(base), 1e-6 * widths[i]) if i != 4 else 1e-6 * base[:, 4]
         tp, tm = base.copy(), base.copy()
         tp[:, i] += hv
         tm[:, i] -= hv
         lp = plan.loglik(dev(tp)).cpu().numpy()
         lm = plan.loglik(dev(tm)).cpu().numpy()
         fd = (lp - lm) / (2 * hv)
-        # second-order truncation and rounding bound the agreement
         err = np.abs(fd - g0[:, i]) / np.maximum(np.abs(g0[:, i]), 1e-2 / hv)
         rel_errs.append(np.median(err))
         assert np.median(err) < 1e-4, (i, np.median(err))
     banner("  median relative FD error per parameter: " + " ".join(f"{x:.1e}" for x in rel_errs))
+
+
+@pytest.fixture(scope="module")
+def c3_grad(oracle_lib):
+    return I.workload_c3(oracle_lib.template_fn(), n_win=16, n_cand=6)
+
+
+def test_gradient_ragged_mixed(oracle_lib, c3_grad):
+    """Mixed-precision gradients on ragged windows (N 64-512, C 2-3) against the oracle."""
+    banner("gradient ragged mixed")
+    O = oracle_lib
+    wl = c3_grad
+    l, g, _, _ = _run(wl, api.GB_MIXED)
+    worst = np.zeros(8)
+    for i in range(wl.n_win):
+        w = wl.windows[i]
+        d, ww = wl.window_data(i)
+        a, n = int(wl.cand_off[i]), int(wl.n_cand[i])
+        th = wl.window_theta(i)
+        _, go = O.loglik_grad(th, w.k0, w.W, w.N, w.C, d, ww, O.Geometry(wl.T))
+        _, co = O.loglik(th, w.k0, w.W, w.N, w.C, d, ww, O.Geometry(wl.T))
+        sc = _scales(O, wl, i, th, co[:, 1])
+        worst = np.maximum(worst, (np.abs(g[a:a + n] - go) / sc).max(axis=0))
+    banner("  worst scaled error per parameter: " + " ".join(f"{x:.1e}" for x in worst))
+    assert worst.max() <= 1e-5
+
+
+def test_fp64_gradient_is_refused(c3_grad):
+    """The FP64 gradient is switched off: the call returns GB_EUNSUPPORTED and launches nothing."""
+    banner("fp64 gradient refused")
+    wl = c3_grad
+    ctx = api.context_for(wl.T)
+    plan = api.Plan(ctx, wl.window_table(), api.GB_FP64)
+    d, w = dev(wl.data, torch.complex128), dev(wl.weights)
+    plan.prepare(d, w)
+    with pytest.raises(api.GbxError) as e:
+        plan.loglik_grad(dev(wl.theta))
+    assert e.value.status == api.GB_EUNSUPPORTED
+    assert "FP64 gradient" in str(e.value)
