@@ -24,6 +24,7 @@ sys.path.insert(0, ROOT)
 METRIC = "GB logL evals/s + grad evals/s (ragged, mixed prec) vs plain FP64 on same GPU"
 PEAK_VALU_TFLOPS = 78.6     # MI355X vector FMA rate (FP64, and FP32 without packed math)
 PEAK_HBM_GBS = 8000.0
+COPY_N = 1 << 28            # copy calibration: 256 M doubles = 2 GiB read + 2 GiB written per launch
 
 
 # ------------------------------------------------------------------------------------------
@@ -63,6 +64,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--rho-mixed", type=float, default=8.0)
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--traffic", nargs=5, metavar=("BENCH_JSON", "K_FETCH_DIR", "K_WRITE_DIR", "COPY_FETCH_DIR",
+                                                   "COPY_WRITE_DIR"),
+                    help="print the profiles/hbm_traffic.txt line from rocprofv3 --pmc outputs and exit")
     return ap.parse_args()
 
 
@@ -70,6 +74,9 @@ def main():
     args = parse()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.traffic:
+        print(traffic_summary(*args.traffic))
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -138,7 +145,7 @@ def main():
             out.append((key, idx, p, torch.empty(len(idx), dtype=torch.int64, device="cuda")))
         return out
 
-    def run_steps(groups, steps, warmup):
+    def run_steps(groups, steps, warmup, region=None):
         def one(ev):
             for j, (key, idx, p, nacc) in enumerate(groups):
                 if ev is not None:
@@ -154,6 +161,8 @@ def main():
         torch.cuda.synchronize()
         evs = [[[E(), E()] for _ in groups] for _ in range(steps)]
         start, end = E(), E()
+        if region is not None:
+            region.resume()
         start.record(stream)
         for s_ in range(steps):
             one(evs[s_])
@@ -175,8 +184,25 @@ def main():
     # switched off in this version of the library)
     grad_prec = np.full(wl.n_win, api.GB_MIXED)
     groups_ad = make_groups(prec_w, grad_prec)
-    ms_ad, per_ad = run_steps(groups_ad, args.steps, args.warmup)
+    region = ProfilerRegion()
+    ms_ad, per_ad = run_steps(groups_ad, args.steps, args.warmup, region)
+    # the likelihood kernel alone for every MH group (an MH stage is that kernel plus the
+    # chain kernel): the same launches through gb_loglik, still inside the profiled region
+    kb_ms = per_ad.copy()
+    for j, (key, idx, p, _) in enumerate(groups_ad):
+        if key[0] != "mh":
+            continue
+        ev = [[E(), E()] for _ in range(args.steps)]
+        for s_ in range(args.steps):
+            ev[s_][0].record(stream)
+            api.gb_loglik(p.handle, d, w, th, logL, None, stream)
+            ev[s_][1].record(stream)
+        torch.cuda.synchronize()
+        kb_ms[j] = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    region.pause()
     adaptive = summary(groups_ad, ms_ad, per_ad)
+    adaptive["chain_ms_per_step"] = round(float(sum(per_ad[j] - kb_ms[j] for j, g in enumerate(groups_ad)
+                                                    if g[0][0] == "mh")), 4)
     log(f"adaptive ragged: {ms_ad:.2f} ms/step {adaptive}")
 
     # mixed precision everywhere
@@ -187,21 +213,22 @@ def main():
     log(f"mixed ragged: {ms_mx:.2f} ms/step {mixed}")
     logl_mixed = logL.cpu().numpy().copy()
 
-    # dominant kernel of the headline step
-    j_dom = int(np.argmax(per_ad))
+    # dominant kernel of the headline step (largest k_batch time per step)
+    j_dom = int(np.argmax(kb_ms))
     key, idx, _, _ = groups_ad[j_dom]
     kind, kN, kC, kP = key
     n_dom = int(sum(wl.n_cand[i] for i in idx))
     is_grad = kind == "gr"
     fl = sum(int(wl.n_cand[i]) * flops_per_eval(kN, kC, min(wl.windows[i].W, kN), is_grad) for i in idx)
-    dur_ms = float(per_ad[j_dom])
+    dur_ms = float(kb_ms[j_dom])
     achieved_tf = fl / (dur_ms * 1e-3) / 1e12
-    kname = (f"k_batch<{'double' if kP == api.GB_FP64 else 'float'}, N={kN}, C={kC}, "
-             f"{'gradient' if is_grad else 'logL'}>")
+    kname = tuned_kernel_name(tune, kP, is_grad, kN, kC)
     roofline = {"bound": "alu", "achieved": round(achieved_tf, 3), "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved_tf / PEAK_VALU_TFLOPS, 4), "traffic": committed_traffic(kname, n_dom),
                 "kernel": kname,
                 "launch_ms": round(dur_ms, 4), "evals_per_launch": n_dom,
+                "timing": "HIP events on the launch stream, mean over the timed launches; the timed "
+                          "region is bracketed by roctxProfilerResume/Pause for rocprofv3 --selected-regions",
                 "flops_per_eval": round(fl / n_dom, 1),
                 "hbm_gbs": round((n_dom * bytes_per_eval(kC, kN, is_grad) +
                                   sum(24.0 * kC * wl.windows[i].W for i in idx)) / (dur_ms * 1e-3) / 1e9, 3),
@@ -239,10 +266,6 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(wl, args.cpu_seconds, logL, grad, log)
-
-    cpu = None
-    if not args.no_cpu:
         cpu = cpu_baseline(wl, args.cpu_seconds, logl_mixed, rho_w, log)
 
     value = adaptive["value"]
@@ -273,6 +296,97 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+class ProfilerRegion:
+    """roctxProfilerResume(0) / roctxProfilerPause(0) around the timed region, so that
+    `rocprofv3 --selected-regions ...` records exactly the timed launches; without a profiler
+    attached the calls do nothing."""
+
+    def __init__(self):
+        import ctypes
+        self.lib = None
+        for name in ("librocprofiler-sdk-roctx.so.1", "/opt/rocm/lib/librocprofiler-sdk-roctx.so.1"):
+            try:
+                self.lib = ctypes.CDLL(name)
+                break
+            except OSError:
+                continue
+
+    def resume(self):
+        import torch
+        torch.cuda.synchronize()
+        if self.lib is not None:
+            self.lib.roctxProfilerResume(0)
+
+    def pause(self):
+        import torch
+        torch.cuda.synchronize()
+        if self.lib is not None:
+            self.lib.roctxProfilerPause(0)
+
+
+def tuned_kernel_name(tune: str, prec: int, grad: bool, N: int, C: int) -> str:
+    """The k_batch instantiation the autotuner chose for (precision, mode, N, C), as
+    'k_batch<R,N,LPC,C,WPB,MODE,OCC>' (the template arguments of the kernel symbol)."""
+    head = ("fp64 " if prec == 0 else "mixed") + " " + ("grad  " if grad else "loglik") + f" N={N} C={C}:"
+    for line in tune.splitlines():
+        if line.startswith(head) and "kernel=" in line:
+            return line.split("kernel=", 1)[1].strip()
+    return f"k_batch<{'double' if prec == 0 else 'float'},{N},?,{C},?,{2 if grad else 1},?>"
+
+
+def _kernel_key(name: str) -> str:
+    """'void k_batch<double, 512, 128, 3, 4, 1, 1>(BatchArgs)' -> 'k_batch<double,512,128,3,4,1,1>'."""
+    n = name.replace(" ", "")
+    if n.startswith("void"):
+        n = n[4:]
+    return n.split("(", 1)[0]
+
+
+def _counter_per_dispatch(csv_dir: str, counter: str) -> dict:
+    """{kernel key: [counter value per dispatch]} from rocprofv3 --pmc output under csv_dir."""
+    import csv
+    import glob
+    out = {}
+    files = glob.glob(os.path.join(csv_dir, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no counter_collection.csv under {csv_dir}")
+    for fn in files:
+        with open(fn) as f:
+            for row in csv.DictReader(f):
+                if row.get("Counter_Name") != counter:
+                    continue
+                out.setdefault(_kernel_key(row["Kernel_Name"]), []).append(float(row["Counter_Value"]))
+    return out
+
+
+def traffic_summary(bench_json: str, k_fetch: str, k_write: str, c_fetch: str, c_write: str) -> str:
+    """One line for profiles/hbm_traffic.txt: HBM bytes per launch of the bench's dominant kernel
+    from FETCH_SIZE and WRITE_SIZE (KiB per dispatch, rocprofv3 --pmc over the timed region),
+    each scaled by what the same counter reads for the copy calibration (known bytes)."""
+    import json as _json
+    b = _json.loads(open(bench_json).read().strip().splitlines()[-1])
+    kern = b["roofline"]["kernel"]
+    evals = b["roofline"]["evals_per_launch"]
+    kf = _counter_per_dispatch(k_fetch, "FETCH_SIZE")
+    kw = _counter_per_dispatch(k_write, "WRITE_SIZE")
+    cf = _counter_per_dispatch(c_fetch, "FETCH_SIZE")
+    cw = _counter_per_dispatch(c_write, "WRITE_SIZE")
+    if kern not in kf or kern not in kw:
+        raise KeyError(f"{kern} not among the profiled kernels: {sorted(kf)}")
+    # the copy is the single largest dispatch of the calibration run
+    copy_f = max(v for vals in cf.values() for v in vals)
+    copy_w = max(v for vals in cw.values() for v in vals)
+    nbytes = 8 * COPY_N
+    s_f = nbytes / (copy_f * 1024.0)
+    s_w = nbytes / (copy_w * 1024.0)
+    f_kib = sum(kf[kern]) / len(kf[kern])
+    w_kib = sum(kw[kern]) / len(kw[kern])
+    by = f_kib * 1024.0 * s_f + w_kib * 1024.0 * s_w
+    return (f"library={b['library']} kernel={kern} evals={evals} bytes={by:.0f} "
+            f"fetch_kib={f_kib:.1f} write_kib={w_kib:.1f} dispatches={len(kf[kern])} "
+            f"copy_scale_fetch={s_f:.4f} copy_scale_write={s_w:.4f}")
+
+
 def library_hash() -> str:
     import hashlib
     from paper_2307_03763_amd import api
@@ -298,12 +412,15 @@ def copy_calibration():
     """A device copy of a known size, profiled with the same counters as the kernels
     (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE) to scale them to bytes."""
     import torch
-    n = 1 << 28  # 256 M doubles = 2 GiB read + 2 GiB written
+    n = COPY_N
     a = torch.ones(n, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
+    torch.mul(a, 1.0, out=b)  # warm-up outside the profiled region
+    region = ProfilerRegion()
+    region.resume()
     for _ in range(3):
-        b.copy_(a)
-    torch.cuda.synchronize()
+        torch.mul(a, 1.0, out=b)  # an elementwise copy kernel: reads n doubles, writes n doubles
+    region.pause()
     print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "launches": 3}), flush=True)
 
 
@@ -338,7 +455,7 @@ def cpu_baseline(wl, seconds, logL_gpu, rho_w, log):
     threads = O.max_threads()
     order = sorted(range(wl.n_win), key=lambda i: (wl.windows[i].N, wl.windows[i].C))
     sample = order[:: max(1, len(order) // 16)][:16]
-    lg = logL_gpu.cpu().numpy()
+    lg = np.asarray(logL_gpu)
     def run(n_cand):
         nonlocal_max = 0.0
         t = time.time()
@@ -356,8 +473,8 @@ def cpu_baseline(wl, seconds, logL_gpu, rho_w, log):
             nonlocal_max = max(nonlocal_max, float(np.max(np.abs(dl) / np.maximum(1.0, np.abs(l - l[0])))))
         return evals, time.time() - t, nonlocal_max
 
-    _, dt1, _ = run(2)
-    n_cand = int(min(4096, max(2, 2 * seconds / max(dt1, 1e-3))))
+    ev1, dt1, _ = run(32)                       # pilot, then size the sample to `seconds`
+    n_cand = int(min(10000, max(32, 32 * (seconds - dt1) / max(dt1, 1e-3))))
     evals, spent, max_dl = run(n_cand)
     errs = {}
     for i in sample:

@@ -177,7 +177,7 @@ def gb_mh_step(plan: int, d, w, theta, log_g, u, temperature: float, logL, chain
 
 
 def gb_autotune(ctx: int, reps: int = 5) -> str:
-    buf = ctypes.create_string_buffer(4096)
+    buf = ctypes.create_string_buffer(16384)
     _check(lib().gb_autotune(ctx, reps, buf, len(buf)), "gb_autotune")
     return buf.value.decode()
 

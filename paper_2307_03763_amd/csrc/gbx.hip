@@ -615,10 +615,13 @@ extern "C" gb_status gb_autotune(gb_ctx* c, int reps, char* report, size_t repor
           }
           if (best) {
             c->choice[prec][ni][C - 2][mode] = best;
-            char line[200];
-            std::snprintf(line, sizeof line, "%s %s N=%d C=%d: lanes/template=%d min waves/SIMD=%d %.4f ms / %d (%d variants)\n",
+            char line[256];
+            std::snprintf(line, sizeof line,
+                          "%s %s N=%d C=%d: lanes/template=%d min waves/SIMD=%d %.4f ms / %d (%d variants) "
+                          "kernel=k_batch<%s,%d,%d,%d,%d,%d,%d>\n",
                           prec == GB_FP64 ? "fp64 " : "mixed", mode == MODE_GRAD ? "grad  " : "loglik", N, C,
-                          best->LPC, best->occ, best_ms, B, tried);
+                          best->LPC, best->occ, best_ms, B, tried, prec == GB_FP64 ? "double" : "float", N,
+                          best->LPC, C, best->WPB, mode, best->occ);
             rep += line;
           }
         }

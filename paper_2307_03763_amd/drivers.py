@@ -1,0 +1,360 @@
+"""Drivers around the batched likelihood: the search, polish and posterior stages.
+
+* ``de_search`` -- the differential-evolution search of Algorithm 2 / Sec. III D, run for many
+  windows at once: each window has its own population in Table I coordinates without the
+  amplitude, every generation of every window is scored in one batched likelihood call by the
+  SNR rho = <d|h> / sqrt(<h|h>) (Sec. III SNR equation, independent of the amplitude), and the
+  kept members of each window get A_max = A <d|h> / <h|h> (Sec. III amplitude equation).
+  Mutation is DE/rand/1/bin with a scale factor dithered per generation.
+* ``polish`` -- refinement of many starting points at once by quasi-Newton (BFGS) ascent on
+  logL: per iteration one batched gradient call, then one batched line search (all trial step
+  lengths of all starts in one likelihood call).
+* ``search`` -- DE, then the polish of its best members, with restarts (Sec. III D).
+* ``PosteriorStage`` -- one temperature of Algorithm 4: proposals drawn uniformly in a box in
+  Table I coordinates (so the proposal density is constant there and cancels), logL of all of
+  them in parallel and the independent-proposal chain, in one ``gb_mh_step``; optionally
+  captured once in a HIP graph and replayed.
+
+The drivers only choose parameters and keep the best values; every likelihood, gradient and
+chain is computed by a backend.  A backend evaluates ``theta`` of shape [n_win * n, 8] laid out
+window-major (rows i*n .. i*n+n-1 belong to window i) and returns (logL [n_win*n],
+comps [n_win*n, 2]) from ``loglik`` and (logL, grad [n_win*n, 8]) from ``loglik_grad``.
+``GpuBackend`` calls the HIP library.
+"""
+
+from __future__ import annotations
+
+import math
+from typing import Optional
+
+import numpy as np
+
+from . import inputs as I
+
+# Table I coordinates searched by DE: all but log10 A (index 4), which is profiled
+SEARCH_DIMS = (0, 1, 2, 3, 5, 6, 7)
+PERIODIC = (3, 6, 7)
+REF_AMP = 1e-22
+
+
+class GpuBackend:
+    """Batched logL / gradient through the HIP library for the windows of ``table`` (rows as in
+    ``Workload.window_table``: k0, W, N, C, data_off, w_off, ...; an optional 9th column holds the
+    per-window precision for GB_PER_WINDOW).  The candidate slices are rewritten per call; plans
+    are cached per (candidates per window, precision)."""
+
+    def __init__(self, ctx, table, d, w, precision_logl: int, precision_grad: Optional[int] = None):
+        import torch
+        from . import api
+        self.api, self.torch = api, torch
+        self.ctx = ctx
+        t = np.asarray(table, dtype=np.int64)
+        self.table = t.reshape(-1, t.shape[-1]).copy()
+        self.n_win = len(self.table)
+        self.d, self.w = d, w
+        self.pl = precision_logl
+        self.pg = api.GB_MIXED if precision_grad is None else precision_grad
+        self.plans = {}
+
+    def _plan(self, n: int, prec: int):
+        key = (n, prec)
+        if key not in self.plans:
+            t = self.table.copy()
+            t[:, 6] = np.arange(self.n_win) * n
+            t[:, 7] = n
+            p = self.api.Plan(self.ctx, t, prec)
+            p.prepare(self.d, self.w)
+            self.plans[key] = p
+        return self.plans[key]
+
+    def _n(self, theta) -> int:
+        if len(theta) % self.n_win:
+            raise ValueError("theta rows must be a multiple of the window count")
+        return len(theta) // self.n_win
+
+    def loglik(self, theta: np.ndarray):
+        th = self.torch.as_tensor(np.ascontiguousarray(theta, dtype=np.float64), device="cuda")
+        l, c = self._plan(self._n(theta), self.pl).loglik(th, comps=True)
+        return l.cpu().numpy(), c.cpu().numpy()
+
+    def loglik_grad(self, theta: np.ndarray):
+        th = self.torch.as_tensor(np.ascontiguousarray(theta, dtype=np.float64), device="cuda")
+        l, g = self._plan(self._n(theta), self.pg).loglik_grad(th)
+        return l.cpu().numpy(), g.cpu().numpy()
+
+    def close(self):
+        for p in self.plans.values():
+            p.close()
+        self.plans.clear()
+
+
+def _snr(comps: np.ndarray) -> np.ndarray:
+    with np.errstate(invalid="ignore", divide="ignore"):
+        rho = comps[..., 0] / np.sqrt(comps[..., 1])
+    return np.where(np.isfinite(rho), rho, -np.inf)
+
+
+def _box_arrays(boxes) -> tuple:
+    if isinstance(boxes, I.PriorBox):
+        boxes = [boxes]
+    return np.stack([b.lo for b in boxes]), np.stack([b.hi for b in boxes])
+
+
+def _fold_into_box(m: np.ndarray, lo: np.ndarray, hi: np.ndarray) -> np.ndarray:
+    """Periodic angles wrap into [lo, hi); the other coordinates reflect at the walls.
+    m: [n_win, pop, 7]; lo, hi: [n_win, 7]."""
+    out = m.copy()
+    for k, dim_i in enumerate(SEARCH_DIMS):
+        lk, hk = lo[:, k, None], hi[:, k, None]
+        v = m[..., k]
+        if dim_i in PERIODIC:
+            out[..., k] = lk + np.mod(v - lk, hk - lk)
+        else:
+            v = np.where(v < lk, 2 * lk - v, v)
+            v = np.where(v > hk, 2 * hk - v, v)
+            out[..., k] = np.clip(v, lk, hk)
+    return out
+
+
+def _three_others(rng: np.random.Generator, n_win: int, pop: int) -> np.ndarray:
+    """For each member i of each population, three distinct indices, all different from i."""
+    idx = rng.integers(0, pop, size=(n_win, pop, 3))
+    me = np.arange(pop)[None, :]
+    for _ in range(1000):
+        bad = ((idx[..., 0] == me) | (idx[..., 1] == me) | (idx[..., 2] == me)
+               | (idx[..., 0] == idx[..., 1]) | (idx[..., 0] == idx[..., 2])
+               | (idx[..., 1] == idx[..., 2]))
+        if not bad.any():
+            return idx
+        idx[bad] = rng.integers(0, pop, size=(int(bad.sum()), 3))
+    raise RuntimeError("population too small for DE/rand/1")
+
+
+def _to_theta(x: np.ndarray) -> np.ndarray:
+    u = np.empty(x.shape[:-1] + (8,))
+    u[..., list(SEARCH_DIMS)] = x
+    u[..., 4] = math.log10(REF_AMP)
+    return I.from_table1(u)
+
+
+def de_search(backend, boxes, rng: np.random.Generator, pop: int = 512, generations: int = 50,
+              cr: float = 0.7, f_lo: float = 0.5, f_hi: float = 1.0, init: Optional[np.ndarray] = None,
+              keep: int = 1):
+    """Maximise rho over the seven non-amplitude parameters inside each window's Table I box.
+
+    ``boxes`` is one PriorBox per window of the backend (or a single one for one window);
+    ``init`` optionally seeds member 0 of each population ([n_win, 8] or [8]).  Returns
+    (theta [n_win, keep, 8] of the best ``keep`` members with A = A_max, rho [n_win, keep],
+    history [generations + 1, n_win] of the best rho per generation)."""
+    lo, hi = _box_arrays(boxes)
+    lo, hi = lo[:, list(SEARCH_DIMS)], hi[:, list(SEARCH_DIMS)]
+    n_win, dim = lo.shape
+    if pop < 4 or not 1 <= keep <= pop:
+        raise ValueError("DE/rand/1 needs pop >= 4 and 1 <= keep <= pop")
+    x = lo[:, None, :] + (hi - lo)[:, None, :] * rng.random((n_win, pop, dim))
+    if init is not None:
+        x[:, 0, :] = I.to_table1(np.broadcast_to(init, (n_win, 8)))[:, list(SEARCH_DIMS)]
+
+    def score(xx):
+        _, comps = backend.loglik(_to_theta(xx).reshape(n_win * pop, 8))
+        return _snr(comps).reshape(n_win, pop)
+
+    s = score(x)
+    history = [s.max(axis=1)]
+    wi = np.arange(n_win)[:, None]
+    for _ in range(generations):
+        r = _three_others(rng, n_win, pop)
+        fscale = rng.uniform(f_lo, f_hi)
+        mutant = x[wi, r[..., 0]] + fscale * (x[wi, r[..., 1]] - x[wi, r[..., 2]])
+        mutant = _fold_into_box(mutant, lo, hi)
+        cross = rng.random((n_win, pop, dim)) < cr
+        cross[wi, np.arange(pop)[None, :], rng.integers(0, dim, (n_win, pop))] = True
+        trial = np.where(cross, mutant, x)
+        s_trial = score(trial)
+        better = s_trial > s
+        x[better] = trial[better]
+        s[better] = s_trial[better]
+        history.append(s.max(axis=1))
+    order = np.argsort(-s, axis=1, kind="stable")[:, :keep]
+    th = _to_theta(x[wi, order])                               # [n_win, keep, 8]
+    # A_max of the kept members: one more batched call, padded to the population size so
+    # that the plan of the scoring calls is reused
+    pad = np.repeat(th[:, :1, :], pop, axis=1)
+    pad[:, :keep, :] = th
+    _, comps = backend.loglik(pad.reshape(n_win * pop, 8))
+    comps = comps.reshape(n_win, pop, 2)[:, :keep, :]
+    th[..., 4] = REF_AMP * comps[..., 0] / comps[..., 1]
+    return th, s[wi, order], np.array(history)
+
+
+def _table1_jacobian(theta: np.ndarray) -> np.ndarray:
+    """d theta / d u for the Table I coordinates u (sin beta, log10 A, cos iota changed)."""
+    j = np.ones_like(theta)
+    j[..., 2] = 1.0 / np.maximum(np.cos(theta[..., 2]), 1e-12)
+    j[..., 4] = theta[..., 4] * math.log(10.0)
+    j[..., 5] = -1.0 / np.maximum(np.sin(theta[..., 5]), 1e-12)
+    return j
+
+
+def polish(backend, theta0: np.ndarray, scale: np.ndarray, iterations: int = 20, n_steps: int = 32,
+           tol: float = 1e-9):
+    """Quasi-Newton (BFGS) ascent on logL from many starts at once.
+
+    ``theta0`` is [n_win, k, 8]: k starts in each window of the backend ([k, 8] or [8] for one
+    window).  ``scale`` is the per-coordinate scale s in Table I coordinates, broadcast to
+    [n_win, k, 8] (a Fisher sigma is the natural choice, a small fraction of the box widths a
+    safe one); the search runs in x = u / s.  Each iteration takes one batched gradient call,
+    then evaluates alpha * p along each start's BFGS direction p for alpha in {0} and
+    10^-6 .. 10^2 in one batched likelihood call and keeps each start's best.  A start stops
+    when no step raises its logL by more than `tol`.
+    Returns (theta shaped like theta0, logL history [iterations + 1] + theta0's leading shape)."""
+    th0 = np.asarray(theta0, dtype=np.float64)
+    shape = th0.shape
+    th = th0.reshape((-1,) + shape[-2:]) if th0.ndim == 3 else th0.reshape(1, -1, 8)
+    n_win, k, _ = th.shape
+    s = np.broadcast_to(np.asarray(scale, dtype=np.float64), (n_win, k, 8)).copy()
+    alphas = np.concatenate([[0.0], np.logspace(-6, 2, n_steps - 1)])
+    na = len(alphas)
+    H = np.broadcast_to(np.eye(8), (n_win, k, 8, 8)).copy()
+    active = np.ones((n_win, k), dtype=bool)
+    wi, ki = np.arange(n_win)[:, None], np.arange(k)[None, :]
+
+    def grad_x(t):
+        _, g = backend.loglik_grad(t.reshape(n_win * k, 8))
+        return g.reshape(n_win, k, 8) * _table1_jacobian(t) * s
+
+    # logL values come from the likelihood calls (the precision chosen for scoring); the
+    # gradient calls only supply directions and curvature pairs
+    gx = grad_x(th)
+    l0, _ = backend.loglik(th.reshape(n_win * k, 8))
+    cur = l0.reshape(n_win, k)
+    hist = [cur.copy()]
+    x = I.to_table1(th) / s
+    for _ in range(iterations):
+        if not active.any():
+            hist.append(cur.copy())
+            continue
+        p = np.einsum("wkij,wkj->wki", H, gx)
+        bad = np.sum(p * gx, axis=-1) <= 0.0
+        if bad.any():                                           # not an ascent direction
+            H[bad] = np.eye(8)
+            p[bad] = gx[bad]
+        pn = np.linalg.norm(p, axis=-1, keepdims=True)
+        p = np.where(pn > 0, p / np.where(pn > 0, pn, 1.0), 0.0)
+        p[~active] = 0.0
+        trial_u = (x[:, :, None, :] + alphas[None, None, :, None] * p[:, :, None, :]) * s[:, :, None, :]
+        trial_u[..., 2] = np.clip(trial_u[..., 2], -1.0, 1.0)
+        trial_u[..., 5] = np.clip(trial_u[..., 5], -1.0, 1.0)
+        trial = I.from_table1(trial_u)                          # [n_win, k, na, 8]
+        lt, _ = backend.loglik(trial.reshape(n_win * k * na, 8))
+        lt = lt.reshape(n_win, k, na)
+        lt = np.where(np.isfinite(lt), lt, -np.inf)
+        j = np.argmax(lt, axis=-1)
+        best = lt[wi, ki, j]
+        move = active & (j > 0) & (best - cur > tol)
+        active = move
+        th_new = np.where(move[..., None], trial[wi, ki, j], th)
+        x_new = I.to_table1(th_new) / s
+        gx_new = grad_x(th_new)
+        sk, yk = x_new - x, gx - gx_new                         # curvature pairs of -logL
+        sy = np.sum(sk * yk, axis=-1)
+        upd = move & (sy > 1e-12 * np.linalg.norm(sk, axis=-1) * np.linalg.norm(yk, axis=-1))
+        if upd.any():
+            r = 1.0 / sy[upd]
+            V = np.eye(8)[None] - r[:, None, None] * np.einsum("bi,bj->bij", sk[upd], yk[upd])
+            H[upd] = (np.einsum("bij,bjk,blk->bil", V, H[upd], V)
+                      + r[:, None, None] * np.einsum("bi,bj->bij", sk[upd], sk[upd]))
+        cur = np.where(move, best, cur)
+        th, x, gx = th_new, x_new, gx_new
+        hist.append(cur.copy())
+    return th.reshape(shape), np.array(hist).reshape((iterations + 1,) + shape[:-1])
+
+
+def search(backend, boxes, rng: np.random.Generator, pop: int = 512, generations: int = 50,
+           keep: int = 8, polish_iterations: int = 20, scale_frac: float = 1e-3, n_searches: int = 1):
+    """Maximum-likelihood search of Sec. III D for every window of the backend: DE over the box,
+    then the BFGS polish of the ``keep`` best members (scale: ``scale_frac`` of the box widths),
+    repeated ``n_searches`` times from fresh populations in case a search ends at a local
+    optimum.  Returns (theta [n_win, 8], logL [n_win]) of the best polished point per window."""
+    lo, hi = _box_arrays(boxes)
+    n_win = len(lo)
+    best_th = np.full((n_win, 8), np.nan)
+    best_l = np.full(n_win, -np.inf)
+    scale = (scale_frac * (hi - lo))[:, None, :]
+    for _ in range(n_searches):
+        th, _, _ = de_search(backend, boxes, rng, pop=pop, generations=generations, keep=keep)
+        th, hist = polish(backend, th, scale, iterations=polish_iterations)
+        l_end = hist[-1]                                       # [n_win, keep]
+        j = np.argmax(l_end, axis=1)
+        cand_l = l_end[np.arange(n_win), j]
+        better = cand_l > best_l
+        best_th[better] = th[np.arange(n_win), j][better]
+        best_l[better] = cand_l[better]
+    return best_th, best_l
+
+
+class PosteriorStage:
+    """One temperature of Algorithm 4 on the single window of a prepared plan whose window holds
+    n candidates: n proposals uniform in the box [lo, hi] (Table I coordinates, so log g = 0),
+    their logL and the independent-proposal chain, all in one ``gb_mh_step``.  ``run()`` launches
+    the stage eagerly on the current stream; ``capture()`` records it once in a HIP graph (the
+    draws come from ``generator``, which every replay advances) and ``replay()`` re-launches it.
+    After either, the buffers theta, u, logL, chain and n_accept hold the stage's result."""
+
+    def __init__(self, plan, box_lo: np.ndarray, box_hi: np.ndarray, temperature: float, generator=None):
+        import torch
+        self.torch = torch
+        if plan.n_win != 1:
+            raise ValueError("PosteriorStage drives a plan of one window")
+        dev = torch.device("cuda")
+        self.plan, self.T = plan, float(temperature)
+        self.gen = generator if generator is not None else torch.cuda.default_generators[torch.cuda.current_device()]
+        self.n = int(plan.table[0, 7])
+        self.lo = torch.as_tensor(np.asarray(box_lo, dtype=np.float64), device=dev)
+        self.hi = torch.as_tensor(np.asarray(box_hi, dtype=np.float64), device=dev)
+        rows = plan.rows
+        self.r = torch.empty((rows, 8), dtype=torch.float64, device=dev)
+        self.theta = torch.zeros((rows, 8), dtype=torch.float64, device=dev)
+        self.u = torch.empty(rows, dtype=torch.float64, device=dev)
+        self.log_g = torch.zeros(rows, dtype=torch.float64, device=dev)
+        self.logL = torch.empty(rows, dtype=torch.float64, device=dev)
+        self.chain = torch.empty(rows, dtype=torch.int32, device=dev)
+        self.n_accept = torch.empty(1, dtype=torch.int64, device=dev)
+        self.graph = None
+
+    def _body(self, stream):
+        torch = self.torch
+        from . import api
+        self.r.uniform_(generator=self.gen)
+        v = self.lo + (self.hi - self.lo) * self.r
+        th = self.theta
+        th.copy_(v)
+        th[:, 2] = torch.asin(v[:, 2].clamp(-1.0, 1.0))
+        th[:, 4] = torch.pow(10.0, v[:, 4])
+        th[:, 5] = torch.acos(v[:, 5].clamp(-1.0, 1.0))
+        self.u.uniform_(generator=self.gen)
+        api.gb_mh_step(self.plan.handle, self.plan.d, self.plan.w, th, self.log_g, self.u, self.T,
+                       self.logL, self.chain, self.n_accept, stream)
+
+    def run(self):
+        self._body(self.torch.cuda.current_stream())
+
+    def capture(self):
+        torch = self.torch
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            self._body(s)                # warm-up outside the capture
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        if self.gen is not torch.cuda.default_generators[torch.cuda.current_device()]:
+            self.graph.register_generator_state(self.gen)   # the default one is registered by torch
+        with torch.cuda.graph(self.graph, stream=s):
+            self._body(s)
+        torch.cuda.synchronize()
+
+    def replay(self):
+        if self.graph is None:
+            raise RuntimeError("capture() first")
+        self.graph.replay()

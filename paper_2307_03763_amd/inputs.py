@@ -302,6 +302,11 @@ class Workload:
         o = int(self.cand_off[i])
         return self.theta[o:o + int(self.n_cand[i])]
 
+    def window_box(self, i: int) -> "PriorBox":
+        """Table I box of window i: the window's bins less W/6 on each side (the padding)."""
+        w = self.windows[i]
+        return table1_box(w.f_lo + w.W / 6 / self.T, w.f_hi - w.W / 6 / self.T, self.T)
+
 
 def add_templates(data_cw: np.ndarray, k0: int, h: np.ndarray, first_bin: np.ndarray, sign: float = 1.0):
     """Add templates h[n, C, N] (bins first_bin..) into a window block data_cw[C, W] (bins k0..),
