@@ -64,9 +64,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--rho-mixed", type=float, default=8.0)
     ap.add_argument("--copy-calibration", action="store_true")
-    ap.add_argument("--traffic", nargs=5, metavar=("BENCH_JSON", "K_FETCH_DIR", "K_WRITE_DIR", "COPY_FETCH_DIR",
-                                                   "COPY_WRITE_DIR"),
+    ap.add_argument("--traffic", nargs=4, metavar=("K_FETCH_DIR", "K_WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="print the profiles/hbm_traffic.txt line from rocprofv3 --pmc outputs and exit")
+    ap.add_argument("--trace-summary", nargs=2, metavar=("BENCH_JSON", "TRACE_DIR"),
+                    help="print the timed-region kernel summary of a rocprofv3 --kernel-trace and exit")
     return ap.parse_args()
 
 
@@ -77,6 +78,9 @@ def main():
         return
     if args.traffic:
         print(traffic_summary(*args.traffic))
+        return
+    if args.trace_summary:
+        print(trace_summary(*args.trace_summary))
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -184,7 +188,7 @@ def main():
     # switched off in this version of the library)
     grad_prec = np.full(wl.n_win, api.GB_MIXED)
     groups_ad = make_groups(prec_w, grad_prec)
-    region = ProfilerRegion()
+    region = TimedRegion()
     ms_ad, per_ad = run_steps(groups_ad, args.steps, args.warmup, region)
     # the likelihood kernel alone for every MH group (an MH stage is that kernel plus the
     # chain kernel): the same launches through gb_loglik, still inside the profiled region
@@ -227,8 +231,8 @@ def main():
                 "frac": round(achieved_tf / PEAK_VALU_TFLOPS, 4), "traffic": committed_traffic(kname, n_dom),
                 "kernel": kname,
                 "launch_ms": round(dur_ms, 4), "evals_per_launch": n_dom,
-                "timing": "HIP events on the launch stream, mean over the timed launches; the timed "
-                          "region is bracketed by roctxProfilerResume/Pause for rocprofv3 --selected-regions",
+                "timing": "HIP events on the launch stream, mean over the timed launches",
+                "launches_in_region": args.steps * (2 if kind == "mh" else 1),
                 "flops_per_eval": round(fl / n_dom, 1),
                 "hbm_gbs": round((n_dom * bytes_per_eval(kC, kN, is_grad) +
                                   sum(24.0 * kC * wl.windows[i].W for i in idx)) / (dur_ms * 1e-3) / 1e9, 3),
@@ -287,6 +291,7 @@ def main():
         "speedup_vs_fp64": (round(adaptive["logl_evals_per_s"] / fp64["logl_evals_per_s"], 3) if fp64 else None),
         "speedup_basis": "logL evals/s of the MH stage, adaptive ragged vs plain FP64 per window",
         "roofline": roofline,
+        "timed_region_ns": region.t,
         "cpu_baseline": cpu,
         "autotune": tune.strip().split("\n"),
         "library": library_hash(),
@@ -296,32 +301,29 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-class ProfilerRegion:
-    """roctxProfilerResume(0) / roctxProfilerPause(0) around the timed region, so that
-    `rocprofv3 --selected-regions ...` records exactly the timed launches; without a profiler
-    attached the calls do nothing."""
+class TimedRegion:
+    """Host clock readings (CLOCK_MONOTONIC and CLOCK_BOOTTIME, ns) around the timed launches,
+    taken after a device synchronisation on both sides, so that the launches of a rocprofv3
+    trace of the same command that fall inside the window are exactly the timed ones."""
 
     def __init__(self):
-        import ctypes
-        self.lib = None
-        for name in ("librocprofiler-sdk-roctx.so.1", "/opt/rocm/lib/librocprofiler-sdk-roctx.so.1"):
-            try:
-                self.lib = ctypes.CDLL(name)
-                break
-            except OSError:
-                continue
+        self.t = {}
+
+    @staticmethod
+    def _now():
+        return {"monotonic": time.clock_gettime_ns(time.CLOCK_MONOTONIC),
+                "boottime": time.clock_gettime_ns(time.CLOCK_BOOTTIME)}
 
     def resume(self):
         import torch
         torch.cuda.synchronize()
-        if self.lib is not None:
-            self.lib.roctxProfilerResume(0)
+        self.t0 = self._now()
 
     def pause(self):
         import torch
         torch.cuda.synchronize()
-        if self.lib is not None:
-            self.lib.roctxProfilerPause(0)
+        t1 = self._now()
+        self.t = {k: [self.t0[k], t1[k]] for k in t1}
 
 
 def tuned_kernel_name(tune: str, prec: int, grad: bool, N: int, C: int) -> str:
@@ -335,55 +337,106 @@ def tuned_kernel_name(tune: str, prec: int, grad: bool, N: int, C: int) -> str:
 
 
 def _kernel_key(name: str) -> str:
-    """'void k_batch<double, 512, 128, 3, 4, 1, 1>(BatchArgs)' -> 'k_batch<double,512,128,3,4,1,1>'."""
+    """'void gbx::k_batch<double, 512, 128, 3, 4, 1, 1>(gbx::BatchArgs)' -> 'k_batch<double,512,128,3,4,1,1>'."""
     n = name.replace(" ", "")
     if n.startswith("void"):
         n = n[4:]
-    return n.split("(", 1)[0]
+    n = n.split("(", 1)[0]
+    return n[5:] if n.startswith("gbx::") else n
 
 
-def _counter_per_dispatch(csv_dir: str, counter: str) -> dict:
-    """{kernel key: [counter value per dispatch]} from rocprofv3 --pmc output under csv_dir."""
+def _dispatches(run_dir: str, counter: str = None) -> list:
+    """Kernel dispatches of a rocprofv3 output directory as (kernel key, start ns, end ns, value):
+    from the SQLite database (rocprofv3's default output) or from its CSV files; value is the
+    counter's value for a --pmc run (counter given), else None."""
     import csv
     import glob
-    out = {}
-    files = glob.glob(os.path.join(csv_dir, "**", "*counter_collection.csv"), recursive=True)
-    if not files:
-        raise FileNotFoundError(f"no counter_collection.csv under {csv_dir}")
-    for fn in files:
+    import sqlite3
+    out = []
+    dbs = glob.glob(os.path.join(run_dir, "**", "*.db"), recursive=True)
+    if dbs:
+        for fn in dbs:
+            con = sqlite3.connect(fn)
+            if counter is None:
+                q = "select name, start, end, NULL from kernels"
+            else:
+                q = f"select name, start, end, counter_value from pmc_events where counter_name = '{counter}'"
+            out += [(_kernel_key(n), int(t0), int(t1), v) for n, t0, t1, v in con.execute(q)]
+            con.close()
+        return out
+    pat = "*kernel_trace.csv" if counter is None else "*counter_collection.csv"
+    for fn in glob.glob(os.path.join(run_dir, "**", pat), recursive=True):
         with open(fn) as f:
             for row in csv.DictReader(f):
-                if row.get("Counter_Name") != counter:
+                if counter is not None and row.get("Counter_Name") != counter:
                     continue
-                out.setdefault(_kernel_key(row["Kernel_Name"]), []).append(float(row["Counter_Value"]))
+                out.append((_kernel_key(row["Kernel_Name"]), int(row.get("Start_Timestamp", 0) or 0),
+                            int(row.get("End_Timestamp", 0) or 0),
+                            float(row["Counter_Value"]) if counter is not None else None))
+    if not out:
+        raise FileNotFoundError(f"no rocprofv3 output under {run_dir}")
     return out
 
 
-def traffic_summary(bench_json: str, k_fetch: str, k_write: str, c_fetch: str, c_write: str) -> str:
-    """One line for profiles/hbm_traffic.txt: HBM bytes per launch of the bench's dominant kernel
-    from FETCH_SIZE and WRITE_SIZE (KiB per dispatch, rocprofv3 --pmc over the timed region),
-    each scaled by what the same counter reads for the copy calibration (known bytes)."""
+def _in_region(disp: list, bench: dict) -> list:
+    """The dispatches inside the bench's timed region, on the host clock under which the dominant
+    kernel shows exactly the expected number of launches."""
+    kern = bench["roofline"]["kernel"]
+    want = bench["roofline"]["launches_in_region"]
+    for clock, (t0, t1) in bench["timed_region_ns"].items():
+        sel = [d for d in disp if d[1] >= t0 and d[2] <= t1]
+        if sum(1 for d in sel if d[0] == kern) == want:
+            return sel
+    raise ValueError(f"no clock puts {want} launches of {kern} inside the timed region")
+
+
+def _last_json(path: str) -> dict:
     import json as _json
-    b = _json.loads(open(bench_json).read().strip().splitlines()[-1])
+    return _json.loads(open(path).read().strip().splitlines()[-1])
+
+
+def trace_summary(bench_json: str, trace_dir: str) -> str:
+    """Per-kernel durations of the launches inside the bench's timed region, from a rocprofv3
+    --kernel-trace of the same command, beside the bench's own event timing of its dominant
+    kernel."""
+    b = _last_json(bench_json)
+    sel = _in_region(_dispatches(trace_dir), b)
+    per = {}
+    for k, t0, t1, _ in sel:
+        per.setdefault(k, []).append((t1 - t0) * 1e-6)
+    span = (max(d[2] for d in sel) - min(d[1] for d in sel)) * 1e-6
     kern = b["roofline"]["kernel"]
-    evals = b["roofline"]["evals_per_launch"]
-    kf = _counter_per_dispatch(k_fetch, "FETCH_SIZE")
-    kw = _counter_per_dispatch(k_write, "WRITE_SIZE")
-    cf = _counter_per_dispatch(c_fetch, "FETCH_SIZE")
-    cw = _counter_per_dispatch(c_write, "WRITE_SIZE")
-    if kern not in kf or kern not in kw:
-        raise KeyError(f"{kern} not among the profiled kernels: {sorted(kf)}")
-    # the copy is the single largest dispatch of the calibration run
-    copy_f = max(v for vals in cf.values() for v in vals)
-    copy_w = max(v for vals in cw.values() for v in vals)
-    nbytes = 8 * COPY_N
-    s_f = nbytes / (copy_f * 1024.0)
-    s_w = nbytes / (copy_w * 1024.0)
-    f_kib = sum(kf[kern]) / len(kf[kern])
-    w_kib = sum(kw[kern]) / len(kw[kern])
-    by = f_kib * 1024.0 * s_f + w_kib * 1024.0 * s_w
-    return (f"library={b['library']} kernel={kern} evals={evals} bytes={by:.0f} "
-            f"fetch_kib={f_kib:.1f} write_kib={w_kib:.1f} dispatches={len(kf[kern])} "
+    lines = [f"timed region: {len(sel)} dispatches over {span:.3f} ms (first start to last end)",
+             f"{'kernel':<44} {'calls':>6} {'avg ms':>9} {'total ms':>10} {'% busy':>7}"]
+    busy = sum(sum(v) for v in per.values())
+    for k, v in sorted(per.items(), key=lambda kv: -sum(kv[1])):
+        lines.append(f"{k:<44} {len(v):>6} {sum(v) / len(v):>9.4f} {sum(v):>10.3f} {100 * sum(v) / busy:>6.1f}%")
+    dom = per[kern]
+    lines.append(f"dominant kernel {kern}: rocprofv3 average {sum(dom) / len(dom):.4f} ms over {len(dom)} "
+                 f"launches; bench HIP-event average {b['roofline']['launch_ms']:.4f} ms")
+    return "\n".join(lines)
+
+
+def traffic_summary(k_fetch: str, k_write: str, c_fetch: str, c_write: str) -> str:
+    """One line for profiles/hbm_traffic.txt: HBM bytes per launch of the dominant kernel from
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch; two rocprofv3 --pmc runs of the bench, each
+    directory DIR beside DIR.json, the bench's output line of that run), each scaled by what
+    the same counter reads for the copy calibration of known size (its largest dispatch)."""
+    vals, kern, b = {}, None, None
+    for ctr, run in (("FETCH_SIZE", k_fetch), ("WRITE_SIZE", k_write)):
+        b = _last_json(run.rstrip("/") + ".json")
+        if kern is not None and b["roofline"]["kernel"] != kern:
+            raise ValueError("the two counter runs chose different kernels")
+        kern = b["roofline"]["kernel"]
+        sel = [d for d in _in_region(_dispatches(run, ctr), b) if d[0] == kern]
+        vals[ctr] = sum(d[3] for d in sel) / len(sel)
+    copy_f = max(d[3] for d in _dispatches(c_fetch, "FETCH_SIZE"))
+    copy_w = max(d[3] for d in _dispatches(c_write, "WRITE_SIZE"))
+    s_f = 8 * COPY_N / (copy_f * 1024.0)
+    s_w = 8 * COPY_N / (copy_w * 1024.0)
+    by = vals["FETCH_SIZE"] * 1024.0 * s_f + vals["WRITE_SIZE"] * 1024.0 * s_w
+    return (f"library={b['library']} kernel={kern} evals={b['roofline']['evals_per_launch']} bytes={by:.0f} "
+            f"fetch_kib={vals['FETCH_SIZE']:.1f} write_kib={vals['WRITE_SIZE']:.1f} "
             f"copy_scale_fetch={s_f:.4f} copy_scale_write={s_w:.4f}")
 
 
@@ -415,12 +468,9 @@ def copy_calibration():
     n = COPY_N
     a = torch.ones(n, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
-    torch.mul(a, 1.0, out=b)  # warm-up outside the profiled region
-    region = ProfilerRegion()
-    region.resume()
     for _ in range(3):
         torch.mul(a, 1.0, out=b)  # an elementwise copy kernel: reads n doubles, writes n doubles
-    region.pause()
+    torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "launches": 3}), flush=True)
 
 
