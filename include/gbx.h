@@ -93,8 +93,10 @@ gb_status gb_waveform(gb_ctx* ctx, const double* theta, int64_t B, int N, int C,
 
 /* Build a plan for `n_win` windows (host array, copied): validates every window, groups the
  * windows by (N, C, precision), splits their candidates into tiles ordered by cost and
- * uploads the work lists (device memory owned by the plan).  Synchronous; allocates.
- * GB_EINVAL on a bad window (message names it). */
+ * uploads the work lists (device memory owned by the plan).  Also reserves the scratch of
+ * gb_mh_step's chain: per window 2P doubles (P = smallest power of two >= n_cand) and
+ * K (n_cand + 1) int32 (2^K > n_cand), about 90 bytes per candidate.  Synchronous;
+ * allocates.  GB_EINVAL on a bad window (message names it); GB_ENOMEM. */
 gb_status gb_plan_create(gb_ctx* ctx, const gb_window* windows, int n_win,
                          gb_precision precision, gb_plan** plan);
 void gb_plan_destroy(gb_plan* plan);
@@ -130,7 +132,11 @@ gb_status gb_loglik_grad(gb_plan* plan, const double* d, const double* w, const 
  *   pi = logL - log_g (u_i = 0 always accepts; NaN logL never accepted).
  * log_g, u: [rows] (proposal log-density and uniforms in [0, 1)); outputs logL: [rows],
  * chain: int32 [rows] (index within the window of the state after each step, chain[0] = 0),
- * n_accept: int64 [n_win].  GB_EINVAL: temperature <= 0 or not finite. */
+ * n_accept: int64 [n_win].  The chain is resolved in logarithmic depth, one workgroup per
+ * window (next accepted proposal of every state from a max-tree of pi_i - T ln u_i, then
+ * binary lifting), with the same comparisons as the step-by-step loop; it uses the plan's
+ * chain scratch, so calls on one plan must not overlap.
+ * GB_EINVAL: temperature <= 0 or not finite. */
 gb_status gb_mh_step(gb_plan* plan, const double* d, const double* w, const double* theta,
                      const double* log_g, const double* u, double temperature,
                      double* logL, int32_t* chain, int64_t* n_accept, void* stream);
@@ -140,6 +146,14 @@ gb_status gb_mh_step(gb_plan* plan, const double* d, const double* w, const doub
  * kept in the context and used by plans created afterwards.  Synchronous; allocates.
  * `report` (host, may be NULL) receives a text summary of at most report_len bytes. */
 gb_status gb_autotune(gb_ctx* ctx, int reps, char* report, size_t report_len);
+
+/* Set the launch shape of one (precision, mode, N, C) group by hand, as gb_autotune would:
+ * for repeating a tuned configuration exactly (for example in a profiling run).  mode:
+ * 1 = likelihood, 2 = gradient.  The shape must be one of the compiled variants (the
+ * autotuner's report names them as k_batch<R,N,lanes,C,waves,mode,min waves per SIMD>).
+ * Affects plans created afterwards.  GB_EINVAL: no such compiled variant. */
+gb_status gb_select_variant(gb_ctx* ctx, gb_precision precision, int mode, int N, int C,
+                            int lanes_per_template, int waves_per_block, int min_waves_per_simd);
 
 #ifdef __cplusplus
 }

@@ -23,7 +23,7 @@ PRECISION = {"fp64": GB_FP64, "mixed": GB_MIXED, "per_window": GB_PER_WINDOW}
 
 EXPORTS = ("gb_create", "gb_destroy", "gb_last_error", "gb_waveform", "gb_plan_create",
            "gb_plan_destroy", "gb_window_prepare", "gb_loglik", "gb_loglik_grad", "gb_mh_step",
-           "gb_autotune")
+           "gb_autotune", "gb_select_variant")
 
 
 class GbxError(RuntimeError):
@@ -78,6 +78,8 @@ def lib():
         L.gb_mh_step.restype = st
         L.gb_autotune.argtypes = [_vp, i, ctypes.c_char_p, ctypes.c_size_t]
         L.gb_autotune.restype = st
+        L.gb_select_variant.argtypes = [_vp, i, i, i, i, i, i, i]
+        L.gb_select_variant.restype = st
         _lib = L
     return _lib
 
@@ -180,6 +182,25 @@ def gb_autotune(ctx: int, reps: int = 5) -> str:
     buf = ctypes.create_string_buffer(16384)
     _check(lib().gb_autotune(ctx, reps, buf, len(buf)), "gb_autotune")
     return buf.value.decode()
+
+
+def gb_select_variant(ctx: int, precision: int, mode: int, N: int, C: int, lanes_per_template: int,
+                      waves_per_block: int, min_waves_per_simd: int):
+    _check(lib().gb_select_variant(ctx, precision, mode, N, C, lanes_per_template, waves_per_block,
+                                   min_waves_per_simd), "gb_select_variant")
+
+
+def apply_tuning(ctx: int, report: str) -> int:
+    """Re-apply the choices of a gb_autotune report (its 'kernel=k_batch<R,N,LPC,C,WPB,MODE,OCC>'
+    entries); returns how many were set."""
+    import re
+    n = 0
+    for m in re.finditer(r"kernel=k_batch<(double|float),(\d+),(\d+),(\d+),(\d+),(\d+),(\d+)>", report):
+        r, N, lpc, C, wpb, mode, occ = m.groups()
+        gb_select_variant(ctx, GB_FP64 if r == "double" else GB_MIXED, int(mode), int(N), int(C), int(lpc),
+                          int(wpb), int(occ))
+        n += 1
+    return n
 
 
 # ------------------------------------------------------------------------------------------

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "gbx_kernels.h"
+#include "gbx_chain.h"
 #include "gbx_variants.h"
 
 using namespace gbx;
@@ -99,50 +100,6 @@ __global__ void __launch_bounds__(256) k_prepare(DevWin* wins, const double* d, 
   if ((threadIdx.x & 63) == 0) part[threadIdx.x / 64] = acc;
   __syncthreads();
   if (threadIdx.x == 0) wins[blockIdx.x].dd = part[0] + part[1] + part[2] + part[3];
-}
-
-// Independent-proposal chain of one source per wave.  In chunks of 64 steps the wave finds
-// the first step whose threshold tau_i = pi_i - T ln u_i exceeds the current pi_c (a ballot),
-// moves the state there and continues after it; the chain index of every step is the last
-// accepted step at or before it.  The comparisons are exactly those of the serial loop.
-__global__ void __launch_bounds__(64) k_mh_chain(const DevWin* wins, const double* logL, const double* log_g,
-                                                 const double* u, double temp, int32_t* chain,
-                                                 int64_t* n_accept) {
-  const DevWin w = wins[blockIdx.x];
-  const int lane = threadIdx.x;
-  const int64_t n = w.n_cand, base = w.cand_off;
-  if (n <= 0) {
-    if (lane == 0) n_accept[blockIdx.x] = 0;
-    return;
-  }
-  double pic = logL[base] - log_g[base];
-  int64_t c = 0, acc = 0;
-  for (int64_t i0 = 0; i0 < n; i0 += 64) {
-    const int64_t i = i0 + lane;
-    const bool in = i < n && i > 0;
-    double pii = 0.0, tau = 0.0;
-    if (in) {
-      pii = logL[base + i] - log_g[base + i];
-      tau = __dsub_rn(pii, __dmul_rn(temp, log(u[base + i])));
-    }
-    uint64_t accmask = 0;
-    int last = -1;
-    for (;;) {
-      const uint64_t m = __ballot(in && lane > last && pic < tau);
-      if (m == 0) break;
-      const int k = __ffsll((unsigned long long)m) - 1;
-      accmask |= 1ull << k;
-      pic = __shfl(pii, k, 64);
-      last = k;
-      ++acc;
-    }
-    const uint64_t upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
-    const uint64_t below = accmask & upto;
-    const int64_t st = below ? i0 + (63 - __clzll((long long)below)) : c;
-    if (i < n) chain[base + i] = (int32_t)st;
-    if (accmask) c = i0 + (63 - __clzll((long long)accmask));
-  }
-  if (lane == 0) n_accept[blockIdx.x] = acc;
 }
 
 // ------------------------------------------------------------------------------- variants
@@ -309,6 +266,9 @@ struct gb_plan {
   gb_ctx* ctx = nullptr;
   std::vector<gb_window> wins;
   DevWin* d_wins = nullptr;
+  ChainWin* d_cw = nullptr;  // chain scratch of every window (max-tree, binary-lifting tables)
+  double* d_tree = nullptr;
+  int32_t* d_jump = nullptr;
   std::vector<Bucket> buckets;
   const double* prep_d = nullptr;
   const double* prep_w = nullptr;
@@ -318,6 +278,9 @@ struct gb_plan {
 extern "C" void gb_plan_destroy(gb_plan* p) {
   if (!p) return;
   (void)hipFree(p->d_wins);
+  (void)hipFree(p->d_cw);
+  (void)hipFree(p->d_tree);
+  (void)hipFree(p->d_jump);
   for (Bucket& b : p->buckets) {
     (void)hipFree(b.d_tiles);
     (void)hipFree(b.d_ctr);
@@ -423,6 +386,29 @@ extern "C" gb_status gb_plan_create(gb_ctx* c, const gb_window* windows, int n_w
     e = hipMalloc(&p->d_wins, sizeof(DevWin) * n_win);
     if (e == hipSuccess) e = hipMemcpy(p->d_wins, dw.data(), sizeof(DevWin) * n_win, hipMemcpyHostToDevice);
   }
+  if (e == hipSuccess && n_win > 0) {
+    // chain scratch: per window a max-tree of 2P doubles and K levels of n + 1 jump entries
+    std::vector<ChainWin> cw(n_win);
+    int64_t toff = 0, joff = 0;
+    for (int i = 0; i < n_win; ++i) {
+      const int64_t n = dw[i].n_cand;
+      int64_t P = 1;
+      while (P < n) P <<= 1;
+      int K = 1;
+      while (((int64_t)1 << K) <= n) ++K;
+      cw[i].tree_off = toff;
+      cw[i].jump_off = joff;
+      cw[i].P = P;
+      cw[i].K = K;
+      cw[i].pad = 0;
+      toff += 2 * P;
+      joff += (int64_t)K * (n + 1);
+    }
+    e = hipMalloc(&p->d_cw, sizeof(ChainWin) * n_win);
+    if (e == hipSuccess) e = hipMemcpy(p->d_cw, cw.data(), sizeof(ChainWin) * n_win, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&p->d_tree, sizeof(double) * (size_t)toff);
+    if (e == hipSuccess) e = hipMalloc(&p->d_jump, sizeof(int32_t) * (size_t)joff);
+  }
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     gb_plan_destroy(p);
@@ -500,10 +486,28 @@ extern "C" gb_status gb_mh_step(gb_plan* p, const double* d, const double* w, co
   if (!log_g || !u || !chain || !n_accept) return fail(GB_EINVAL, "gb_mh_step: null array");
   gb_status s = run_batch(p, MODE_LOGLIK, d, w, theta, logL, nullptr, nullptr, (hipStream_t)stream, "gb_mh_step");
   if (s != GB_OK) return s;
-  hipLaunchKernelGGL(k_mh_chain, dim3((unsigned)p->wins.size()), dim3(64), 0, (hipStream_t)stream, p->d_wins, logL,
-                     log_g, u, temperature, chain, n_accept);
+  hipLaunchKernelGGL(k_mh_chain, dim3((unsigned)p->wins.size()), dim3(1024), 0, (hipStream_t)stream, p->d_wins,
+                     p->d_cw, logL, log_g, u, temperature, p->d_tree, p->d_jump, chain, n_accept);
   HIPCHK(hipGetLastError());
   return GB_OK;
+}
+
+extern "C" gb_status gb_select_variant(gb_ctx* c, gb_precision prec, int mode, int N, int C, int lpc, int wpb,
+                                       int occ) {
+  if (!c) return fail(GB_EINVAL, "gb_select_variant: null context");
+  if ((prec != GB_FP64 && prec != GB_MIXED) || (mode != MODE_LOGLIK && mode != MODE_GRAD) || !pow2_in_range(N) ||
+      (C != 2 && C != 3))
+    return fail(GB_EINVAL, "gb_select_variant: bad precision, mode, N or C");
+  const VariantList& l = all_variants();
+  for (int i = 0; i < l.n; ++i) {
+    const Variant& v = l.v[i];
+    if (v.prec == (int)prec && v.mode == mode && v.N == N && v.C == C && v.LPC == lpc && v.WPB == wpb && v.occ == occ) {
+      c->choice[prec][n_index(N)][C - 2][mode] = &v;
+      return GB_OK;
+    }
+  }
+  return fail(GB_EINVAL, "gb_select_variant: no compiled variant k_batch<%s,%d,%d,%d,%d,%d,%d>",
+              prec == GB_FP64 ? "double" : "float", N, lpc, C, wpb, mode, occ);
 }
 
 // Time every compiled variant of each (precision, N, C, mode) family on synthetic candidates

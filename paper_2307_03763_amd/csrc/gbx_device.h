@@ -65,7 +65,38 @@ __device__ __forceinline__ cplx<R> mul_mi(cplx<R> a) { return mk<R>(a.y, -a.x); 
 
 // sin and cos of 2 pi x (x in cycles).  FP64: sincospi.  FP32: the hardware
 // transcendentals, which take their argument in revolutions; |x| <= 1 here.
-__device__ __forceinline__ void sincos_rev(double x, double* s, double* c) { sincospi(2.0 * x, s, c); }
+// sin and cos of 2 pi x, x in revolutions (FP64).  Quadrant reduction x = n/4 + r with
+// n = rint(4x) and |r| <= 1/8 (both steps exact for |x| < 2^50), the Taylor series of sin and
+// cos at theta = 2 pi r, |theta| <= pi/4 (first omitted terms: theta^17/17! < 5e-17 and
+// theta^18/18! < 3e-18), then a rotation by n quarter turns.
+__device__ __forceinline__ void sincos_rev(double x, double* s, double* c) {
+  const double n = rint(4.0 * x);
+  const double r = fma(n, -0.25, x);
+  const double th = r * (2.0 * kPi);
+  const double t2 = th * th;
+  double ps = -1.0 / 1307674368000.0;      // -1/15!
+  ps = fma(ps, t2, 1.0 / 6227020800.0);    // 1/13!
+  ps = fma(ps, t2, -1.0 / 39916800.0);     // -1/11!
+  ps = fma(ps, t2, 1.0 / 362880.0);        // 1/9!
+  ps = fma(ps, t2, -1.0 / 5040.0);         // -1/7!
+  ps = fma(ps, t2, 1.0 / 120.0);           // 1/5!
+  ps = fma(ps, t2, -1.0 / 6.0);            // -1/3!
+  const double sn = fma(ps * t2, th, th);
+  double pc = 1.0 / 20922789888000.0;      // 1/16!
+  pc = fma(pc, t2, -1.0 / 87178291200.0);  // -1/14!
+  pc = fma(pc, t2, 1.0 / 479001600.0);     // 1/12!
+  pc = fma(pc, t2, -1.0 / 3628800.0);      // -1/10!
+  pc = fma(pc, t2, 1.0 / 40320.0);         // 1/8!
+  pc = fma(pc, t2, -1.0 / 720.0);          // -1/6!
+  pc = fma(pc, t2, 1.0 / 24.0);            // 1/4!
+  pc = fma(pc, t2, -0.5);                  // -1/2!
+  const double cs = fma(pc, t2, 1.0);
+  // e^{i 2 pi x} = i^n e^{i theta}
+  const int q = (int)(long long)n & 3;
+  const double a = (q & 1) ? cs : sn, b = (q & 1) ? sn : cs;
+  *s = (q & 2) ? -a : a;
+  *c = (q == 1 || q == 2) ? -b : b;
+}
 __device__ __forceinline__ void sincos_rev(float x, float* s, float* c) {
   *s = __builtin_amdgcn_sinf(x);
   *c = __builtin_amdgcn_cosf(x);
@@ -196,15 +227,23 @@ __device__ __forceinline__ void slow_sample(const Cand<R>& s, const double* __re
     const int o = OB_P1 + 3 * i;
     kp[i] = s.k[0] * obR[(o + 0) * N + m] + s.k[1] * obR[(o + 1) * N + m] + s.k[2] * obR[(o + 2) * N + m];
   }
+  // e^{i pi f k.dx_i / c} per spacecraft; the offsets from the guiding centre sum to zero, so
+  // the third factor is the conjugate of the product of the other two
+  cplx<R> ph[3];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    R sc, cc;
+    sincos_rev((R)0.5 * fr * kp[i], &sc, &cc);
+    ph[i] = mk<R>(cc, sc);
+  }
+  ph[2] = conjg(ph[0] * ph[1]);
   // arm 12 -> opposite spacecraft 3, arm 23 -> 1, arm 31 -> 2
   const int opp[3] = {2, 0, 1};
   cplx<R> P[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    R sc, cc;
-    sincos_rev((R)0.5 * fr * kp[opp[a]], &sc, &cc);
     const cplx<R> b = mk<R>(s.ap.x * Fp[a] + s.ax.x * Fx[a], s.ap.y * Fp[a] + s.ax.y * Fx[a]);
-    P[a] = b * mk<R>(cc, sc);
+    P[a] = b * ph[opp[a]];
   }
   // link sincs: n12 = +arm 12 for link 12, -arm 12 for link 21 (and cyclically)
   const R s12 = sinc_r(x * ((R)1 - kn[0])), s21 = sinc_r(x * ((R)1 + kn[0]));
