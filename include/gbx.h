@@ -22,7 +22,7 @@
  *    surface at the caller's next synchronisation.  gb_last_error() returns a message for
  *    the last non-OK status of the calling thread.
  *  - Candidates whose theta is not finite, whose amplitude is negative, or whose f0 is not
- *    in (0, 0.5 * arm-transfer limit] get NaN outputs; the rest of the batch is unaffected.
+ *    in (0, 4e15 / T) get NaN outputs; the rest of the batch is unaffected.
  *  - A plan may be used by one stream at a time (its work queues are per plan).
  */
 #ifndef GBX_H

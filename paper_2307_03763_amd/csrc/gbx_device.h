@@ -120,7 +120,9 @@ __device__ __forceinline__ double sinc_r(double u) {
     p = p * u2 - 1.0 / 6.0;                        // -1/3!
     return p * u2 + 1.0;
   }
-  return sin(u) / u;
+  double sn, cs;
+  sincos_rev(u * (0.5 / kPi), &sn, &cs);
+  return sn / u;
 }
 __device__ __forceinline__ float sinc_r(float u) {
   if (fabsf(u) <= 2.0f) {
@@ -369,7 +371,7 @@ __device__ __forceinline__ void sinc_d(double u, double* s, double* ds) {
     *ds = q * u;
   } else {
     double sn, cs;
-    sincos(u, &sn, &cs);
+    sincos_rev(u * (0.5 / kPi), &sn, &cs);
     *s = sn / u;
     *ds = (cs - *s) / u;
   }
@@ -477,11 +479,19 @@ __device__ __forceinline__ void grad_sample_rev(const Cand<R>& s, const CandG<R>
     kp[a] = s.k[0] * p0 + s.k[1] * p1 + s.k[2] * p2;
     up[a] = s.u[0] * p0 + s.u[1] * p1 + s.u[2] * p2;
     vp[a] = s.v[0] * p0 + s.v[1] * p1;
+  }
+  // spacecraft phase factors e^{i pi f k.dx / c}: arms 23 and 31 face spacecraft 1 and 2; the
+  // offsets sum to zero, so the factor of spacecraft 3 (arm 12) is the conjugate of their product
+#pragma unroll
+  for (int a = 1; a < 3; ++a) {
     R sc, cc;
     sincos_rev((R)0.5 * fr * kp[a], &sc, &cc);
     E[a] = mk<R>(cc, sc);
-    P[a] = mk<R>(s.ap.x * Fp[a] + s.ax.x * Fx[a], s.ap.y * Fp[a] + s.ax.y * Fx[a]) * E[a];
   }
+  E[0] = conjg(E[1] * E[2]);
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    P[a] = mk<R>(s.ap.x * Fp[a] + s.ax.x * Fx[a], s.ap.y * Fp[a] + s.ax.y * Fx[a]) * E[a];
   // links: index 2a is the "1 - k.n_a" link, 2a+1 the "1 + k.n_a" link of arm a
   // (arm 12: links 12, 21; arm 23: 23, 32; arm 31: 31, 13)
   R sv[6], sd[6];
@@ -540,26 +550,27 @@ __device__ __forceinline__ void grad_sample_rev(const Cand<R>& s, const CandG<R>
     gb += rp * dFp_b + rx * dFx_b;
     gl += rp * dFp_l + rx * dFx_l;
   }
-  // link sincs: coefficient of s_rs in Q is c_rs P_arm
-  const cplx<R> c12 = (bY * D - bX) * P[0], c21 = (bY - bX * D) * P[0];
-  const cplx<R> c23 = (bZ * D - bY) * P[1], c32 = (bZ - bY * D) * P[1];
-  const cplx<R> c31 = (bX * D - bZ) * P[2], c13 = (bX - bZ * D) * P[2];
-  const cplx<R> cl[6] = {c12, c21, c23, c32, c31, c13};
+  // link sincs: the coefficient of s_rs in K Q is e_rs (K P_arm)
+  cplx<R> KP[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) KP[a] = K * P[a];
+  const cplx<R> bXD = bX * D, bYD = bY * D, bZD = bZ * D;
+  const cplx<R> el[6] = {bYD - bX, bY - bXD, bZD - bY, bZ - bYD, bXD - bZ, bX - bZD};
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int sgn = 0; sgn < 2; ++sgn) {
       const int l = 2 * a + sgn;
       const R pm = sgn ? (R)1 : (R)-1;  // u = x (1 + pm k.n)
-      const R rr = (K * cl[l]).x * sd[l];
+      const R rr = (el[l] * KP[a]).x * sd[l];
       gf += rr * pi * Lr * ((R)1 + pm * kn[a]);
       gb += rr * pm * x * un[a];
       gl += rr * pm * x * sg.cb * vn[a];
     }
-  // the delay inside Lam: dQ/dD = sum_a (dLam_a/dD) P_a, dD/df = -2 pi i (L/c) D
-  const cplx<R> cD = scal(bY, s12) * P[0] - scal(bX, s21) * P[0] + scal(bZ, s23) * P[1] - scal(bY, s32) * P[1] +
-                     scal(bX, s31) * P[2] - scal(bZ, s13) * P[2];
-  gf += twopi * Lr * (K * cD * D).y;
+  // the delay inside Lam: d(KQ)/dD = sum_a (dLam_a/dD) K P_a, dD/df = -2 pi i (L/c) D
+  const cplx<R> KcD = (scal(bY, s12) - scal(bX, s21)) * KP[0] + (scal(bZ, s23) - scal(bY, s32)) * KP[1] +
+                      (scal(bX, s31) - scal(bZ, s13)) * KP[2];
+  gf += twopi * Lr * (KcD * D).y;
 
   const double gfd = (double)gf;
   acc.gf += gfd;

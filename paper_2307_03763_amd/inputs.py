@@ -530,3 +530,55 @@ def workload_c5_windows(n_target: int = 4000, T: float = T2, f_min: float = 0.3e
 
 def nextpow2(x: int) -> int:
     return 1 << max(0, int(math.ceil(math.log2(max(1, x)))))
+
+
+def workload_c5(template_fn: Optional[TemplateFn], n_target: int = 4000, n_gb: int = 20000, pop: int = 512,
+                noise: bool = True, T: float = T2) -> Workload:
+    """Full band: the windows of Algorithm 1 over 0.3-30 mHz with B_max scaled so that
+    ``n_target`` segments result (workload_c5_windows); each padded by a quarter of its width on
+    both sides (W = 3 kappa B_max T bins, clamped to [64, 4096]).  ``n_gb`` GBs: f0 log-uniform
+    0.3-30 mHz, A log-uniform 1e-23..1e-21, fdot from chirp masses 0.1-1 Msun, sources wider than
+    1024 - 16 bins rejected (as C3).  Every GB is injected into every window its band overlaps;
+    N = nextpow2(widest overlapping band + 16) clamped to [64, 1024]; C by the paper rule at the
+    window centre.  Candidates: a DE population of ``pop`` per window, uniform over the window's
+    Table I box."""
+    r_inj, r_noise, r_prop, _ = _streams(5)
+    kappa, segs = workload_c5_windows(n_target, T)
+    f_min, f_max = 0.3e-3, 30e-3
+    gbs, bw = [], []
+    rejected = 0
+    while len(gbs) < n_gb:
+        f0 = math.exp(r_inj.uniform(math.log(f_min), math.log(f_max)))
+        fd = float(fdot_gr(f0, r_inj.uniform(0.1, 1.0)))
+        b = _source_bandwidth_bins(f0, fd, T)
+        if b > 1024 - 16:
+            rejected += 1
+            continue
+        amp = 10.0 ** r_inj.uniform(-23, -21)
+        gbs.append(make_theta([f0], fd, amp, random_angles(r_inj, 1))[0])
+        bw.append(b)
+    gbs = np.array(gbs)
+    bw = np.array(bw)
+    q = np.floor(gbs[:, 0] * T)
+    order = np.argsort(q)
+    gbs, bw, q = gbs[order], bw[order], q[order]
+    lo_bin, hi_bin = q - bw / 2 - 1, q + bw / 2 + 1
+    wins, thetas = [], []
+    for fa, fb in segs:
+        fc = 0.5 * (fa + fb)
+        W = int(min(4096, max(64, round(1.5 * (fb - fa) * T))))
+        k0 = int(math.floor(fc * T)) - W // 2
+        i0 = int(np.searchsorted(hi_bin, k0 - 1024))
+        sel = [j for j in range(i0, len(gbs)) if lo_bin[j] < k0 + W and hi_bin[j] >= k0 and q[j] < k0 + W + 1024]
+        srcs = gbs[sel] if sel else np.zeros((0, 8))
+        widest = float(bw[sel].max()) if sel else 0.0
+        N = int(min(1024, max(64, nextpow2(int(math.ceil(widest)) + 16))))
+        w = WindowSpec(k0=k0, W=W, N=N, C=channels_for(fc), f_lo=k0 / T, f_hi=(k0 + W) / T, sources=srcs)
+        wins.append(w)
+        box = table1_box(w.f_lo + W / 6 / T, w.f_hi - W / 6 / T, T)
+        thetas.append(draw_uniform_box(r_prop, box.lo, box.hi, pop))
+    wl = _concat(wins, thetas, f"C5 full band: {len(wins)} windows 0.3-30 mHz (kappa {kappa:.3f}), "
+                               f"{n_gb} GBs, DE population {pop} per window, T=2^22*15 s", T)
+    wl.rejected = (rejected, rejected + n_gb)
+    wl.kappa = kappa
+    return finalize_data(wl, template_fn, r_noise, noise)

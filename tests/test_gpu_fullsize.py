@@ -1,0 +1,251 @@
+"""Parity at the full sizes of the five workloads, in the launch configuration the benchmark
+uses (autotuned launch shapes; one plan over all windows, grouped by (N, C, precision) inside
+the library; adaptive per-window precision where the workload asks for it).  The oracle
+recomputes sampled rows one by one; chains are compared bit for bit.
+
+* C1: 1,000 FP64 candidates, all rows.
+* C2: 10,000 candidates in the Fisher-reduced box around source 1 of three overlapping GBs;
+  FP64 logL of all rows; the 10,000-step chain at T = 1, bit-exact; also without subtracting
+  the other two sources.
+* C3: the benchmark's batch (256 windows x 10,000 proposals): adaptive logL on 2,048 sampled
+  rows and mixed gradients on 256 sampled rows.
+* C4: 64 windows x 4,096 candidates uniform over Table I: mixed gradients on 512 sampled rows
+  against the oracle gradient, and one candidate per window against central differences of the
+  FP64 logL (steps of 1e-6 of the Table I widths).
+* C5: 4,000 full-band windows x 512 DE candidates (2.05 M rows): adaptive logL on 2 sampled rows
+  per window.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2307_03763_amd import api
+from paper_2307_03763_amd import inputs as I
+from tests.gpu_common import banner, dev, loglik_tolerance
+
+pytestmark = pytest.mark.gpu
+
+RHO_MIXED = 8.0          # the benchmark's precision policy: mixed at or below, FP64 above
+BAR_MIXED = 1e-5         # logL differences, relative to max(1, |difference|)
+
+
+@pytest.fixture(scope="module")
+def tuned():
+    """One context per observation time, autotuned once (as the benchmark does)."""
+    cache = {}
+
+    def get(T):
+        if T not in cache:
+            ctx = api.context_for(T)
+            api.gb_autotune(ctx.handle, 2)
+            cache[T] = ctx
+        return cache[T]
+    return get
+
+
+def _window_rho(O, wl):
+    """sqrt(<h|h>) of the loudest injection of every window (oracle, FP64)."""
+    g = O.Geometry(wl.T)
+    out = np.zeros(wl.n_win)
+    for i, w in enumerate(wl.windows):
+        if len(w.sources):
+            d, ww = wl.window_data(i)
+            _, c = O.loglik(w.sources, w.k0, w.W, w.N, w.C, d, ww, g)
+            out[i] = math.sqrt(c[:, 1].max())
+    return out
+
+
+def _upload(wl):
+    return dev(wl.data, torch.complex128), dev(wl.weights), dev(wl.theta)
+
+
+def _sample_rows(wl, per_window, rng):
+    rows = []
+    for i in range(wl.n_win):
+        n = int(wl.n_cand[i])
+        if n:
+            rows.append(int(wl.cand_off[i]) + rng.choice(n, size=min(per_window, n), replace=False))
+    return rows
+
+
+def _check_rows(O, wl, l_gpu, rows_per_window, prec_w):
+    """FP64 windows: |l - l_oracle| within the FP64 bound; mixed windows: logL differences
+    against the window's first sampled row within BAR_MIXED."""
+    g = O.Geometry(wl.T)
+    worst64, worstmx = 0.0, 0.0
+    for i, r in enumerate(rows_per_window):
+        if len(r) == 0:
+            continue
+        w = wl.windows[i]
+        d, ww = wl.window_data(i)
+        lo, co = O.loglik(wl.theta[r], w.k0, w.W, w.N, w.C, d, ww, g)
+        lg = l_gpu[r]
+        if prec_w[i] == api.GB_FP64:
+            dd = float(np.sum(ww * np.abs(d) ** 2))
+            tol = loglik_tolerance(dd, co[:, 0], co[:, 1])
+            worst64 = max(worst64, float(np.max(np.abs(lg - lo) / tol)))
+        elif len(r) > 1:
+            e = np.abs((lg - lg[0]) - (lo - lo[0])) / np.maximum(1.0, np.abs(lo - lo[0]))
+            worstmx = max(worstmx, float(e.max()))
+    return worst64, worstmx
+
+
+def _grad_bar(O, wl, i, th, g_gpu):
+    """Mixed-gradient check of one window's rows against the oracle gradient: the difference of
+    each component within 1e-5 of sqrt(F_ii (<d|d> + <h|h>)), the size of that component's
+    natural scale (Cauchy-Schwarz bound of Re<d-h|dh/dtheta_i>)."""
+    w = wl.windows[i]
+    d, ww = wl.window_data(i)
+    g = O.Geometry(wl.T)
+    _, go = O.loglik_grad(th, w.k0, w.W, w.N, w.C, d, ww, g)
+    dd = float(np.sum(ww * np.abs(d) ** 2))
+    worst = 0.0
+    for b in range(len(th)):
+        F = O.fisher(th[b], w.k0, w.W, w.N, w.C, ww, g)
+        _, c = O.loglik(th[b], w.k0, w.W, w.N, w.C, d, ww, g)
+        scale = np.sqrt(np.maximum(np.diag(F), 1e-300) * (dd + c[0, 1]))
+        worst = max(worst, float(np.max(np.abs(g_gpu[b] - go[b]) / scale)))
+    return worst
+
+
+def test_c1_full(oracle_lib, tuned):
+    banner("full size C1: 1,000 candidates, FP64, all rows")
+    O = oracle_lib
+    wl = I.workload_c1(O.template_fn(), n_cand=1000)
+    plan = api.Plan(tuned(wl.T), wl.window_table(), api.GB_FP64)
+    d, w, th = _upload(wl)
+    plan.prepare(d, w)
+    l, c = plan.loglik(th, comps=True)
+    l, c = l.cpu().numpy(), c.cpu().numpy()
+    lo, co = O.loglik_workload(wl)
+    dd = float(np.sum(wl.weights * np.abs(wl.data) ** 2))
+    assert np.all(np.abs(l - lo[0]) <= loglik_tolerance(dd, co[0][:, 0], co[0][:, 1]))
+    assert np.allclose(c, co[0], rtol=1e-9, atol=1e-9 * np.abs(co[0]).max())
+
+
+@pytest.mark.parametrize("subtract", [True, False])
+def test_c2_full(oracle_lib, tuned, subtract):
+    banner(f"full size C2: 10,000 candidates, 10,000-step chain, subtract_others={subtract}")
+    O = oracle_lib
+    probe = I.workload_c2(O.template_fn(), n_cand=1, subtract_others=subtract)
+    src = probe.windows[0].sources[0]
+    w0 = probe.windows[0]
+    _, ww = probe.window_data(0)
+    F = O.fisher(src, w0.k0, w0.W, w0.N, w0.C, ww, O.Geometry(probe.T))
+    jac = np.ones(8)
+    jac[2] = 1.0 / math.cos(src[2])
+    jac[4] = src[4] * math.log(10.0)
+    jac[5] = -1.0 / math.sin(src[5])
+    sigma = np.sqrt(np.diag(np.linalg.inv(F * np.outer(jac, jac))))
+    wl = I.workload_c2(O.template_fn(), n_cand=10000, subtract_others=subtract, sigma=sigma)
+    plan = api.Plan(tuned(wl.T), wl.window_table(), api.GB_FP64)
+    d, w, th = _upload(wl)
+    plan.prepare(d, w)
+    rng = np.random.default_rng(21)
+    log_g = np.zeros(len(wl.theta))          # uniform proposals in the reduced box
+    u = rng.random(len(wl.theta))
+    l, chain, nacc = plan.mh_step(th, dev(log_g), dev(u), 1.0)
+    torch.cuda.synchronize()
+    l, chain, nacc = l.cpu().numpy(), chain.cpu().numpy(), nacc.cpu().numpy()
+    lo, co = O.loglik_workload(wl)
+    dd = float(np.sum(wl.weights * np.abs(wl.data) ** 2))
+    assert np.all(np.abs(l - lo[0]) <= loglik_tolerance(dd, co[0][:, 0], co[0][:, 1]))
+    ref, acc = O.mh_chain(l, log_g, u, 1.0)
+    np.testing.assert_array_equal(chain, ref)
+    assert nacc[0] == acc
+    banner(f"  accepted {acc} of 10,000")
+
+
+def test_c3_full(oracle_lib, tuned):
+    banner("full size C3: 256 windows x 10,000, adaptive logL (2,048 rows), mixed gradients (256 rows)")
+    O = oracle_lib
+    wl = I.workload_c3(O.template_fn(), n_win=256, n_cand=10000)
+    rho = _window_rho(O, wl)
+    prec_w = np.where(rho <= RHO_MIXED, api.GB_MIXED, api.GB_FP64)
+    table = np.concatenate([wl.window_table(), prec_w[:, None]], axis=1)
+    ctx = tuned(wl.T)
+    plan = api.Plan(ctx, table, api.GB_PER_WINDOW)
+    d, w, th = _upload(wl)
+    plan.prepare(d, w)
+    l = plan.loglik(th).cpu().numpy()
+    rng = np.random.default_rng(31)
+    rows = _sample_rows(wl, 8, rng)
+    w64, wmx = _check_rows(O, wl, l, rows, prec_w)
+    banner(f"  FP64 windows: worst |dlogL| / bound {w64:.2f}; mixed windows: worst error {wmx:.2e}")
+    assert w64 <= 1.0 and wmx <= BAR_MIXED
+    gplan = api.Plan(ctx, wl.window_table(), api.GB_MIXED)
+    gplan.prepare(d, w)
+    _, grad = gplan.loglik_grad(th)
+    grad = grad.cpu().numpy()
+    worst = 0.0
+    for i in range(0, wl.n_win, 8):                 # 32 windows x 8 rows
+        r = rows[i]
+        worst = max(worst, _grad_bar(O, wl, i, wl.theta[r], grad[r]))
+    banner(f"  mixed gradients: worst error / scale {worst:.2e}")
+    assert worst <= 1e-5
+
+
+def test_c4_full(oracle_lib, tuned):
+    banner("full size C4: 64 windows x 4,096 gradients (512 rows vs oracle, 64 vs central differences)")
+    O = oracle_lib
+    wl = I.workload_c4(O.template_fn(), n_win=64, n_cand=4096)
+    ctx = tuned(wl.T)
+    d, w, th = _upload(wl)
+    gplan = api.Plan(ctx, wl.window_table(), api.GB_MIXED)
+    gplan.prepare(d, w)
+    _, grad = gplan.loglik_grad(th)
+    grad = grad.cpu().numpy()
+    rng = np.random.default_rng(41)
+    rows = _sample_rows(wl, 8, rng)
+    worst = max(_grad_bar(O, wl, i, wl.theta[rows[i]], grad[rows[i]]) for i in range(wl.n_win))
+    banner(f"  mixed gradients vs oracle: worst error / scale {worst:.2e}")
+    assert worst <= 1e-5
+    # central differences of the FP64 logL (GPU), one candidate per window, 16 evaluations each
+    widths = np.stack([wl.window_box(i).width for i in range(wl.n_win)])
+    pick = np.array([r[0] for r in rows])
+    base = I.to_table1(wl.theta[pick])
+    steps = 1e-6 * widths
+    pts = np.empty((wl.n_win, 16, 8))
+    for k in range(8):
+        for s, sgn in enumerate((1.0, -1.0)):
+            u = base.copy()
+            u[:, k] += sgn * steps[:, k]
+            pts[:, 2 * k + s] = I.from_table1(u)
+    tab = wl.window_table().copy()
+    tab[:, 6] = np.arange(wl.n_win) * 16
+    tab[:, 7] = 16
+    fplan = api.Plan(ctx, tab, api.GB_FP64)
+    fplan.prepare(d, w)
+    lf = fplan.loglik(dev(pts.reshape(-1, 8))).cpu().numpy().reshape(wl.n_win, 16)
+    fd_u = (lf[:, 0::2] - lf[:, 1::2]) / (2 * steps)        # d logL / d u (Table I coordinates)
+    jac = np.ones((wl.n_win, 8))                              # d theta / d u
+    th0 = wl.theta[pick]
+    jac[:, 2] = 1.0 / np.cos(th0[:, 2])
+    jac[:, 4] = th0[:, 4] * math.log(10.0)
+    jac[:, 5] = -1.0 / np.sin(th0[:, 5])
+    g_u = grad[pick] * jac
+    scale = np.abs(fd_u) + np.abs(g_u) + 1e-3 * np.abs(g_u).max(axis=1, keepdims=True)
+    rel = np.abs(g_u - fd_u) / scale
+    banner(f"  central differences: median relative difference {np.median(rel):.1e}")
+    assert np.median(rel) < 1e-4
+
+
+def test_c5_full(oracle_lib, tuned):
+    banner("full size C5: 4,000 windows x 512 candidates, adaptive logL, 2 rows per window")
+    O = oracle_lib
+    wl = I.workload_c5(O.template_fn())
+    rho = _window_rho(O, wl)
+    prec_w = np.where(rho <= RHO_MIXED, api.GB_MIXED, api.GB_FP64)
+    table = np.concatenate([wl.window_table(), prec_w[:, None]], axis=1)
+    plan = api.Plan(tuned(wl.T), table, api.GB_PER_WINDOW)
+    d, w, th = _upload(wl)
+    plan.prepare(d, w)
+    l = plan.loglik(th).cpu().numpy()
+    rows = _sample_rows(wl, 2, np.random.default_rng(51))
+    w64, wmx = _check_rows(O, wl, l, rows, prec_w)
+    banner(f"  {int((prec_w == api.GB_MIXED).sum())} mixed windows; FP64 worst |dlogL| / bound {w64:.2f}; "
+           f"mixed worst error {wmx:.2e}")
+    assert w64 <= 1.0 and wmx <= BAR_MIXED

@@ -49,6 +49,23 @@ def test_waveform_fp64_matches_oracle(oracle_lib, ctx1, N, C):
     assert max(errs) <= 1e-10, max(errs)
 
 
+def test_waveform_high_frequency(oracle_lib, ctx1):
+    """30-60 mHz: the link transfer argument pi f L (1 +- k.n) / c exceeds 2 on some links, so the
+    sinc takes its quotient branch instead of the series."""
+    banner("waveform fp64 / mixed, 30-60 mHz, N=1024, C=3")
+    O = oracle_lib
+    th = _random_theta(np.random.default_rng(77), 23, f_lo=30e-3, f_hi=60e-3)
+    ho, fbo = O.waveform(th, 1024, 3, O.Geometry(I.T1))
+    for prec, bar in ((api.GB_FP64, 1e-10), (api.GB_MIXED, 5e-6)):
+        h, fb = ctx1.waveform(dev(th), 1024, 3, prec)
+        torch.cuda.synchronize()
+        h, fb = h.cpu().numpy(), fb.cpu().numpy()
+        assert np.array_equal(fb, fbo)
+        errs = np.array([rel_l2(h[b], ho[b]) for b in range(len(th))])
+        banner(f"  precision {prec}: max rel L2 {errs.max():.2e}")
+        assert errs.max() <= bar, (prec, errs.max())
+
+
 @pytest.mark.parametrize("N", [64, 256, 1024])
 def test_waveform_mixed_accuracy(oracle_lib, ctx1, N):
     banner(f"waveform mixed N={N}")
