@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--rho-mixed", type=float, default=8.0)
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--no-posterior", action="store_true")
+    ap.add_argument("--posterior-sources", type=int, default=3)
     ap.add_argument("--traffic", nargs=4, metavar=("K_FETCH_DIR", "K_WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="print the profiles/hbm_traffic.txt line from rocprofv3 --pmc outputs and exit")
     ap.add_argument("--tune-from", metavar="BENCH_JSON",
@@ -277,6 +279,10 @@ def main():
         for p in win_plans:
             p.close()
 
+    post = None
+    if not args.no_posterior:
+        post = posterior_leg(args.posterior_sources, log)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(wl, args.cpu_seconds, logl_mixed, rho_w, log)
@@ -300,10 +306,12 @@ def main():
         "speedup_vs_fp64": (round(adaptive["logl_evals_per_s"] / fp64["logl_evals_per_s"], 3) if fp64 else None),
         "speedup_basis": "logL evals/s of the MH stage, adaptive ragged vs plain FP64 per window",
         "roofline": roofline,
+        "posterior": post,
         "timed_region_ns": region.t,
         "cpu_baseline": cpu,
         "autotune": tune.strip().split("\n"),
         "library": library_hash(),
+        "kernel_src": kernel_source_hash(),
         "context": "paper: 1.8 s per posterior of 6 x 10,000 likelihoods on a Quadro RTX 4000 Mobile "
                    "(about 3.3e4 logL/s including chain and KDE); different hardware and work",
     }
@@ -444,7 +452,8 @@ def traffic_summary(k_fetch: str, k_write: str, c_fetch: str, c_write: str) -> s
     s_f = 8 * COPY_N / (copy_f * 1024.0)
     s_w = 8 * COPY_N / (copy_w * 1024.0)
     by = vals["FETCH_SIZE"] * 1024.0 * s_f + vals["WRITE_SIZE"] * 1024.0 * s_w
-    return (f"library={b['library']} kernel={kern} evals={b['roofline']['evals_per_launch']} bytes={by:.0f} "
+    return (f"kernel_src={b.get('kernel_src', '?')} library={b['library']} kernel={kern} "
+            f"evals={b['roofline']['evals_per_launch']} bytes={by:.0f} "
             f"fetch_kib={vals['FETCH_SIZE']:.1f} write_kib={vals['WRITE_SIZE']:.1f} "
             f"copy_scale_fetch={s_f:.4f} copy_scale_write={s_w:.4f}")
 
@@ -455,19 +464,34 @@ def library_hash() -> str:
     return hashlib.sha256(open(api.LIB_PATH, "rb").read()).hexdigest()[:16]
 
 
+KERNEL_SOURCES = ("gbx_device.h", "gbx_kernels.h", "gbx_variants.h", "k_f64_loglik.hip", "k_mixed_loglik.hip",
+                  "k_mixed_grad.hip", "k_waveform.hip")
+
+
+def kernel_source_hash() -> str:
+    """sha256[:16] of the sources the k_batch kernels are compiled from and of the compile flags:
+    a counter summary stays valid while these are unchanged."""
+    import hashlib
+    from paper_2307_03763_amd import build
+    h = hashlib.sha256(" ".join(build.FLAGS[:-2]).encode())
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2307_03763_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def committed_traffic(kernel: str, evals: int):
     """HBM bytes per launch of `kernel` from the committed counter summary
-    (profiles/hbm_traffic.txt, lines 'library=<hash> kernel=<name> evals=<n> bytes=<B>'),
-    scaled to `evals`; None when absent or taken with another build of the library."""
+    (profiles/hbm_traffic.txt, lines 'kernel_src=<hash> kernel=<name> evals=<n> bytes=<B> ...'),
+    scaled to `evals`; None when absent or taken from other kernel sources."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
     if not os.path.exists(path):
         return None
-    h = library_hash()
+    h = kernel_source_hash()
     for line in open(path):
         if line.lstrip().startswith("#"):
             continue
         f = dict(x.split("=", 1) for x in line.split() if "=" in x)
-        if f.get("library") == h and f.get("kernel") == kernel.replace(" ", ""):
+        if f.get("kernel_src") == h and f.get("kernel") == kernel.replace(" ", ""):
             return round(float(f["bytes"]) * evals / float(f["evals"]), 1)
     return None
 
@@ -503,6 +527,40 @@ def window_snr(api, ctx, wl, d, w):
     out = np.array([np.sqrt(hh[tab[i, 6]:tab[i, 6] + tab[i, 7]].max()) for i in range(wl.n_win)])
     p.close()
     return out
+
+
+def posterior_leg(n_sources, log):
+    """Algorithm 4 end to end for the target source of the C2 window (three overlapping GBs,
+    the other two subtracted): Fisher matrix, reduced box, six temperatures x 10,000 proposals
+    with pairwise-KDE proposals after the first; wall-clock seconds per source (host work
+    included), over `n_sources` repetitions with different random streams."""
+    import numpy as np
+    import torch
+
+    from paper_2307_03763_amd import api
+    from paper_2307_03763_amd import drivers as D
+    from paper_2307_03763_amd import inputs as I
+    ctx = api.context_for(I.T2)
+    wl = I.workload_c2(api.template_fn(ctx, api.GB_FP64), n_cand=1)
+    row = wl.window_table()[0]
+    be = D.GpuPosteriorBackend(ctx, row, torch.as_tensor(wl.data, device="cuda"),
+                               torch.as_tensor(wl.weights, device="cuda"))
+    src = wl.windows[0].sources[0]
+    box = wl.window_box(0)
+    D.annealed_posterior(be, src, box, np.random.default_rng(0), n=10000)   # warm-up (plans, code)
+    times, acc = [], []
+    for k in range(n_sources):
+        torch.cuda.synchronize()
+        t0 = time.time()
+        stages, _, _ = D.annealed_posterior(be, src, box, np.random.default_rng(100 + k), n=10000)
+        torch.cuda.synchronize()
+        times.append(time.time() - t0)
+        acc.append([s["n_accept"] for s in stages])
+    log(f"posterior: {np.median(times):.3f} s per source (6 x 10,000)")
+    return {"seconds_per_source": round(float(np.median(times)), 4), "temperatures": [15, 10, 5, 3, 2, 1],
+            "proposals_per_stage": 10000, "accepted_per_stage": acc[0],
+            "workload": "C2 target source (8 mHz, N=256, T=2^22*15 s), injected parameters as the MLE",
+            "context": "paper: 1.8 s per signal for the same six stages on a Quadro RTX 4000 Mobile"}
 
 
 def cpu_baseline(wl, seconds, logL_gpu, rho_w, log):

@@ -155,6 +155,32 @@ gb_status gb_autotune(gb_ctx* ctx, int reps, char* report, size_t report_len);
 gb_status gb_select_variant(gb_ctx* ctx, gb_precision precision, int mode, int N, int C,
                             int lanes_per_template, int waves_per_block, int min_waves_per_simd);
 
+/* Fisher information matrix of n sources, F_ij = <d_i h | d_j h> at theta (Sec. III G FIM
+ * equation; the derivatives of the template, as the paper's reading of its garbled
+ * "d_i p(d|theta)"), in Table I coordinates u (sin beta, log10 A and cos iota in place of
+ * beta, A, iota), by second-order forward differences
+ *   d_i h = (-3 h(u) + 4 h(u + e_i) - h(u + 2 e_i)) / (2 e_i)
+ * with per-source steps e (the paper takes 1e-9 of the prior widths; e_i = 0 leaves row and
+ * column i zero).  The templates are FP64 (gb_waveform) and the scalar product is summed over
+ * the C channels and the bins of the source's window with weights w, as in gb_loglik.
+ * theta, steps: device [n][8]; windows: host [n] (k0, W, N, C and data_off are used; one
+ * window per source); w: device, indexed by data_off; F: device [n][8][8].  Synchronous;
+ * allocates 17 templates of C x N per source of the largest (N, C) group.  GB_EINVAL on a
+ * bad window. */
+gb_status gb_fisher(gb_ctx* ctx, const double* theta, const double* steps, int n, const gb_window* windows,
+                    const double* w, double* F, void* stream);
+
+/* Log density of weighted 2-D Gaussian kernel density estimates (the pairwise KDE proposals
+ * of Sec. III G: (A, iota), (lambda, beta), (f, fdot)), summed over n_pairs pairs:
+ *   out[i] = sum_p log sum_j wts[p][j] N(x[i][p]; pts[p][j], L_p L_p^T)
+ * pts: device [n_pairs][m][2]; wts: device [n_pairs][m] (each pair's weights sum to one;
+ * zero weights allowed); chol: device [n_pairs][3] = (l00, l10, l11), the lower Cholesky
+ * factor of each pair's bandwidth matrix (l00, l11 > 0); x: device [q][n_pairs][2];
+ * out: device [q].  FP64, log-sum-exp (no underflow in the tails).  GB_EINVAL on bad
+ * sizes or null arrays. */
+gb_status gb_kde_logpdf(const double* pts, const double* wts, int n_pairs, int64_t m, const double* chol,
+                        const double* x, int64_t q, double* out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

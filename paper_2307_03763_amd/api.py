@@ -23,7 +23,7 @@ PRECISION = {"fp64": GB_FP64, "mixed": GB_MIXED, "per_window": GB_PER_WINDOW}
 
 EXPORTS = ("gb_create", "gb_destroy", "gb_last_error", "gb_waveform", "gb_plan_create",
            "gb_plan_destroy", "gb_window_prepare", "gb_loglik", "gb_loglik_grad", "gb_mh_step",
-           "gb_autotune", "gb_select_variant")
+           "gb_autotune", "gb_select_variant", "gb_fisher", "gb_kde_logpdf")
 
 
 class GbxError(RuntimeError):
@@ -80,6 +80,10 @@ def lib():
         L.gb_autotune.restype = st
         L.gb_select_variant.argtypes = [_vp, i, i, i, i, i, i, i]
         L.gb_select_variant.restype = st
+        L.gb_fisher.argtypes = [_vp, _vp, _vp, i, ctypes.POINTER(gb_window), _vp, _vp, _vp]
+        L.gb_fisher.restype = st
+        L.gb_kde_logpdf.argtypes = [_vp, _vp, i, i64, _vp, _vp, i64, _vp, _vp]
+        L.gb_kde_logpdf.restype = st
         _lib = L
     return _lib
 
@@ -188,6 +192,29 @@ def gb_select_variant(ctx: int, precision: int, mode: int, N: int, C: int, lanes
                       waves_per_block: int, min_waves_per_simd: int):
     _check(lib().gb_select_variant(ctx, precision, mode, N, C, lanes_per_template, waves_per_block,
                                    min_waves_per_simd), "gb_select_variant")
+
+
+def gb_fisher(ctx: int, theta: torch.Tensor, steps: torch.Tensor, table, w: torch.Tensor, stream=None) -> torch.Tensor:
+    """Fisher matrices [n, 8, 8] of the sources theta [n, 8] in Table I coordinates; table: one
+    window row per source (as Workload.window_table)."""
+    n = theta.shape[0]
+    F = torch.empty((n, 8, 8), dtype=torch.float64, device=theta.device)
+    wins = windows_array(table)
+    _check(lib().gb_fisher(ctx, _dev(theta, torch.float64, "theta"), _dev(steps, torch.float64, "steps"), n, wins,
+                           _dev(w, torch.float64, "w"), _dev(F, torch.float64, "F"), _stream(stream)), "gb_fisher")
+    return F
+
+
+def gb_kde_logpdf(pts: torch.Tensor, wts: torch.Tensor, chol: torch.Tensor, x: torch.Tensor, stream=None) -> torch.Tensor:
+    """Sum over parameter pairs of the log KDE density: pts [P, m, 2], wts [P, m], chol [P, 3],
+    x [q, P, 2] -> [q]."""
+    P, m = int(pts.shape[0]), int(pts.shape[1])
+    q = int(x.shape[0])
+    out = torch.empty(q, dtype=torch.float64, device=x.device)
+    _check(lib().gb_kde_logpdf(_dev(pts, torch.float64, "pts"), _dev(wts, torch.float64, "wts"), P, m,
+                               _dev(chol, torch.float64, "chol"), _dev(x, torch.float64, "x"), q,
+                               _dev(out, torch.float64, "out"), _stream(stream)), "gb_kde_logpdf")
+    return out
 
 
 def apply_tuning(ctx: int, report: str) -> int:

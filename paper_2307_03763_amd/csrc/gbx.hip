@@ -13,6 +13,7 @@
 
 #include "gbx_kernels.h"
 #include "gbx_chain.h"
+#include "gbx_post.h"
 #include "gbx_variants.h"
 
 using namespace gbx;
@@ -488,6 +489,83 @@ extern "C" gb_status gb_mh_step(gb_plan* p, const double* d, const double* w, co
   if (s != GB_OK) return s;
   hipLaunchKernelGGL(k_mh_chain, dim3((unsigned)p->wins.size()), dim3(1024), 0, (hipStream_t)stream, p->d_wins,
                      p->d_cw, logL, log_g, u, temperature, p->d_tree, p->d_jump, chain, n_accept);
+  HIPCHK(hipGetLastError());
+  return GB_OK;
+}
+
+// ------------------------------------------------------------------------------- posterior helpers
+extern "C" gb_status gb_fisher(gb_ctx* c, const double* theta, const double* steps, int n, const gb_window* windows,
+                               const double* w, double* F, void* stream) {
+  if (!c) return fail(GB_EINVAL, "gb_fisher: null context");
+  if (n < 0 || (n > 0 && (!windows || !theta || !steps || !w || !F))) return fail(GB_EINVAL, "gb_fisher: bad arguments");
+  if (n == 0) return GB_OK;
+  std::vector<FisherWin> fw(n);
+  for (int i = 0; i < n; ++i) {
+    const gb_window& g = windows[i];
+    if (!pow2_in_range(g.N)) return fail(GB_EINVAL, "gb_fisher: source %d: N = %d is not a power of two in [64, 1024]", i, g.N);
+    if (g.C != 2 && g.C != 3) return fail(GB_EINVAL, "gb_fisher: source %d: C = %d (must be 2 or 3)", i, g.C);
+    if (g.W < 1 || g.k0 < 0 || g.data_off < 0) return fail(GB_EINVAL, "gb_fisher: source %d: bad window", i);
+    fw[i].k0 = g.k0;
+    fw[i].data_off = g.data_off;
+    fw[i].W = g.W;
+    fw[i].pad = 0;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  FisherWin* d_fw = nullptr;
+  int32_t* d_idx = nullptr;
+  double *d_th = nullptr, *d_h = nullptr;
+  int64_t* d_fb = nullptr;
+  hipError_t e = hipMalloc(&d_fw, sizeof(FisherWin) * n);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_fw, fw.data(), sizeof(FisherWin) * n, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMalloc(&d_idx, sizeof(int32_t) * n);
+  gb_status status = GB_OK;
+  // one (N, C) group at a time: templates of its 17 points per source, then the reduction
+  std::vector<char> done(n, 0);
+  for (int i0 = 0; i0 < n && e == hipSuccess && status == GB_OK; ++i0) {
+    if (done[i0]) continue;
+    const int N = windows[i0].N, C = windows[i0].C;
+    std::vector<int32_t> idx;
+    for (int i = i0; i < n; ++i)
+      if (!done[i] && windows[i].N == N && windows[i].C == C) {
+        idx.push_back(i);
+        done[i] = 1;
+      }
+    const int m = (int)idx.size();
+    const int64_t B = (int64_t)m * kFdPoints;
+    e = hipMemcpyAsync(d_idx, idx.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(d_th);
+    (void)hipFree(d_h);
+    (void)hipFree(d_fb);
+    d_th = d_h = nullptr;
+    d_fb = nullptr;
+    if (e == hipSuccess) e = hipMalloc(&d_th, sizeof(double) * 8 * B);
+    if (e == hipSuccess) e = hipMalloc(&d_h, sizeof(double) * 2 * C * N * B);
+    if (e == hipSuccess) e = hipMalloc(&d_fb, sizeof(int64_t) * B);
+    if (e != hipSuccess) break;
+    hipLaunchKernelGGL(k_fisher_points, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, st, theta, steps, d_idx, m, d_th);
+    e = hipGetLastError();
+    if (e != hipSuccess) break;
+    status = gb_waveform(c, d_th, B, N, C, GB_FP64, d_h, d_fb, stream);
+    if (status != GB_OK) break;
+    hipLaunchKernelGGL(k_fisher_reduce, dim3((unsigned)m), dim3(256), 0, st, d_h, d_fb, d_idx, m, d_fw, w, steps, N, C, F);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  for (void* q : {(void*)d_fw, (void*)d_idx, (void*)d_th, (void*)d_h, (void*)d_fb}) (void)hipFree(q);
+  if (status != GB_OK) return status;
+  if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? GB_ENOMEM : GB_EHIP, "gb_fisher: %s", hipGetErrorString(e));
+  return GB_OK;
+}
+
+extern "C" gb_status gb_kde_logpdf(const double* pts, const double* wts, int n_pairs, int64_t m, const double* chol,
+                                   const double* x, int64_t q, double* out, void* stream) {
+  if (n_pairs < 1 || m < 0 || q < 0) return fail(GB_EINVAL, "gb_kde_logpdf: bad sizes");
+  if (q == 0) return GB_OK;
+  if (!pts || !wts || !chol || !x || !out) return fail(GB_EINVAL, "gb_kde_logpdf: null array");
+  if ((q + 255) / 256 > 0x7fffffff) return fail(GB_EINVAL, "gb_kde_logpdf: too many queries");
+  hipLaunchKernelGGL(k_kde_logpdf, dim3((unsigned)((q + 255) / 256)), dim3(256), 0, (hipStream_t)stream, pts, wts,
+                     n_pairs, m, chol, x, q, out);
   HIPCHK(hipGetLastError());
   return GB_OK;
 }

@@ -358,3 +358,137 @@ class PosteriorStage:
         if self.graph is None:
             raise RuntimeError("capture() first")
         self.graph.replay()
+
+
+# ---------------------------------------------------------------------------------------------
+# Annealed posterior (Algorithm 4 with the proposal updates of Sec. III G)
+
+KDE_PAIRS = ((4, 5), (3, 2), (0, 1))   # (log10 A, cos iota), (lambda, sin beta), (f0, fdot)
+UNIFORM_DIMS = (6, 7)                   # psi, phi0: kept in their narrow reduced-box ranges
+
+
+class UniformBox:
+    """Proposals uniform in a box of Table I coordinates (log g constant, taken as 0)."""
+
+    def __init__(self, lo, hi):
+        self.lo, self.hi = np.asarray(lo, dtype=np.float64), np.asarray(hi, dtype=np.float64)
+
+    def draw(self, rng, n, backend=None):
+        u = self.lo + (self.hi - self.lo) * rng.random((n, 8))
+        return u, np.zeros(n)
+
+
+class PairKDE:
+    """Proposal distribution of the later annealing stages: a weighted 2-D Gaussian KDE of the
+    previous chain for each of the pairs (A, iota), (lambda, beta), (f, fdot) in Table I
+    coordinates, and uniform psi, phi0 in the reduced box.  The kernel points are the chain's
+    distinct states weighted by how often the chain holds them; bandwidth by Scott's rule,
+    H = n_eff^(-1/3) * (weighted covariance of the pair).  Draws outside the prior box are drawn
+    again (the truncation changes g only by a constant, which cancels in the acceptance ratio)."""
+
+    def __init__(self, states_u, lo_prior, hi_prior, lo_box, hi_box):
+        uniq, counts = np.unique(states_u, axis=0, return_counts=True)
+        self.pts = uniq
+        self.w = counts / counts.sum()
+        n_eff = 1.0 / np.sum(self.w ** 2)
+        self.chol = []
+        for a, b in KDE_PAIRS:
+            xy = uniq[:, [a, b]]
+            mu = self.w @ xy
+            d = xy - mu
+            cov = (self.w[:, None] * d).T @ d / max(1e-300, 1.0 - np.sum(self.w ** 2))
+            cov = cov + np.diag(1e-12 * np.maximum(np.abs(np.diag(cov)), 1e-300))
+            H = cov * n_eff ** (-1.0 / 3.0)
+            L = np.linalg.cholesky(H)
+            self.chol.append([L[0, 0], L[1, 0], L[1, 1]])
+        self.chol = np.array(self.chol)
+        self.lo_p, self.hi_p = np.asarray(lo_prior), np.asarray(hi_prior)
+        self.lo_b, self.hi_b = np.asarray(lo_box), np.asarray(hi_box)
+
+    def draw(self, rng, n, backend):
+        out = np.empty((n, 8))
+        filled = 0
+        for _ in range(1000):
+            if filled >= n:
+                break
+            k = 2 * (n - filled) + 16
+            u = np.empty((k, 8))
+            for p, (a, b) in enumerate(KDE_PAIRS):
+                j = rng.choice(len(self.pts), size=k, p=self.w)
+                L = np.array([[self.chol[p, 0], 0.0], [self.chol[p, 1], self.chol[p, 2]]])
+                u[:, [a, b]] = self.pts[j][:, [a, b]] + rng.standard_normal((k, 2)) @ L.T
+            for d in UNIFORM_DIMS:
+                u[:, d] = self.lo_b[d] + (self.hi_b[d] - self.lo_b[d]) * rng.random(k)
+            # periodic angles (lambda, psi, phi0) are not bounded by the prior box
+            ok = np.all((u[:, [0, 1, 2, 4, 5]] >= self.lo_p[[0, 1, 2, 4, 5]]) &
+                        (u[:, [0, 1, 2, 4, 5]] <= self.hi_p[[0, 1, 2, 4, 5]]), axis=1)
+            take = u[ok][: n - filled]
+            out[filled:filled + len(take)] = take
+            filled += len(take)
+        if filled < n:
+            raise RuntimeError("KDE proposals keep leaving the prior box")
+        x = np.stack([out[:, [a, b]] for a, b in KDE_PAIRS], axis=1)          # [n, 3, 2]
+        pts = np.stack([self.pts[:, [a, b]] for a, b in KDE_PAIRS], axis=0)   # [3, m, 2]
+        wts = np.broadcast_to(self.w, (len(KDE_PAIRS), len(self.w)))
+        log_g = backend.kde_logpdf(pts, np.ascontiguousarray(wts), self.chol, x)
+        return out, log_g
+
+
+def annealed_posterior(backend, theta_mle, box: I.PriorBox, rng: np.random.Generator,
+                       temps=(15.0, 10.0, 5.0, 3.0, 2.0, 1.0), n: int = 10000, fd_step: float = 1e-9):
+    """Algorithm 4 for one source: the Fisher matrix at theta_mle (finite differences with steps
+    of ``fd_step`` of the Table I widths) gives sigma and the reduced box (Sec. III G); then for
+    every temperature n proposals (uniform in the reduced box first, then from the pairwise KDE
+    of the previous chain), their logL in parallel and the independent-proposal chain.
+    Returns (per-stage list of dicts with T, states (theta of the chain, [n, 8]), n_accept,
+    logL of the states; the reduced box (lo, hi); sigma in Table I coordinates)."""
+    theta_mle = np.asarray(theta_mle, dtype=np.float64)
+    F = backend.fisher(theta_mle[None, :], (fd_step * box.width)[None, :])[0]
+    sigma = np.sqrt(np.diag(np.linalg.inv(F)))
+    lo, hi = I.reduced_box(theta_mle, box, sigma)
+    sampler = UniformBox(lo, hi)
+    stages = []
+    for T in temps:
+        props_u, log_g = sampler.draw(rng, n, backend)
+        props = I.from_table1(props_u)
+        uni = rng.random(n)
+        logL, chain, nacc = backend.mh(props, log_g, uni, T)
+        states_u = props_u[chain]
+        stages.append({"T": float(T), "states": props[chain], "n_accept": int(nacc), "logL": logL[chain]})
+        sampler = PairKDE(states_u, box.lo, box.hi, lo, hi)
+    return stages, (lo, hi), sigma
+
+
+class GpuPosteriorBackend:
+    """The library calls of the annealed posterior for one window: gb_fisher, gb_mh_step and
+    gb_kde_logpdf (plans cached per proposal count)."""
+
+    def __init__(self, ctx, window_row, d, w):
+        import torch
+        from . import api
+        self.api, self.torch = api, torch
+        self.ctx = ctx
+        self.row = np.asarray(window_row, dtype=np.int64).copy()
+        self.d, self.w = d, w
+        self.plans = {}
+
+    def _dev(self, a):
+        return self.torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+
+    def fisher(self, theta, steps):
+        rows = np.repeat(self.row[None, :], len(theta), axis=0)
+        return self.api.gb_fisher(self.ctx.handle, self._dev(theta), self._dev(steps), rows, self.w).cpu().numpy()
+
+    def mh(self, theta, log_g, u, T):
+        n = len(theta)
+        if n not in self.plans:
+            row = self.row.copy()
+            row[6], row[7] = 0, n
+            p = self.api.Plan(self.ctx, row[None, :], self.api.GB_FP64)
+            p.prepare(self.d, self.w)
+            self.plans[n] = p
+        l, ch, na = self.plans[n].mh_step(self._dev(theta), self._dev(log_g), self._dev(u), T)
+        return l.cpu().numpy(), ch.cpu().numpy(), int(na.cpu()[0])
+
+    def kde_logpdf(self, pts, wts, chol, x):
+        return self.api.gb_kde_logpdf(self._dev(pts), self._dev(wts), self._dev(chol), self._dev(x)).cpu().numpy()
