@@ -170,6 +170,19 @@ gb_status gb_select_variant(gb_ctx* ctx, gb_precision precision, int mode, int N
 gb_status gb_fisher(gb_ctx* ctx, const double* theta, const double* steps, int n, const gb_window* windows,
                     const double* w, double* F, void* stream);
 
+/* d_out = d_in + sign * (sum of the templates of the listed sources, each placed in its own
+ * window): the residuals of the search (Algorithm 2: data minus the signals found so far) and
+ * of the posterior stage.  FP64 templates at the window's N and C (gb_waveform); bins outside the
+ * window are dropped; within a window the sources are added in their listed order, so the
+ * result is deterministic.  theta: device [n_src][8]; src_win: HOST int32 [n_src], the window
+ * (index into windows) of each source; windows: host [n_win] (k0, W, N, C and data_off are
+ * used); d_in, d_out: device complex128 indexed by data_off, d_out may equal d_in; every
+ * window's block of d_out is written (a copy of d_in where the window has no source).
+ * Synchronous; allocates the templates.  GB_EINVAL on a bad window or window index. */
+gb_status gb_add_templates(gb_ctx* ctx, const gb_window* windows, int n_win, const double* theta,
+                           const int32_t* src_win, int n_src, double sign, const double* d_in, double* d_out,
+                           void* stream);
+
 /* Log density of weighted 2-D Gaussian kernel density estimates (the pairwise KDE proposals
  * of Sec. III G: (A, iota), (lambda, beta), (f, fdot)), summed over n_pairs pairs:
  *   out[i] = sum_p log sum_j wts[p][j] N(x[i][p]; pts[p][j], L_p L_p^T)

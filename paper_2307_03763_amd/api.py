@@ -23,7 +23,7 @@ PRECISION = {"fp64": GB_FP64, "mixed": GB_MIXED, "per_window": GB_PER_WINDOW}
 
 EXPORTS = ("gb_create", "gb_destroy", "gb_last_error", "gb_waveform", "gb_plan_create",
            "gb_plan_destroy", "gb_window_prepare", "gb_loglik", "gb_loglik_grad", "gb_mh_step",
-           "gb_autotune", "gb_select_variant", "gb_fisher", "gb_kde_logpdf")
+           "gb_autotune", "gb_select_variant", "gb_fisher", "gb_kde_logpdf", "gb_add_templates")
 
 
 class GbxError(RuntimeError):
@@ -84,6 +84,9 @@ def lib():
         L.gb_fisher.restype = st
         L.gb_kde_logpdf.argtypes = [_vp, _vp, i, i64, _vp, _vp, i64, _vp, _vp]
         L.gb_kde_logpdf.restype = st
+        L.gb_add_templates.argtypes = [_vp, ctypes.POINTER(gb_window), i, _vp, ctypes.POINTER(ctypes.c_int32), i, d,
+                                       _vp, _vp, _vp]
+        L.gb_add_templates.restype = st
         _lib = L
     return _lib
 
@@ -215,6 +218,23 @@ def gb_kde_logpdf(pts: torch.Tensor, wts: torch.Tensor, chol: torch.Tensor, x: t
                                _dev(chol, torch.float64, "chol"), _dev(x, torch.float64, "x"), q,
                                _dev(out, torch.float64, "out"), _stream(stream)), "gb_kde_logpdf")
     return out
+
+
+def gb_add_templates(ctx: int, table, theta: torch.Tensor, src_win, sign: float, d_in: torch.Tensor,
+                     d_out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """d_out = d_in + sign * sum of the templates of theta [n, 8], source s placed in window
+    src_win[s] of table.  Returns d_out (a new tensor unless given)."""
+    wins = windows_array(table)
+    sw = np.ascontiguousarray(np.asarray(src_win, dtype=np.int32))
+    if d_out is None:
+        d_out = torch.empty_like(d_in)
+    n_src = int(len(sw))
+    th = theta if n_src else torch.zeros((1, 8), dtype=torch.float64, device=d_in.device)
+    _check(lib().gb_add_templates(ctx, wins, len(wins), _dev(th, torch.float64, "theta"),
+                                  sw.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), n_src, float(sign),
+                                  _real_view(d_in).data_ptr(), _real_view(d_out).data_ptr(), _stream(stream)),
+           "gb_add_templates")
+    return d_out
 
 
 def apply_tuning(ctx: int, report: str) -> int:

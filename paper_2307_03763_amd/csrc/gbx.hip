@@ -558,6 +558,105 @@ extern "C" gb_status gb_fisher(gb_ctx* c, const double* theta, const double* ste
   return GB_OK;
 }
 
+extern "C" gb_status gb_add_templates(gb_ctx* c, const gb_window* windows, int n_win, const double* theta,
+                                      const int32_t* src_win, int n_src, double sign, const double* d_in,
+                                      double* d_out, void* stream) {
+  if (!c) return fail(GB_EINVAL, "gb_add_templates: null context");
+  if (n_win < 0 || n_src < 0 || (n_win > 0 && (!windows || !d_in || !d_out)) || (n_src > 0 && (!theta || !src_win)))
+    return fail(GB_EINVAL, "gb_add_templates: bad arguments");
+  if (n_win == 0) return GB_OK;
+  for (int i = 0; i < n_win; ++i) {
+    const gb_window& g = windows[i];
+    if (!pow2_in_range(g.N) || (g.C != 2 && g.C != 3) || g.W < 1 || g.k0 < 0 || g.data_off < 0)
+      return fail(GB_EINVAL, "gb_add_templates: window %d: bad N, C, W, k0 or offset", i);
+  }
+  for (int s = 0; s < n_src; ++s)
+    if (src_win[s] < 0 || src_win[s] >= n_win) return fail(GB_EINVAL, "gb_add_templates: source %d: bad window index", s);
+  hipStream_t st = (hipStream_t)stream;
+  // (N, C) groups of windows; per group the list of its sources and their templates
+  std::vector<AddWin> aw(n_win);
+  std::vector<void*> bufs;
+  std::vector<std::vector<int32_t>> win_src(n_win);
+  std::vector<int32_t> pos_in_group(n_src, -1);
+  hipError_t e = hipSuccess;
+  gb_status status = GB_OK;
+  std::vector<char> done(n_win, 0);
+  for (int w0 = 0; w0 < n_win && e == hipSuccess && status == GB_OK; ++w0) {
+    if (done[w0]) continue;
+    const int N = windows[w0].N, C = windows[w0].C;
+    std::vector<int32_t> gsrc;  // sources of this group, in input order
+    for (int s = 0; s < n_src; ++s)
+      if (windows[src_win[s]].N == N && windows[src_win[s]].C == C) {
+        pos_in_group[s] = (int32_t)gsrc.size();
+        gsrc.push_back(s);
+      }
+    double* d_th = nullptr;
+    double* d_h = nullptr;
+    int64_t* d_fb = nullptr;
+    int32_t* d_src = nullptr;
+    const int m = (int)gsrc.size();
+    std::vector<int32_t> lists;  // per window of the group: its sources (group positions)
+    std::vector<int> win_of_group;
+    for (int w = w0; w < n_win; ++w)
+      if (!done[w] && windows[w].N == N && windows[w].C == C) {
+        done[w] = 1;
+        win_of_group.push_back(w);
+      }
+    for (int s : gsrc) win_src[src_win[s]].push_back(pos_in_group[s]);
+    std::vector<int64_t> starts;
+    for (int w : win_of_group) {
+      starts.push_back((int64_t)lists.size());
+      lists.insert(lists.end(), win_src[w].begin(), win_src[w].end());
+    }
+    int32_t* d_gidx = nullptr;
+    if (m > 0) {
+      // gather the group's parameters
+      e = hipMalloc(&d_th, sizeof(double) * 8 * m);
+      if (e == hipSuccess) e = hipMalloc(&d_gidx, sizeof(int32_t) * m);
+      if (e == hipSuccess) e = hipMemcpyAsync(d_gidx, gsrc.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, st);
+      if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)((8 * m + 255) / 256)), dim3(256), 0, st, theta, d_gidx, m, d_th);
+        e = hipGetLastError();
+      }
+      if (e == hipSuccess) e = hipMalloc(&d_h, sizeof(double) * 2 * (size_t)C * N * m);
+      if (e == hipSuccess) e = hipMalloc(&d_fb, sizeof(int64_t) * m);
+      if (e == hipSuccess) status = gb_waveform(c, d_th, m, N, C, GB_FP64, d_h, d_fb, stream);
+    }
+    if (e == hipSuccess && !lists.empty()) {
+      e = hipMalloc(&d_src, sizeof(int32_t) * lists.size());
+      if (e == hipSuccess) e = hipMemcpyAsync(d_src, lists.data(), sizeof(int32_t) * lists.size(), hipMemcpyHostToDevice, st);
+    }
+    for (void* b : {(void*)d_th, (void*)d_h, (void*)d_fb, (void*)d_src, (void*)d_gidx})
+      if (b) bufs.push_back(b);
+    for (size_t q = 0; q < win_of_group.size(); ++q) {
+      const int w = win_of_group[q];
+      aw[w].k0 = windows[w].k0;
+      aw[w].data_off = windows[w].data_off;
+      aw[w].h = d_h;
+      aw[w].fb = d_fb;
+      aw[w].src = d_src ? d_src + starts[q] : nullptr;
+      aw[w].W = windows[w].W;
+      aw[w].N = N;
+      aw[w].C = C;
+      aw[w].n_src = (int32_t)win_src[w].size();
+    }
+  }
+  AddWin* d_aw = nullptr;
+  if (e == hipSuccess && status == GB_OK) e = hipMalloc(&d_aw, sizeof(AddWin) * n_win);
+  if (e == hipSuccess && status == GB_OK)
+    e = hipMemcpyAsync(d_aw, aw.data(), sizeof(AddWin) * n_win, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && status == GB_OK) {
+    hipLaunchKernelGGL(k_add_templates, dim3((unsigned)n_win), dim3(256), 0, st, d_aw, sign, d_in, d_out);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(d_aw);
+  for (void* b : bufs) (void)hipFree(b);
+  if (status != GB_OK) return status;
+  if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? GB_ENOMEM : GB_EHIP, "gb_add_templates: %s", hipGetErrorString(e));
+  return GB_OK;
+}
+
 extern "C" gb_status gb_kde_logpdf(const double* pts, const double* wts, int n_pairs, int64_t m, const double* chol,
                                    const double* x, int64_t q, double* out, void* stream) {
   if (n_pairs < 1 || m < 0 || q < 0) return fail(GB_EINVAL, "gb_kde_logpdf: bad sizes");

@@ -1,6 +1,7 @@
-// Device code of the posterior stage's helpers: the Fisher information matrix by finite
-// differences of templates, and weighted 2-D kernel density estimates (Sec. III G).  Included
-// by the host-side translation unit only (the kernels are not templates).
+// Device code of the search and posterior stages' helpers: the Fisher information matrix by
+// finite differences of templates, weighted 2-D kernel density estimates (Sec. III G), and
+// data minus (or plus) lists of templates (Algorithm 2 residuals).  Included by the host-side
+// translation unit only (the kernels are not templates).
 #pragma once
 #include "gbx_kernels.h"
 
@@ -171,6 +172,46 @@ __global__ void __launch_bounds__(256) k_kde_logpdf(const double* __restrict__ p
     total += M + log(S) - log(2.0 * kPi * l00 * l11);
   }
   if (act) out[g] = total;
+}
+
+// Rows idx[0..m) of an [n][8] parameter array, gathered into out [m][8].
+__global__ void __launch_bounds__(256) k_gather_rows(const double* __restrict__ theta, const int32_t* __restrict__ idx,
+                                                     int m, double* __restrict__ out) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= 8 * m) return;
+  out[g] = theta[8 * (int64_t)idx[g / 8] + g % 8];
+}
+
+// One window of gb_add_templates: its bins, and where its sources' templates are.
+struct AddWin {
+  int64_t k0, data_off;
+  const double* h;       // complex templates [n][C][N] of the window's (N, C) group
+  const int64_t* fb;     // their first bins
+  const int32_t* src;    // indices (within the group's template list) of the window's sources
+  int32_t W, N, C, n_src;
+};
+
+// d_out = d_in + sign * sum of the window's templates, bin by bin, the sources in their listed
+// order (deterministic).  One workgroup per window.
+__global__ void __launch_bounds__(256) k_add_templates(const AddWin* __restrict__ wins, double sign,
+                                                       const double* d_in, double* d_out) {
+  const AddWin aw = wins[blockIdx.x];
+  for (int64_t e = threadIdx.x; e < (int64_t)aw.C * aw.W; e += blockDim.x) {
+    const int c = (int)(e / aw.W);
+    const int64_t k = aw.k0 + e % aw.W;
+    double re = 0.0, im = 0.0;
+    for (int s = 0; s < aw.n_src; ++s) {
+      const int j = aw.src[s];
+      const int64_t off = k - aw.fb[j];
+      if (off < 0 || off >= aw.N) continue;
+      const double* hv = aw.h + 2 * (((int64_t)j * aw.C + c) * aw.N + off);
+      re += hv[0];
+      im += hv[1];
+    }
+    const int64_t g = 2 * (aw.data_off + e);
+    d_out[g] = d_in[g] + sign * re;
+    d_out[g + 1] = d_in[g + 1] + sign * im;
+  }
 }
 
 }  // namespace gbx

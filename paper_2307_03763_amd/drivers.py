@@ -492,3 +492,100 @@ class GpuPosteriorBackend:
 
     def kde_logpdf(self, pts, wts, chol, x):
         return self.api.gb_kde_logpdf(self._dev(pts), self._dev(wts), self._dev(chol), self._dev(x)).cpu().numpy()
+
+
+# ---------------------------------------------------------------------------------------------
+# Search within frequency segments (Algorithm 2), for many segments at once
+
+def _rho_of(comps):
+    with np.errstate(invalid="ignore", divide="ignore"):
+        r = comps[:, 0] / np.sqrt(comps[:, 1])
+    return np.where(np.isfinite(r), r, -np.inf)
+
+
+def local_search(backend, seg_edges, rng: np.random.Generator, n_signals: int, rho_threshold: float = 9.0,
+                 n_searches: int = 3, pop: int = 512, generations: int = 50, keep: int = 8,
+                 polish_iterations: int = 20, scale_frac: float = 1e-3, joint_sweeps: int = 2):
+    """Algorithm 2 for every window of the backend at once (each window = one padded segment;
+    seg_edges [n_win, 2] = the unpadded segment's edges in Hz).  Per signal: n_searches DE +
+    polish searches on the residual (the first one ends the window when rho on the analysed data
+    is at most rho_threshold - 2), the best of them by rho on the residual ends the window when
+    its rho on the analysed data is at most rho_threshold; a signal inside the unpadded segment
+    joins theta_in, one outside joins theta_out; then theta_in is refined jointly on the data
+    minus theta_out (block-coordinate polish: each source on the data minus all other found
+    sources, ``joint_sweeps`` sweeps), and the residual becomes the data minus all found
+    signals.  Returns (theta_in, theta_out): per window a list of parameter vectors."""
+    n_win = backend.n_win
+    seg = np.asarray(seg_edges, dtype=np.float64)
+    boxes = backend.boxes
+    widths = np.stack([b.width for b in boxes])
+    found_in = [[] for _ in range(n_win)]
+    found_out = [[] for _ in range(n_win)]
+    active = np.ones(n_win, dtype=bool)
+    backend.set_residual(found_in, found_out)
+    for _ in range(n_signals):
+        if not active.any():
+            break
+        best_th = np.zeros((n_win, 8))
+        best_rho = np.full(n_win, -np.inf)
+        best_rho_an = np.full(n_win, -np.inf)
+        for j in range(n_searches):
+            th, _ = search(backend, boxes, rng, pop=pop, generations=generations, keep=keep,
+                           polish_iterations=polish_iterations, scale_frac=scale_frac)
+            rho_res = _rho_of(backend.loglik(th)[1])
+            rho_an = backend.rho_analyze(th)
+            if j == 0:
+                active &= ~(rho_an <= rho_threshold - 2.0)
+            better = rho_res > best_rho
+            best_th[better], best_rho[better], best_rho_an[better] = th[better], rho_res[better], rho_an[better]
+        active &= ~(best_rho_an <= rho_threshold)
+        for i in np.nonzero(active)[0]:
+            inside = seg[i, 0] <= best_th[i, 0] < seg[i, 1]
+            (found_in if inside else found_out)[i].append(best_th[i].copy())
+        # joint refinement of the sources inside, each on the data minus all other found sources
+        k_max = max((len(f) for f in found_in), default=0)
+        for _ in range(joint_sweeps if k_max else 0):
+            for k in range(k_max):
+                has = np.array([len(found_in[i]) > k for i in range(n_win)]) & active
+                if not has.any():
+                    continue
+                backend.set_residual([[t for m, t in enumerate(found_in[i]) if m != k or not has[i]]
+                                      for i in range(n_win)], found_out)
+                start = np.stack([found_in[i][k] if has[i] else _box_centre(boxes[i]) for i in range(n_win)])
+                th, _ = polish(backend, start[:, None, :], (scale_frac * widths)[:, None, :],
+                               iterations=polish_iterations)
+                for i in np.nonzero(has)[0]:
+                    found_in[i][k] = th[i, 0].copy()
+        backend.set_residual(found_in, found_out)
+    return found_in, found_out
+
+
+def _box_centre(box: I.PriorBox) -> np.ndarray:
+    return I.from_table1(0.5 * (box.lo + box.hi))
+
+
+class GpuSearchBackend(GpuBackend):
+    """The library calls of local_search for the windows of ``table``: likelihoods and gradients
+    on the current residual (data minus the sources found so far, formed by gb_add_templates),
+    and rho on the analysed data itself."""
+
+    def __init__(self, ctx, table, d, w, boxes, precision_logl: int, precision_grad: Optional[int] = None):
+        super().__init__(ctx, table, d.clone(), w, precision_logl, precision_grad)
+        self.d_analyze = d
+        self.boxes = list(boxes)
+        self.analyze = GpuBackend(ctx, table, d, w, self.api.GB_FP64)
+
+    def set_residual(self, *lists):
+        theta, src = [], []
+        for lst in lists:
+            for i, srcs in enumerate(lst):
+                for t in srcs:
+                    theta.append(t)
+                    src.append(i)
+        th = self.torch.as_tensor(np.array(theta).reshape(-1, 8), dtype=self.torch.float64, device="cuda")
+        self.api.gb_add_templates(self.ctx.handle, self.table, th, src, -1.0, self.d_analyze, self.d)
+        for p in self.plans.values():
+            p.prepare(self.d, self.w)
+
+    def rho_analyze(self, theta):
+        return _rho_of(self.analyze.loglik(theta)[1])
