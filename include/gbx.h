@@ -184,14 +184,17 @@ gb_status gb_add_templates(gb_ctx* ctx, const gb_window* windows, int n_win, con
                            void* stream);
 
 /* Log density of weighted 2-D Gaussian kernel density estimates (the pairwise KDE proposals
- * of Sec. III G: (A, iota), (lambda, beta), (f, fdot)), summed over n_pairs pairs:
- *   out[i] = sum_p log sum_j wts[p][j] N(x[i][p]; pts[p][j], L_p L_p^T)
- * pts: device [n_pairs][m][2]; wts: device [n_pairs][m] (each pair's weights sum to one;
- * zero weights allowed); chol: device [n_pairs][3] = (l00, l10, l11), the lower Cholesky
- * factor of each pair's bandwidth matrix (l00, l11 > 0); x: device [q][n_pairs][2];
- * out: device [q].  FP64, log-sum-exp (no underflow in the tails).  GB_EINVAL on bad
- * sizes or null arrays. */
-gb_status gb_kde_logpdf(const double* pts, const double* wts, int n_pairs, int64_t m, const double* chol,
+ * of Sec. III G: (A, iota), (lambda, beta), (f, fdot)), summed over n_pairs pairs, for
+ * n_sets independent sets (one per source, so that many sources' annealing stages share a
+ * launch):
+ *   out[s][i] = sum_p log sum_j wts[s][p][j] N(x[s][i][p]; pts[s][p][j], L_sp L_sp^T)
+ * pts: device [n_sets][n_pairs][m][2]; wts: device [n_sets][n_pairs][m] (each pair's weights
+ * sum to one; zero weights allowed, so sets with fewer points are padded to m); chol: device
+ * [n_sets][n_pairs][3] = (l00, l10, l11), the lower Cholesky factor of each bandwidth matrix
+ * (l00, l11 > 0); x: device [n_sets][q][n_pairs][2]; out: device [n_sets][q].  FP64,
+ * log-sum-exp (no underflow in the tails).  GB_EINVAL on bad sizes (n_sets above 65535) or
+ * null arrays. */
+gb_status gb_kde_logpdf(const double* pts, const double* wts, int n_sets, int n_pairs, int64_t m, const double* chol,
                         const double* x, int64_t q, double* out, void* stream);
 
 #ifdef __cplusplus

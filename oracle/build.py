@@ -12,11 +12,11 @@ OUT = os.path.join(HERE, "liboracle.so")
 def build(verbose: bool = False) -> str:
     # -ffp-contract=off: every product and sum rounded separately (no fused multiply-add)
     cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
-           "-Wall", "-Wextra", "-o", OUT + ".tmp", SRC]
+           "-Wall", "-Wextra", "-o", f"{OUT}.{os.getpid()}.tmp", SRC]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(OUT + ".tmp", OUT)
+    os.replace(f"{OUT}.{os.getpid()}.tmp", OUT)
     return OUT
 
 

@@ -82,7 +82,7 @@ def lib():
         L.gb_select_variant.restype = st
         L.gb_fisher.argtypes = [_vp, _vp, _vp, i, ctypes.POINTER(gb_window), _vp, _vp, _vp]
         L.gb_fisher.restype = st
-        L.gb_kde_logpdf.argtypes = [_vp, _vp, i, i64, _vp, _vp, i64, _vp, _vp]
+        L.gb_kde_logpdf.argtypes = [_vp, _vp, i, i, i64, _vp, _vp, i64, _vp, _vp]
         L.gb_kde_logpdf.restype = st
         L.gb_add_templates.argtypes = [_vp, ctypes.POINTER(gb_window), i, _vp, ctypes.POINTER(ctypes.c_int32), i, d,
                                        _vp, _vp, _vp]
@@ -210,11 +210,17 @@ def gb_fisher(ctx: int, theta: torch.Tensor, steps: torch.Tensor, table, w: torc
 
 def gb_kde_logpdf(pts: torch.Tensor, wts: torch.Tensor, chol: torch.Tensor, x: torch.Tensor, stream=None) -> torch.Tensor:
     """Sum over parameter pairs of the log KDE density: pts [P, m, 2], wts [P, m], chol [P, 3],
-    x [q, P, 2] -> [q]."""
-    P, m = int(pts.shape[0]), int(pts.shape[1])
-    q = int(x.shape[0])
-    out = torch.empty(q, dtype=torch.float64, device=x.device)
-    _check(lib().gb_kde_logpdf(_dev(pts, torch.float64, "pts"), _dev(wts, torch.float64, "wts"), P, m,
+    x [q, P, 2] -> [q]; or S independent sets: pts [S, P, m, 2], wts [S, P, m], chol [S, P, 3],
+    x [S, q, P, 2] -> [S, q]."""
+    one = pts.dim() == 3
+    S = 1 if one else int(pts.shape[0])
+    P, m = int(pts.shape[-3]), int(pts.shape[-2])
+    q = int(x.shape[-3])
+    if (tuple(wts.shape[-2:]) != (P, m) or tuple(chol.shape[-2:]) != (P, 3) or tuple(x.shape[-2:]) != (P, 2)
+            or (not one and (wts.shape[0] != S or chol.shape[0] != S or x.shape[0] != S))):
+        raise ValueError("gb_kde_logpdf: inconsistent shapes")
+    out = torch.empty((q,) if one else (S, q), dtype=torch.float64, device=x.device)
+    _check(lib().gb_kde_logpdf(_dev(pts, torch.float64, "pts"), _dev(wts, torch.float64, "wts"), S, P, m,
                                _dev(chol, torch.float64, "chol"), _dev(x, torch.float64, "x"), q,
                                _dev(out, torch.float64, "out"), _stream(stream)), "gb_kde_logpdf")
     return out

@@ -657,14 +657,14 @@ extern "C" gb_status gb_add_templates(gb_ctx* c, const gb_window* windows, int n
   return GB_OK;
 }
 
-extern "C" gb_status gb_kde_logpdf(const double* pts, const double* wts, int n_pairs, int64_t m, const double* chol,
-                                   const double* x, int64_t q, double* out, void* stream) {
-  if (n_pairs < 1 || m < 0 || q < 0) return fail(GB_EINVAL, "gb_kde_logpdf: bad sizes");
-  if (q == 0) return GB_OK;
+extern "C" gb_status gb_kde_logpdf(const double* pts, const double* wts, int n_sets, int n_pairs, int64_t m,
+                                   const double* chol, const double* x, int64_t q, double* out, void* stream) {
+  if (n_sets < 0 || n_sets > 65535 || n_pairs < 1 || m < 0 || q < 0) return fail(GB_EINVAL, "gb_kde_logpdf: bad sizes");
+  if (q == 0 || n_sets == 0) return GB_OK;
   if (!pts || !wts || !chol || !x || !out) return fail(GB_EINVAL, "gb_kde_logpdf: null array");
   if ((q + 255) / 256 > 0x7fffffff) return fail(GB_EINVAL, "gb_kde_logpdf: too many queries");
-  hipLaunchKernelGGL(k_kde_logpdf, dim3((unsigned)((q + 255) / 256)), dim3(256), 0, (hipStream_t)stream, pts, wts,
-                     n_pairs, m, chol, x, q, out);
+  hipLaunchKernelGGL(k_kde_logpdf, dim3((unsigned)((q + 255) / 256), (unsigned)n_sets), dim3(256), 0,
+                     (hipStream_t)stream, pts, wts, n_pairs, m, chol, x, q, out);
   HIPCHK(hipGetLastError());
   return GB_OK;
 }

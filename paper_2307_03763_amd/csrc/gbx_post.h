@@ -120,7 +120,8 @@ __global__ void __launch_bounds__(256) k_fisher_reduce(const double* __restrict_
   }
 }
 
-// Weighted 2-D Gaussian kernel density estimates of P parameter pairs, evaluated at q points:
+// Weighted 2-D Gaussian kernel density estimates of P parameter pairs, evaluated at q points,
+// for independent sets (one per source; blockIdx.y):
 //   out[i] = sum_p log( sum_j w_pj N(x_ip; y_pj, L_p L_p^T) ),
 // with the bandwidth's Cholesky factor L_p = [[l00, 0], [l10, l11]].  One thread per query;
 // the kernel points are staged through LDS in tiles and summed by a running log-sum-exp.
@@ -129,6 +130,12 @@ __global__ void __launch_bounds__(256) k_kde_logpdf(const double* __restrict__ p
                                                     const double* __restrict__ x, int64_t q, double* __restrict__ out) {
   __shared__ double s_y[256][3];
   const int tid = threadIdx.x;
+  const int64_t set = blockIdx.y;
+  pts += set * P * m * 2;
+  wts += set * P * m;
+  chol += set * P * 3;
+  x += set * q * P * 2;
+  out += set * q;
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + tid;
   const bool act = g < q;
   double total = 0.0;

@@ -589,3 +589,326 @@ class GpuSearchBackend(GpuBackend):
 
     def rho_analyze(self, theta):
         return _rho_of(self.analyze.loglik(theta)[1])
+
+
+# ---------------------------------------------------------------------------------------------
+# The global search over many segments (Algorithm 3 with the three runs of Table II)
+
+def overlapping_windows(table, sources: np.ndarray, T: float) -> tuple:
+    """(source index, window index) pairs: every window whose bins meet the N bins of the
+    source's template at that window's N (first bin floor(f0 T) - N/2)."""
+    t = np.asarray(table, dtype=np.int64)
+    k0, W, N = t[:, 0], t[:, 1], t[:, 2]
+    si, wi = [], []
+    for s, th in enumerate(np.atleast_2d(sources)):
+        q = int(np.floor(th[0] * T))
+        first = q - N // 2
+        hit = np.nonzero((first < k0 + W) & (first + N > k0))[0]
+        si += [s] * len(hit)
+        wi += list(hit)
+    return np.array(si, dtype=np.int64), np.array(wi, dtype=np.int32)
+
+
+def global_search(backend_factory, table, T: float, seg_edges, d, rng: np.random.Generator,
+                  subtract, runs=((0, 3), (1, 10), (0, 10)), **search_kw):
+    """Algorithm 3 over all segments: segments alternate even/odd by index; each run is
+    local_search over the segments of one parity (all at once) on the data minus the sources the
+    previous run found (Table II: even segments with n_signals = 3 on d, odd segments with 10 on
+    d minus the even results, even segments again with 10 on d minus the odd results).
+    ``backend_factory(rows, d_analyze)`` builds a search backend for a subset of windows;
+    ``subtract(d, sources, src_win)`` returns d minus the listed templates (each in the windows
+    given).  Returns (recovered parameter vectors [n, 8], index of the segment of each)."""
+    t = np.asarray(table, dtype=np.int64)
+    seg = np.asarray(seg_edges, dtype=np.float64)
+    results = {}
+    d_run = d
+    for parity, n_signals in runs:
+        rows = np.arange(parity, len(t), 2)
+        be = backend_factory(rows, d_run)
+        found_in, _ = local_search(be, seg[rows], rng, n_signals, **search_kw)
+        results[parity] = [(rows[i], th) for i in range(len(rows)) for th in found_in[i]]
+        srcs = np.array([th for _, th in results[parity]]).reshape(-1, 8)
+        si, wi = overlapping_windows(t, srcs, T)
+        d_run = subtract(d, srcs[si], wi) if len(si) else d
+    rec = results.get(0, []) + results.get(1, [])
+    if not rec:
+        return np.zeros((0, 8)), np.zeros(0, dtype=np.int64)
+    return np.array([th for _, th in rec]), np.array([r for r, _ in rec], dtype=np.int64)
+
+
+def _from_table1_t(u):
+    """Table I coordinates back to parameters, on tensors (as inputs.from_table1)."""
+    import torch
+    th = u.clone()
+    th[..., 2] = torch.asin(u[..., 2].clamp(-1.0, 1.0))
+    th[..., 4] = torch.pow(10.0, u[..., 4])
+    th[..., 5] = torch.acos(u[..., 5].clamp(-1.0, 1.0))
+    return th
+
+
+class PairKDEBatch:
+    """PairKDE for S sources at once, on tensors (on the backend's device): the proposals u
+    [S, n, 8] (Table I coordinates) of a stage and its chains [S, n] (indices into them).  The
+    kernel points of source s are its chain's distinct states weighted by how often the chain
+    holds them, padded with zero weights to the largest count over the sources; bandwidths by
+    Scott's rule as in PairKDE.  A kernel point of a pair is drawn by picking a uniform position
+    of the chain (the same distribution as drawing a distinct state by its weight)."""
+
+    def __init__(self, u, chain, lo_prior, hi_prior, lo_box, hi_box):
+        import torch
+        self.torch = torch
+        S, n = chain.shape
+        dev = u.device
+        chain = chain.long()
+        flat = (chain + n * torch.arange(S, device=dev)[:, None]).reshape(-1)
+        counts = torch.bincount(flat, minlength=S * n).reshape(S, n).to(torch.float64)
+        held = counts > 0
+        m = int(held.sum(dim=1).max().item())
+        order = torch.sort((~held).to(torch.int8), dim=1, stable=True).indices[:, :m]
+        self.w = torch.gather(counts, 1, order) / n                               # [S, m]
+        self.pts = torch.gather(u, 1, order[:, :, None].expand(S, m, 8))          # [S, m, 8]
+        sw2 = (self.w * self.w).sum(dim=1)
+        n_eff = 1.0 / sw2
+        chol = []
+        for a, b in KDE_PAIRS:
+            xy = self.pts[:, :, [a, b]]
+            mu = (self.w[:, :, None] * xy).sum(dim=1)
+            d = xy - mu[:, None, :]
+            wd = self.w[:, :, None] * d
+            c00 = (wd[:, :, 0] * d[:, :, 0]).sum(dim=1)
+            c01 = (wd[:, :, 0] * d[:, :, 1]).sum(dim=1)
+            c11 = (wd[:, :, 1] * d[:, :, 1]).sum(dim=1)
+            den = (1.0 - sw2).clamp(min=1e-300)
+            c00, c01, c11 = c00 / den, c01 / den, c11 / den
+            c00 = c00 + 1e-12 * c00.abs().clamp(min=1e-300)
+            c11 = c11 + 1e-12 * c11.abs().clamp(min=1e-300)
+            f = n_eff ** (-1.0 / 3.0)
+            h00, h01, h11 = c00 * f, c01 * f, c11 * f
+            l00 = torch.sqrt(h00)
+            l10 = h01 / l00
+            l11 = torch.sqrt((h11 - l10 * l10).clamp(min=0.0))
+            l11 = torch.where(l11 > 0, l11, torch.sqrt(h11) * 1e-6)
+            chol.append(torch.stack([l00, l10, l11], dim=1))
+        self.chol = torch.stack(chol, dim=1)                                       # [S, 3, 3]
+        self.u, self.chain = u, chain
+        self.lo_p, self.hi_p = lo_prior, hi_prior
+        self.lo_b, self.hi_b = lo_box, hi_box
+
+    def _candidates(self, sel, k, gen):
+        torch = self.torch
+        S_a = len(sel)
+        n = self.chain.shape[1]
+        dev = self.u.device
+        cand = torch.empty((S_a, k, 8), dtype=torch.float64, device=dev)
+        u_a, ch_a = self.u[sel], self.chain[sel]
+        for p, (a, b) in enumerate(KDE_PAIRS):
+            t = torch.randint(0, n, (S_a, k), generator=gen, device=dev)
+            j = torch.gather(ch_a, 1, t)
+            base = torch.gather(u_a, 1, j[:, :, None].expand(S_a, k, 8))
+            z = torch.randn((S_a, k, 2), generator=gen, dtype=torch.float64, device=dev)
+            L = self.chol[sel, p]
+            cand[:, :, a] = base[:, :, a] + z[:, :, 0] * L[:, None, 0]
+            cand[:, :, b] = base[:, :, b] + z[:, :, 0] * L[:, None, 1] + z[:, :, 1] * L[:, None, 2]
+        for dd in UNIFORM_DIMS:
+            r = torch.rand((S_a, k), generator=gen, dtype=torch.float64, device=dev)
+            lo, hi = self.lo_b[sel, dd], self.hi_b[sel, dd]
+            cand[:, :, dd] = lo[:, None] + (hi - lo)[:, None] * r
+        bd = [0, 1, 2, 4, 5]      # lambda, psi, phi0 are periodic: not bounded by the prior box
+        ok = ((cand[:, :, bd] >= self.lo_p[sel][:, None, bd]) & (cand[:, :, bd] <= self.hi_p[sel][:, None, bd])).all(dim=2)
+        return cand, ok
+
+    def draw(self, gen, n, backend):
+        torch = self.torch
+        S = self.chain.shape[0]
+        dev = self.u.device
+        out = torch.empty((S, n, 8), dtype=torch.float64, device=dev)
+        filled = torch.zeros(S, dtype=torch.int64, device=dev)
+        for _ in range(1000):
+            sel = torch.nonzero(filled < n).reshape(-1)
+            if len(sel) == 0:
+                break
+            need = n - filled[sel]
+            k = 2 * int(need.max().item()) + 16
+            cand, ok = self._candidates(sel, k, gen)
+            rank = torch.cumsum(ok.to(torch.int64), dim=1)
+            take = ok & (rank <= need[:, None])
+            got = take.sum(dim=1)
+            # rows of cand that are taken go to out[s, filled[s] + rank - 1]
+            s_idx, c_idx = torch.nonzero(take, as_tuple=True)
+            dst = filled[sel][s_idx] + rank[s_idx, c_idx] - 1
+            out[sel[s_idx], dst] = cand[s_idx, c_idx]
+            filled[sel] += got
+        if bool((filled < n).any().item()):
+            raise RuntimeError("KDE proposals keep leaving the prior box")
+        x = torch.stack([out[:, :, [a, b]] for a, b in KDE_PAIRS], dim=2)                   # [S, n, 3, 2]
+        pts = torch.stack([self.pts[:, :, [a, b]] for a, b in KDE_PAIRS], dim=1)            # [S, 3, m, 2]
+        wts = self.w[:, None, :].expand(S, len(KDE_PAIRS), self.w.shape[1]).contiguous()
+        log_g = backend.kde_logpdf(pts.contiguous(), wts, self.chol.contiguous(), x.contiguous())
+        return out, log_g
+
+
+def annealed_posterior_batch(backend, theta_mle: np.ndarray, boxes, seed: int,
+                             temps=(15.0, 10.0, 5.0, 3.0, 2.0, 1.0), n: int = 10000, fd_step: float = 1e-9):
+    """Algorithm 4 for S sources at once (Algorithm 5 runs it for every recovered source): one
+    gb_fisher call gives every source's sigma and reduced box; each temperature draws n
+    proposals per source (uniform in the reduced box first, then from the source's pairwise KDE
+    of its previous chain), and one gb_mh_step resolves all S chains.  The draws stay on the
+    backend's device (a torch generator seeded with ``seed``).  Returns (per-stage list of
+    dicts with T, states [S, n, 8], n_accept [S], logL of the states [S, n]; the reduced boxes
+    (lo, hi) [S, 8]; sigma [S, 8])."""
+    import torch
+    theta_mle = np.atleast_2d(np.asarray(theta_mle, dtype=np.float64))
+    S = len(theta_mle)
+    dev = backend.device
+    widths = np.stack([b.width for b in boxes])
+    F = backend.fisher(theta_mle, fd_step * widths)
+    lo, hi, sigma = np.empty((S, 8)), np.empty((S, 8)), np.empty((S, 8))
+    for k in range(S):
+        try:
+            sg = np.sqrt(np.diag(np.linalg.inv(F[k])))
+        except np.linalg.LinAlgError:
+            sg = np.full(8, np.nan)
+        sigma[k] = sg if np.all(np.isfinite(sg)) else 1e-3 * widths[k]
+        lo[k], hi[k] = I.reduced_box(theta_mle[k], boxes[k], sigma[k])
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    lo_t, hi_t = t(lo), t(hi)
+    lo_p, hi_p = t(np.stack([b.lo for b in boxes])), t(np.stack([b.hi for b in boxes]))
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(int(seed))
+    u = lo_t[:, None, :] + (hi_t - lo_t)[:, None, :] * torch.rand((S, n, 8), generator=gen, dtype=torch.float64,
+                                                                   device=dev)
+    log_g = torch.zeros((S, n), dtype=torch.float64, device=dev)
+    stages = []
+    for i, T in enumerate(temps):
+        props = _from_table1_t(u)
+        uni = torch.rand((S, n), generator=gen, dtype=torch.float64, device=dev)
+        logL, chain, nacc = backend.mh(props.reshape(S * n, 8), log_g.reshape(-1), uni.reshape(-1), float(T))
+        chain = chain.reshape(S, n).long()
+        states = torch.gather(props, 1, chain[:, :, None].expand(S, n, 8))
+        stages.append({"T": float(T), "states": states, "n_accept": nacc,
+                       "logL": torch.gather(logL.reshape(S, n), 1, chain)})
+        if i + 1 < len(temps):
+            u, log_g = PairKDEBatch(u, chain, lo_p, hi_p, lo_t, hi_t).draw(gen, n, backend)
+    return stages, (lo, hi), sigma
+
+
+class GpuPosteriorBatchBackend:
+    """The library calls of annealed_posterior_batch: S sources, each with its own copy of its
+    window holding d_posterior = d_residual + s(theta_MLE) (Algorithm 5); gb_fisher over the
+    S windows, gb_mh_step with n proposals per window, gb_kde_logpdf with one set per source."""
+
+    def __init__(self, ctx, table, d_residual, w, sources, rows):
+        import torch
+        from . import api
+        self.api, self.torch = api, torch
+        self.device = torch.device("cuda")
+        self.ctx = ctx
+        t = np.asarray(table, dtype=np.int64)
+        rows = np.asarray(rows, dtype=np.int64)
+        tab = t[rows].copy()
+        sizes = tab[:, 3] * tab[:, 1]
+        offs = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+        gather = np.concatenate([np.arange(t[r, 4], t[r, 4] + sz) for r, sz in zip(rows, sizes)])
+        gi = torch.as_tensor(gather, device=self.device)
+        self.d = d_residual.index_select(0, gi).contiguous()
+        self.w = w.index_select(0, gi).contiguous()
+        tab[:, 4] = offs
+        tab[:, 5] = offs
+        self.tab = tab
+        th = torch.as_tensor(np.atleast_2d(np.asarray(sources, dtype=np.float64)), device=self.device)
+        api.gb_add_templates(ctx.handle, tab, th, np.arange(len(tab), dtype=np.int32), 1.0, self.d, self.d)
+        self.plans = {}
+
+    def fisher(self, theta, steps):
+        t = lambda a: self.torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=self.device)
+        return self.api.gb_fisher(self.ctx.handle, t(theta), t(steps), self.tab, self.w).cpu().numpy()
+
+    def mh(self, theta, log_g, u, T):
+        n = len(theta) // len(self.tab)
+        if n not in self.plans:
+            tab = self.tab.copy()
+            tab[:, 6] = np.arange(len(tab)) * n
+            tab[:, 7] = n
+            p = self.api.Plan(self.ctx, tab, self.api.GB_FP64)
+            p.prepare(self.d, self.w)
+            self.plans[n] = p
+        return self.plans[n].mh_step(theta.contiguous(), log_g.contiguous(), u.contiguous(), T)
+
+    def kde_logpdf(self, pts, wts, chol, x):
+        return self.api.gb_kde_logpdf(pts, wts, chol, x)
+
+    def close(self):
+        for p in self.plans.values():
+            p.close()
+        self.plans = {}
+
+
+def posterior_batch(ctx, table, T: float, d_residual, w, sources, seg_rows, boxes, seed: int,
+                    n: int = 10000, temps=(15.0, 10.0, 5.0, 3.0, 2.0, 1.0), fd_step: float = 1e-9,
+                    chunk: int = 256):
+    """Algorithm 5's posterior step for every recovered source: ``d_residual`` is the data minus
+    all recovered sources (window layout of ``table``), ``seg_rows`` the window of each source;
+    the sources run through annealed_posterior_batch ``chunk`` at a time, each on its window
+    plus its own template.  Returns (final-stage states [n_src, n, 8] (numpy), accepted
+    proposals per stage [n_src, n_stages], logL of the final states [n_src, n])."""
+    src = np.atleast_2d(np.asarray(sources, dtype=np.float64))
+    rows = np.asarray(seg_rows, dtype=np.int64)
+    states, accepted, logL = [], [], []
+    for c0 in range(0, len(src), chunk):
+        sl = slice(c0, min(len(src), c0 + chunk))
+        be = GpuPosteriorBatchBackend(ctx, table, d_residual, w, src[sl], rows[sl])
+        stages, _, _ = annealed_posterior_batch(be, src[sl], [boxes[r] for r in rows[sl]], seed + c0,
+                                                temps=temps, n=n, fd_step=fd_step)
+        states.append(stages[-1]["states"].cpu().numpy())
+        logL.append(stages[-1]["logL"].cpu().numpy())
+        accepted.append(np.stack([s["n_accept"].cpu().numpy() for s in stages], axis=1))
+        be.close()
+    if not states:
+        return np.zeros((0, n, 8)), np.zeros((0, len(temps)), dtype=np.int64), np.zeros((0, n))
+    return np.concatenate(states), np.concatenate(accepted), np.concatenate(logL)
+
+
+def match_delta(ctx, table, T: float, w, recovered, rec_rows, injected, n_near: int = 3) -> np.ndarray:
+    """Scaled error of Sec. V, delta = <s_rec - s_inj | s_rec - s_inj> / <s_rec | s_rec>, of every
+    recovered source against the ``n_near`` injected sources nearest in frequency, in the
+    recovered source's window; returns the smallest delta of each (inf with no injected source).
+    One window per (recovered, injected) pair holds the injected template as data, so the
+    likelihood kernel's components give delta = -2 logL / <h|h>."""
+    import torch
+    from . import api
+    dev = torch.device("cuda")
+    rec = np.atleast_2d(np.asarray(recovered, dtype=np.float64))
+    inj = np.atleast_2d(np.asarray(injected, dtype=np.float64))
+    if len(rec) == 0 or len(inj) == 0:
+        return np.full(len(rec), np.inf)
+    t = np.asarray(table, dtype=np.int64)
+    order = np.argsort(inj[:, 0])
+    f_sorted = inj[order, 0]
+    pairs = []
+    for k in range(len(rec)):
+        c = np.searchsorted(f_sorted, rec[k, 0])
+        near = sorted(range(max(0, c - n_near), min(len(inj), c + n_near)),
+                      key=lambda j: abs(f_sorted[j] - rec[k, 0]))[:n_near]
+        pairs += [(k, int(order[j])) for j in near]
+    tab = t[np.asarray(rec_rows)[[k for k, _ in pairs]]].copy()
+    sizes = tab[:, 3] * tab[:, 1]
+    offs = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+    gather = np.concatenate([np.arange(t[r, 4], t[r, 4] + s) for r, s in
+                             zip(np.asarray(rec_rows)[[k for k, _ in pairs]], sizes)])
+    w_p = w.index_select(0, torch.as_tensor(gather, device=dev)).contiguous()
+    tab[:, 4] = offs
+    tab[:, 5] = offs
+    tab[:, 6] = np.arange(len(pairs))
+    tab[:, 7] = 1
+    d0 = torch.zeros(int(sizes.sum()), dtype=torch.complex128, device=dev)
+    d_p = api.gb_add_templates(ctx.handle, tab, torch.as_tensor(inj[[j for _, j in pairs]], device=dev),
+                               np.arange(len(pairs), dtype=np.int32), 1.0, d0)
+    plan = api.Plan(ctx, tab, api.GB_FP64)
+    plan.prepare(d_p, w_p)
+    l, c = plan.loglik(torch.as_tensor(rec[[k for k, _ in pairs]], device=dev), comps=True)
+    plan.close()
+    delta = (-2.0 * l.cpu().numpy()) / c.cpu().numpy()[:, 1]
+    best = np.full(len(rec), np.inf)
+    for (k, _), dl in zip(pairs, delta):
+        best[k] = min(best[k], dl)
+    return best

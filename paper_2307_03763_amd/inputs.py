@@ -533,7 +533,7 @@ def nextpow2(x: int) -> int:
 
 
 def workload_c5(template_fn: Optional[TemplateFn], n_target: int = 4000, n_gb: int = 20000, pop: int = 512,
-                noise: bool = True, T: float = T2) -> Workload:
+                noise: bool = True, T: float = T2, segments: Optional[tuple] = None) -> Workload:
     """Full band: the windows of Algorithm 1 over 0.3-30 mHz with B_max scaled so that
     ``n_target`` segments result (workload_c5_windows); each padded by a quarter of its width on
     both sides (W = 3 kappa B_max T bins, clamped to [64, 4096]).  ``n_gb`` GBs: f0 log-uniform
@@ -541,9 +541,12 @@ def workload_c5(template_fn: Optional[TemplateFn], n_target: int = 4000, n_gb: i
     1024 - 16 bins rejected (as C3).  Every GB is injected into every window its band overlaps;
     N = nextpow2(widest overlapping band + 16) clamped to [64, 1024]; C by the paper rule at the
     window centre.  Candidates: a DE population of ``pop`` per window, uniform over the window's
-    Table I box."""
+    Table I box.  ``segments`` = (i0, i1) keeps the contiguous segments i0 .. i1-1 only (the GB
+    population is the same; the sources overlapping the kept windows are injected)."""
     r_inj, r_noise, r_prop, _ = _streams(5)
     kappa, segs = workload_c5_windows(n_target, T)
+    if segments is not None:
+        segs = segs[segments[0]:segments[1]]
     f_min, f_max = 0.3e-3, 30e-3
     gbs, bw = [], []
     rejected = 0
@@ -581,4 +584,6 @@ def workload_c5(template_fn: Optional[TemplateFn], n_target: int = 4000, n_gb: i
                                f"{n_gb} GBs, DE population {pop} per window, T=2^22*15 s", T)
     wl.rejected = (rejected, rejected + n_gb)
     wl.kappa = kappa
+    wl.segments = np.array(segs)
+    wl.population = gbs
     return finalize_data(wl, template_fn, r_noise, noise)

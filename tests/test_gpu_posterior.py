@@ -5,11 +5,13 @@ posterior (Algorithm 4) driven by the library.
   forward differences; against the oracle's finite differences with the same steps and against
   the exact (dual-number) Fisher matrix, at the paper's step (1e-9 of the Table I widths,
   rounding-limited on both sides) and at 1e-7; and the sigmas that size the reduced box.
-* gb_kde_logpdf: three pairs, ragged tile sizes, zero weights, single kernel point; against the
-  definition.
+* gb_kde_logpdf: three pairs, ragged tile sizes, zero weights, single kernel point; several
+  independent sets in one launch; against the definition.
 * annealed_posterior with the GPU backend on a loud 8 mHz source: the final chain against the
   Fisher Gaussian (conditional on psi, phi0), as the CPU test does with the oracle backend; every
   stage's chain bit-exact against the oracle's chain on the GPU's own logL and log g.
+* annealed_posterior_batch (two sources in two windows, one launch per stage): the same checks
+  for each source.
 """
 
 import numpy as np
@@ -41,9 +43,10 @@ def test_fisher_matches_oracle(oracle_lib, post):
     w_t = dev(wl.weights)
     # The paper's step (1e-9 of the widths) is dominated by template rounding on both sides
     # (the oracle's own differences reach 7e-4 of sqrt(F_ii F_jj) and 4e-3 in sigma on these
-    # sources); at 1e-7 the two difference quotients agree closely and both sit near the exact
-    # matrix.
-    for fac, bar_fd, bar_exact, bar_sigma in ((1e-9, 1e-2, 1e-2, 2e-2), (1e-7, 1e-5, 1e-4, 1e-4)):
+    # sources).  That rounding term scales as 1 / step, so at 1e-7 each side carries ~7e-6 and
+    # two independent roundings differ by up to ~2e-5 on the worst of 24 sources (bar 3e-5),
+    # while both sit near the exact matrix.
+    for fac, bar_fd, bar_exact, bar_sigma in ((1e-9, 1e-2, 1e-2, 2e-2), (1e-7, 3e-5, 1e-4, 1e-4)):
         steps = fac * widths
         F = api.gb_fisher(ctx.handle, dev(th), dev(steps), wl.window_table(), w_t).cpu().numpy()
         worst_fd = worst_ex = worst_s = 0.0
@@ -115,3 +118,60 @@ def test_annealed_posterior_gpu(oracle_lib, post):
     for k in range(6):
         assert abs(final[:, k].mean() - u_mle[k]) < 0.6 * s_cond[k]
         assert 0.7 < final[:, k].std() / s_cond[k] < 1.4
+
+
+def test_kde_logpdf_sets_match_oracle(post):
+    banner("gb_kde_logpdf: 5 independent sets in one launch, zero-weight padding")
+    rng = np.random.default_rng(17)
+    S, P, m, q = 5, 3, 300, 700
+    pts = rng.normal(size=(S, P, m, 2))
+    wts = rng.random((S, P, m))
+    for s in range(S):
+        wts[s, :, m - 37 * s:] = 0.0        # set s holds m - 37 s points
+    wts /= wts.sum(axis=2, keepdims=True)
+    chol = np.abs(rng.normal(size=(S, P, 3))) * 0.3 + 0.05
+    chol[:, :, 1] -= 0.1
+    x = rng.normal(size=(S, q, P, 2))
+    got = api.gb_kde_logpdf(dev(pts), dev(wts), dev(chol), dev(x)).cpu().numpy()
+    assert got.shape == (S, q)
+    for s in range(S):
+        np.testing.assert_allclose(got[s], post.kde_logpdf(pts[s], wts[s], chol[s], x[s]), rtol=1e-12, atol=1e-9)
+
+
+def test_annealed_posterior_batch_gpu(oracle_lib, post):
+    banner("batched annealed posterior: two sources, six temperatures x 10,000, one launch per stage")
+    from tests.test_posterior_cpu import _loud_pair, check_against_fisher, pair_mles
+    O = oracle_lib
+    wl = _loud_pair(O)
+    mles = pair_mles(O, post, wl)
+    ctx = api.context_for(wl.T)
+    table = wl.window_table()
+    d = dev(wl.data, torch.complex128)
+    d_res = api.gb_add_templates(ctx.handle, table, dev(mles), np.arange(2, dtype=np.int32), -1.0, d)
+    be = D.GpuPosteriorBatchBackend(ctx, table, d_res, dev(wl.weights), mles, [0, 1])
+    # d_residual + own template gives back each window's data
+    assert torch.max(torch.abs(be.d - d)).item() <= 1e-12 * torch.max(torch.abs(d)).item()
+
+    class Checked:
+        device = be.device
+
+        def fisher(self, t, s):
+            return be.fisher(t, s)
+
+        def kde_logpdf(self, p, w, c, x):
+            return be.kde_logpdf(p, w, c, x)
+
+        def mh(self, theta, log_g, u, T):
+            l, ch, na = be.mh(theta, log_g, u, T)
+            n = len(theta) // 2
+            lh, gh, uh, chh = l.cpu().numpy(), log_g.cpu().numpy(), u.cpu().numpy(), ch.cpu().numpy()
+            for k in range(2):
+                sl = slice(k * n, (k + 1) * n)
+                ref, acc = O.mh_chain(lh[sl], gh[sl], uh[sl], T)
+                assert np.array_equal(chh[sl], ref) and int(na[k]) == acc
+            return l, ch, na
+
+    stages, _, _ = D.annealed_posterior_batch(Checked(), mles, [wl.window_box(i) for i in range(2)], seed=5, n=10000)
+    banner(f"  accepted per stage {[s['n_accept'].tolist() for s in stages]}")
+    check_against_fisher(O, post, wl, mles, [{"states": s["states"].cpu().numpy()} for s in stages])
+    be.close()

@@ -49,3 +49,98 @@ def test_local_search_gpu(oracle_lib):
     found_in, found_out = D.local_search(be, seg, np.random.default_rng(3), n_signals=2, n_searches=2,
                                          pop=256, generations=100, polish_iterations=30)
     check_search(O, wl, seg, found_in, found_out)
+
+
+def test_global_search_gpu(oracle_lib):
+    banner("global search (Algorithm 3, three runs) over eight segments on the GPU")
+    from tests.test_search_cpu import band_workload
+    O = oracle_lib
+    wl, segs, src = band_workload(O)
+    ctx = api.context_for(wl.T)
+    table = wl.window_table()
+    w = dev(wl.weights)
+    boxes = [wl.window_box(i) for i in range(wl.n_win)]
+
+    def factory(rows, d_an):
+        return D.GpuSearchBackend(ctx, table[rows], d_an, w, [boxes[r] for r in rows], api.GB_FP64, api.GB_MIXED)
+
+    def subtract(d, srcs, win):
+        return api.gb_add_templates(ctx.handle, table, dev(srcs), win, -1.0, d)
+
+    found, seg_of = D.global_search(factory, table, wl.T, segs, dev(wl.data, torch.complex128),
+                                    np.random.default_rng(4), subtract, n_searches=2, pop=192, generations=80,
+                                    polish_iterations=30)
+    assert len(found) == len(src), (len(found), len(src))
+    d_bins = np.abs(found[:, 0][:, None] - src[:, 0][None, :]) * wl.T
+    assert np.all(d_bins.min(axis=1) < 0.5) and np.all(d_bins.min(axis=0) < 0.5)
+    assert np.all((found[:, 0] >= segs[seg_of, 0]) & (found[:, 0] < segs[seg_of, 1]))
+
+
+def _band_setup(O):
+    from tests.test_search_cpu import band_workload
+    wl, segs, src = band_workload(O)
+    ctx = api.context_for(wl.T)
+    table = wl.window_table()
+    # the window of each source: the segment whose unpadded part holds it
+    rows = np.array([int(np.nonzero((segs[:, 0] <= f) & (f < segs[:, 1]))[0][0]) for f in src[:, 0]])
+    return wl, segs, src, ctx, table, rows
+
+
+def _oracle_block(O, wl, i, sources, base=None):
+    """Window i's data block (or zeros) plus the oracle templates of ``sources``."""
+    w = wl.windows[i]
+    g = O.Geometry(wl.T)
+    blk = np.zeros((w.C, w.W), dtype=np.complex128) if base is None else base.copy()
+    if len(sources):
+        h, fb = O.waveform(np.atleast_2d(sources), w.N, w.C, g)
+        I.add_templates(blk, w.k0, h, fb, sign=1.0)
+    return blk
+
+
+def test_match_delta_gpu(oracle_lib):
+    banner("match delta (Sec. V) of recovered against injected sources, against the oracle")
+    O = oracle_lib
+    wl, segs, src, ctx, table, rows = _band_setup(O)
+    rng = np.random.default_rng(9)
+    rec = src.copy()
+    rec[:, 0] += rng.uniform(-0.4, 0.4, len(src)) / wl.T
+    rec[:, 4] *= rng.uniform(0.8, 1.2, len(src))
+    rec[0] = src[0]
+    got = D.match_delta(ctx, table, wl.T, dev(wl.weights), rec, rows, src)
+    assert abs(got[0]) < 1e-12
+    for k in range(len(rec)):
+        _, ww = wl.window_data(rows[k])
+        h_r = _oracle_block(O, wl, rows[k], rec[k])
+        near = np.argsort(np.abs(src[:, 0] - rec[k, 0]))[:3]
+        ref = min(np.sum(ww * np.abs(h_r - _oracle_block(O, wl, rows[k], src[j])) ** 2) / np.sum(ww * np.abs(h_r) ** 2)
+                  for j in near)
+        assert abs(got[k] - ref) <= 1e-10 * max(ref, 1e-3), (k, got[k], ref)
+
+
+def test_posterior_batch_gpu(oracle_lib):
+    banner("annealed posteriors of six sources at once (Algorithm 5), against the oracle")
+    O = oracle_lib
+    wl, segs, src, ctx, table, rows = _band_setup(O)
+    si, wi = D.overlapping_windows(table, src, wl.T)
+    d = dev(wl.data, torch.complex128)
+    d_res = api.gb_add_templates(ctx.handle, table, dev(src[si]), wi, -1.0, d)
+    boxes = [wl.window_box(i) for i in range(wl.n_win)]
+    n = 4096
+    states, nacc, logL = D.posterior_batch(ctx, table, wl.T, d_res, dev(wl.weights), src, rows, boxes, seed=6,
+                                           n=n, chunk=4)
+    assert states.shape == (len(src), n, 8) and nacc.shape == (len(src), 6)
+    assert np.all(nacc > 0) and np.all(nacc < n)
+    g = O.Geometry(wl.T)
+    for k in range(len(src)):
+        i = rows[k]
+        w = wl.windows[i]
+        d_blk, ww = wl.window_data(i)
+        # the posterior data: the window's data minus every other source overlapping it
+        others = [src[s] for s, ww_ in zip(si, wi) if ww_ == i and s != k]
+        d_post = d_blk - _oracle_block(O, wl, i, np.array(others).reshape(-1, 8))
+        pick = np.unique(np.linspace(0, n - 1, 64).astype(int))
+        ref, _ = O.loglik(states[k, pick], w.k0, w.W, w.N, w.C, d_post, ww, g)
+        np.testing.assert_allclose(logL[k, pick], ref, rtol=1e-10, atol=1e-8)
+        # the chain stays near the injected source (a few bins, amplitude within a factor 2)
+        assert np.all(np.abs(states[k, n // 2:, 0] - src[k, 0]) * wl.T < 2.0)
+        assert 0.5 < np.median(states[k, n // 2:, 4]) / src[k, 4] < 2.0

@@ -85,3 +85,86 @@ def test_annealed_posterior_matches_fisher(oracle_lib):
         m, sd = final[:, k].mean(), final[:, k].std()
         assert abs(m - u_mle[k]) < 0.6 * s_cond[k], (k, m, u_mle[k], s_cond[k])
         assert 0.7 < sd / s_cond[k] < 1.4, (k, sd, s_cond[k])
+
+
+def _loud_pair(O):
+    """Two loud plain windows (8 mHz and 5 mHz, SNR ~ 60 each) in one workload."""
+    a = _loud_window(O, 8e-3, 60.0, 3)
+    b = _loud_window(O, 5e-3, 60.0, 8)
+    wins = [a.windows[0], b.windows[0]]
+    wl = I._concat(wins, [w.sources for w in wins], "two loud test windows", I.T1)
+    return I.finalize_data(wl, O.template_fn(), np.random.default_rng(11), noise=True)
+
+
+class OracleBatchBackend:
+    """annealed_posterior_batch's calls with the oracle, one window per source (CPU tensors)."""
+
+    def __init__(self, O, post, wl, rows):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cpu")
+        self.one = [OracleBackend(O, post, wl, int(i)) for i in rows]
+        self.O = O
+
+    def fisher(self, theta, steps):
+        return np.concatenate([b.fisher(t[None], s[None]) for b, t, s in zip(self.one, theta, steps)])
+
+    def mh(self, theta, log_g, u, T):
+        S = len(self.one)
+        n = len(theta) // S
+        th, lg, uu = theta.numpy(), log_g.numpy(), u.numpy()
+        ls, cs, acc = [], [], []
+        for k, b in enumerate(self.one):
+            sl = slice(k * n, (k + 1) * n)
+            l, ch, na = b.mh(th[sl], lg[sl], uu[sl], T)
+            ls.append(l)
+            cs.append(ch)
+            acc.append(na)
+        t = self.torch
+        return t.as_tensor(np.concatenate(ls)), t.as_tensor(np.concatenate(cs).astype(np.int32)), t.as_tensor(acc)
+
+    def kde_logpdf(self, pts, wts, chol, x):
+        return self.torch.as_tensor(np.stack([self.one[0].kde_logpdf(p.numpy(), w.numpy(), c.numpy(), xx.numpy())
+                                              for p, w, c, xx in zip(pts, wts, chol, x)]))
+
+
+def pair_mles(O, post, wl):
+    mles = []
+    for i in range(wl.n_win):
+        be = OracleBackend(O, post, wl, i)
+        src = wl.windows[i].sources[0]
+        F0 = post.fisher_u(src, be.w.k0, be.w.W, be.w.N, be.w.C, be.ww, be.g)
+        mle, _ = D.polish(be, src, np.sqrt(np.diag(np.linalg.inv(F0))), iterations=60)
+        mles.append(mle)
+    return np.array(mles)
+
+
+def check_against_fisher(O, post, wl, mles, stages):
+    for i in range(wl.n_win):
+        be = OracleBackend(O, post, wl, i)
+        Fm = post.fisher_u(mles[i], be.w.k0, be.w.W, be.w.N, be.w.C, be.ww, be.g)
+        s_cond = np.sqrt(np.diag(np.linalg.inv(Fm[:6, :6])))
+        u_mle = I.to_table1(mles[i])
+        final = I.to_table1(np.asarray(stages[-1]["states"][i]))
+        for k in range(6):
+            m, sd = final[:, k].mean(), final[:, k].std()
+            assert abs(m - u_mle[k]) < 0.6 * s_cond[k], (i, k, m, u_mle[k], s_cond[k])
+            assert 0.7 < sd / s_cond[k] < 1.4, (i, k, sd, s_cond[k])
+
+
+def test_annealed_posterior_batch_matches_fisher(oracle_lib):
+    """Algorithm 5's batched form: two sources in two windows through one call of the batched
+    annealing (draws on torch tensors, one chain per source); each final chain against its own
+    Fisher Gaussian as above (a mix-up between the sources would put a chain far off)."""
+    from oracle import posterior as post
+    O = oracle_lib
+    wl = _loud_pair(O)
+    mles = pair_mles(O, post, wl)
+    be = OracleBatchBackend(O, post, wl, [0, 1])
+    boxes = [wl.window_box(i) for i in range(2)]
+    stages, (lo, hi), sigma = D.annealed_posterior_batch(be, mles, boxes, seed=5, n=10000)
+    assert [s["T"] for s in stages] == [15.0, 10.0, 5.0, 3.0, 2.0, 1.0]
+    assert all(np.all((np.asarray(s["n_accept"]) > 0) & (np.asarray(s["n_accept"]) < 10000)) for s in stages)
+    u = I.to_table1(mles)
+    assert np.all(u >= lo) and np.all(u <= hi)
+    check_against_fisher(O, post, wl, mles, stages)

@@ -33,33 +33,42 @@ def segments_workload(O, template=True, seed=11):
 
 
 class OracleSearchBackend:
-    """Window-major batched likelihoods on the residual (data minus found sources) with the oracle."""
+    """Window-major batched likelihoods on the residual (data minus found sources) with the oracle,
+    for the windows ``rows`` of a workload (all by default) and analysed data ``d`` (the
+    workload's by default, same layout)."""
 
-    def __init__(self, O, wl):
+    def __init__(self, O, wl, rows=None, d=None):
         self.O, self.wl = O, wl
-        self.n_win = wl.n_win
-        self.boxes = [wl.window_box(i) for i in range(wl.n_win)]
+        self.rows = list(range(wl.n_win)) if rows is None else [int(r) for r in rows]
+        self.n_win = len(self.rows)
+        self.boxes = [wl.window_box(i) for i in self.rows]
         self.g = O.Geometry(wl.T)
-        self.res = [wl.window_data(i)[0].copy() for i in range(wl.n_win)]
+        self.d = wl.data if d is None else d
+        self.an = [self._block(i) for i in self.rows]
+        self.res = [a.copy() for a in self.an]
+
+    def _block(self, i):
+        w = self.wl.windows[i]
+        o = int(self.wl.data_off[i])
+        return self.d[o:o + w.C * w.W].reshape(w.C, w.W)
 
     def set_residual(self, *lists):
-        for i in range(self.n_win):
-            d, _ = self.wl.window_data(i)
-            r = d.copy()
-            srcs = [t for lst in lists for t in lst[i]]
+        for j, i in enumerate(self.rows):
+            r = self.an[j].copy()
+            srcs = [t for lst in lists for t in lst[j]]
             if srcs:
                 w = self.wl.windows[i]
                 h, fb = self.O.waveform(np.array(srcs), w.N, w.C, self.g)
                 I.add_templates(r, w.k0, h, fb, sign=-1.0)
-            self.res[i] = r
+            self.res[j] = r
 
     def _each(self, fn, theta, data):
         n = len(theta) // self.n_win
         outs = []
-        for i in range(self.n_win):
+        for j, i in enumerate(self.rows):
             w = self.wl.windows[i]
             _, ww = self.wl.window_data(i)
-            outs.append(fn(theta[i * n:(i + 1) * n], w.k0, w.W, w.N, w.C, data[i], ww, self.g))
+            outs.append(fn(theta[j * n:(j + 1) * n], w.k0, w.W, w.N, w.C, data[j], ww, self.g))
         return np.concatenate([o[0] for o in outs]), np.concatenate([o[1] for o in outs])
 
     def loglik(self, theta):
@@ -69,8 +78,74 @@ class OracleSearchBackend:
         return self._each(self.O.loglik_grad, theta, self.res)
 
     def rho_analyze(self, theta):
-        _, c = self._each(self.O.loglik, theta, [self.wl.window_data(i)[0] for i in range(self.n_win)])
+        _, c = self._each(self.O.loglik, theta, self.an)
         return c[:, 0] / np.sqrt(c[:, 1])
+
+
+def oracle_subtract(O, wl):
+    """d minus the oracle templates of the listed sources, each in the listed window."""
+    g = O.Geometry(wl.T)
+
+    def sub(d, srcs, win):
+        out = d.copy()
+        for th, i in zip(srcs, win):
+            w = wl.windows[int(i)]
+            h, fb = O.waveform(th[None, :], w.N, w.C, g)
+            o = int(wl.data_off[i])
+            I.add_templates(out[o:o + w.C * w.W].reshape(w.C, w.W), w.k0, h, fb, sign=-1.0)
+        return out
+    return sub
+
+
+def band_workload(O, n_seg=8, n_src=6, seed=21, f_start=2e-3):
+    """Consecutive Algorithm 1 segments from f_start (T ~ 1 yr), padded by a quarter of the
+    segment on each side, N = 64; n_src loud GBs (SNR 20-50) placed over the band at least 8
+    bins apart, some in the padding of their segment's neighbours."""
+    rng = np.random.default_rng(seed)
+    T = I.T1
+    segs = []
+    f = f_start
+    for _ in range(n_seg):
+        f_next = f + 2.0 * float(I.b_max(f, T))
+        segs.append((f, f_next))
+        f = f_next
+    wins = []
+    for fa, fb in segs:
+        W = max(64, int(round(1.5 * (fb - fa) * T)))
+        k0 = int(np.floor(0.5 * (fa + fb) * T)) - W // 2
+        wins.append(I.WindowSpec(k0=k0, W=W, N=64, C=2, f_lo=k0 / T, f_hi=(k0 + W) / T, sources=np.zeros((0, 8))))
+    lo_bin, hi_bin = segs[0][0] * T, segs[-1][1] * T
+    bins = []
+    while len(bins) < n_src:
+        b = rng.uniform(lo_bin + 4, hi_bin - 4)
+        if all(abs(b - c) > 8 for c in bins):
+            bins.append(b)
+    src = I.make_theta(np.array(bins) / T, 1e-18, 1e-22, I.random_angles(rng, n_src))
+    # scale each amplitude to an SNR in [20, 50] (flat-noise estimate at the source)
+    s_a, _ = I.psd_aet(src[:, 0])
+    src[:, 4] = I.a_of_rho(rng.uniform(20, 50, n_src), src[:, 0], T, s_a)
+    for w in wins:
+        q = np.floor(src[:, 0] * T)
+        hit = (q - 32 < w.k0 + w.W) & (q + 32 > w.k0)
+        w.sources = src[hit]
+    wl = I._concat(wins, [np.zeros((1, 8)) for _ in wins], "band", T)
+    wl = I.finalize_data(wl, O.template_fn(), np.random.default_rng(seed + 1), noise=True)
+    return wl, np.array(segs), src
+
+
+def test_global_search_cpu(oracle_lib):
+    """Algorithm 3 with the three runs of Table II over eight segments: every injected source
+    found once (frequency within half a bin), nothing else."""
+    O = oracle_lib
+    wl, segs, src = band_workload(O)
+    found, seg_of = D.global_search(lambda rows, d: OracleSearchBackend(O, wl, rows, d), wl.window_table(), wl.T,
+                                    segs, wl.data, np.random.default_rng(4), oracle_subtract(O, wl),
+                                    n_searches=2, pop=192, generations=80, polish_iterations=30)
+    assert len(found) == len(src), (len(found), len(src))
+    d_bins = np.abs(found[:, 0][:, None] - src[:, 0][None, :]) * wl.T
+    assert np.all(d_bins.min(axis=1) < 0.5) and np.all(d_bins.min(axis=0) < 0.5)
+    # each found source sits in the unpadded part of its segment
+    assert np.all((found[:, 0] >= segs[seg_of, 0]) & (found[:, 0] < segs[seg_of, 1]))
 
 
 def check_search(O, wl, seg, found_in, found_out):
