@@ -628,7 +628,8 @@ def pipeline_leg(segments, log):
     torch.cuda.synchronize()
     t0 = time.time()
     found, found_seg = D.global_search(factory, table, T, segs, d, np.random.default_rng(2023), subtract,
-                                       n_searches=3, pop=512, generations=50, polish_iterations=20)
+                                       n_searches=3, pop=512, generations=50, polish_iterations=20,
+                                       progress=lambda m: log(f"pipeline: {m}"))
     torch.cuda.synchronize()
     t1 = time.time()
     log(f"pipeline: global search {t1 - t0:.1f} s, {len(found)} recovered")

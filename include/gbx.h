@@ -183,6 +183,19 @@ gb_status gb_add_templates(gb_ctx* ctx, const gb_window* windows, int n_win, con
                            const int32_t* src_win, int n_src, double sign, const double* d_in, double* d_out,
                            void* stream);
 
+/* Local noise estimate of every window and channel (Sec. III, noise within a frequency
+ * segment): S = the median over the window's W bins of the one-sided periodogram 2 |d_k|^2 / T
+ * (the paper's 2 |A|^2 / (N f_sample) for DFT values A, written for continuous-transform data
+ * d = dt A), and the scalar-product weights w_k = 4 / (T S), constant along the channel.  The
+ * median of an even count is the mean of the two middle values.  windows: host [n_win] (W,
+ * C and data_off are used; W at most 4096); d: device complex128 indexed by data_off (the
+ * residual the estimate follows); w: device float64, each window's C x W block overwritten;
+ * S: device [n_win][3] (channel levels; entries of absent channels untouched) or NULL.  A
+ * window whose median is 0 gets infinite weights.  Synchronous; allocates the window list.
+ * GB_EINVAL on a bad window, T <= 0 or null arrays. */
+gb_status gb_noise_estimate(const gb_window* windows, int n_win, const double* d, double T, double* w, double* S,
+                            void* stream);
+
 /* Log density of weighted 2-D Gaussian kernel density estimates (the pairwise KDE proposals
  * of Sec. III G: (A, iota), (lambda, beta), (f, fdot)), summed over n_pairs pairs, for
  * n_sets independent sets (one per source, so that many sources' annealing stages share a

@@ -23,7 +23,8 @@ PRECISION = {"fp64": GB_FP64, "mixed": GB_MIXED, "per_window": GB_PER_WINDOW}
 
 EXPORTS = ("gb_create", "gb_destroy", "gb_last_error", "gb_waveform", "gb_plan_create",
            "gb_plan_destroy", "gb_window_prepare", "gb_loglik", "gb_loglik_grad", "gb_mh_step",
-           "gb_autotune", "gb_select_variant", "gb_fisher", "gb_kde_logpdf", "gb_add_templates")
+           "gb_autotune", "gb_select_variant", "gb_fisher", "gb_kde_logpdf", "gb_add_templates",
+           "gb_noise_estimate")
 
 
 class GbxError(RuntimeError):
@@ -84,6 +85,8 @@ def lib():
         L.gb_fisher.restype = st
         L.gb_kde_logpdf.argtypes = [_vp, _vp, i, i, i64, _vp, _vp, i64, _vp, _vp]
         L.gb_kde_logpdf.restype = st
+        L.gb_noise_estimate.argtypes = [ctypes.POINTER(gb_window), i, _vp, d, _vp, _vp, _vp]
+        L.gb_noise_estimate.restype = st
         L.gb_add_templates.argtypes = [_vp, ctypes.POINTER(gb_window), i, _vp, ctypes.POINTER(ctypes.c_int32), i, d,
                                        _vp, _vp, _vp]
         L.gb_add_templates.restype = st
@@ -224,6 +227,20 @@ def gb_kde_logpdf(pts: torch.Tensor, wts: torch.Tensor, chol: torch.Tensor, x: t
                                _dev(chol, torch.float64, "chol"), _dev(x, torch.float64, "x"), q,
                                _dev(out, torch.float64, "out"), _stream(stream)), "gb_kde_logpdf")
     return out
+
+
+def gb_noise_estimate(table, d: torch.Tensor, T: float, w: Optional[torch.Tensor] = None, stream=None):
+    """Median-periodogram noise level of every window and channel of ``table`` from the data d,
+    and the weights 4 / (T S) written into w (a copy of d's layout, new unless given).  Returns
+    (w, S [n_win, 3])."""
+    wins = windows_array(table)
+    if w is None:
+        w = torch.zeros(d.shape, dtype=torch.float64, device=d.device)
+    S = torch.zeros((len(wins), 3), dtype=torch.float64, device=d.device)
+    _check(lib().gb_noise_estimate(wins, len(wins), _dev(d, torch.complex128, "d"), float(T),
+                                   _dev(w, torch.float64, "w"), _dev(S, torch.float64, "S"), _stream(stream)),
+           "gb_noise_estimate")
+    return w, S
 
 
 def gb_add_templates(ctx: int, table, theta: torch.Tensor, src_win, sign: float, d_in: torch.Tensor,

@@ -14,6 +14,7 @@
 #include "gbx_kernels.h"
 #include "gbx_chain.h"
 #include "gbx_post.h"
+#include "gbx_noise.h"
 #include "gbx_variants.h"
 
 using namespace gbx;
@@ -654,6 +655,34 @@ extern "C" gb_status gb_add_templates(gb_ctx* c, const gb_window* windows, int n
   for (void* b : bufs) (void)hipFree(b);
   if (status != GB_OK) return status;
   if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? GB_ENOMEM : GB_EHIP, "gb_add_templates: %s", hipGetErrorString(e));
+  return GB_OK;
+}
+
+extern "C" gb_status gb_noise_estimate(const gb_window* windows, int n_win, const double* d, double T, double* w,
+                                       double* S, void* stream) {
+  if (n_win < 0 || (n_win > 0 && (!windows || !d || !w)) || !(T > 0.0) || !std::isfinite(T))
+    return fail(GB_EINVAL, "gb_noise_estimate: bad arguments");
+  if (n_win == 0) return GB_OK;
+  std::vector<NoiseWin> nw(n_win);
+  for (int i = 0; i < n_win; ++i) {
+    const gb_window& g = windows[i];
+    if (g.W < 1 || g.W > kNoiseMaxW || (g.C != 2 && g.C != 3) || g.data_off < 0)
+      return fail(GB_EINVAL, "gb_noise_estimate: window %d: W must be 1..%d, C 2 or 3, offset >= 0", i, kNoiseMaxW);
+    nw[i].data_off = g.data_off;
+    nw[i].W = g.W;
+    nw[i].C = g.C;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  NoiseWin* d_nw = nullptr;
+  hipError_t e = hipMalloc(&d_nw, sizeof(NoiseWin) * n_win);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_nw, nw.data(), sizeof(NoiseWin) * n_win, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_noise_median, dim3((unsigned)n_win, 3), dim3(1024), 0, st, d_nw, d, T, w, S);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(d_nw);
+  if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? GB_ENOMEM : GB_EHIP, "gb_noise_estimate: %s", hipGetErrorString(e));
   return GB_OK;
 }
 

@@ -505,7 +505,7 @@ def _rho_of(comps):
 
 def local_search(backend, seg_edges, rng: np.random.Generator, n_signals: int, rho_threshold: float = 9.0,
                  n_searches: int = 3, pop: int = 512, generations: int = 50, keep: int = 8,
-                 polish_iterations: int = 20, scale_frac: float = 1e-3, joint_sweeps: int = 2):
+                 polish_iterations: int = 20, scale_frac: float = 1e-3, joint_sweeps: int = 2, progress=None):
     """Algorithm 2 for every window of the backend at once (each window = one padded segment;
     seg_edges [n_win, 2] = the unpadded segment's edges in Hz).  Per signal: n_searches DE +
     polish searches on the residual (the first one ends the window when rho on the analysed data
@@ -514,7 +514,8 @@ def local_search(backend, seg_edges, rng: np.random.Generator, n_signals: int, r
     joins theta_in, one outside joins theta_out; then theta_in is refined jointly on the data
     minus theta_out (block-coordinate polish: each source on the data minus all other found
     sources, ``joint_sweeps`` sweeps), and the residual becomes the data minus all found
-    signals.  Returns (theta_in, theta_out): per window a list of parameter vectors."""
+    signals.  ``progress(message)``, if given, hears of every signal step.  Returns (theta_in,
+    theta_out): per window a list of parameter vectors."""
     n_win = backend.n_win
     seg = np.asarray(seg_edges, dtype=np.float64)
     boxes = backend.boxes
@@ -523,9 +524,12 @@ def local_search(backend, seg_edges, rng: np.random.Generator, n_signals: int, r
     found_out = [[] for _ in range(n_win)]
     active = np.ones(n_win, dtype=bool)
     backend.set_residual(found_in, found_out)
-    for _ in range(n_signals):
+    for step in range(n_signals):
         if not active.any():
             break
+        if progress:
+            progress(f"signal {step + 1}: {int(active.sum())} of {n_win} segments still searching, "
+                     f"{sum(len(f) for f in found_in)} found")
         best_th = np.zeros((n_win, 8))
         best_rho = np.full(n_win, -np.inf)
         best_rho_an = np.full(n_win, -np.inf)
@@ -567,13 +571,21 @@ def _box_centre(box: I.PriorBox) -> np.ndarray:
 class GpuSearchBackend(GpuBackend):
     """The library calls of local_search for the windows of ``table``: likelihoods and gradients
     on the current residual (data minus the sources found so far, formed by gb_add_templates),
-    and rho on the analysed data itself."""
+    and rho on the analysed data itself.  noise="psd" keeps the given weights; noise="median"
+    follows the paper's dynamic local estimate: after every change of the residual, each
+    window's weights become 4 / (T S) with S its median periodogram (gb_noise_estimate), and
+    both the residual's and the analysed data's scalar products use them."""
 
-    def __init__(self, ctx, table, d, w, boxes, precision_logl: int, precision_grad: Optional[int] = None):
-        super().__init__(ctx, table, d.clone(), w, precision_logl, precision_grad)
+    def __init__(self, ctx, table, d, w, boxes, precision_logl: int, precision_grad: Optional[int] = None,
+                 noise: str = "psd"):
+        if noise not in ("psd", "median"):
+            raise ValueError("noise must be 'psd' or 'median'")
+        self.noise = noise
+        w_own = w.clone() if noise == "median" else w
+        super().__init__(ctx, table, d.clone(), w_own, precision_logl, precision_grad)
         self.d_analyze = d
         self.boxes = list(boxes)
-        self.analyze = GpuBackend(ctx, table, d, w, self.api.GB_FP64)
+        self.analyze = GpuBackend(ctx, table, d, w_own, self.api.GB_FP64)
 
     def set_residual(self, *lists):
         theta, src = [], []
@@ -584,11 +596,19 @@ class GpuSearchBackend(GpuBackend):
                     src.append(i)
         th = self.torch.as_tensor(np.array(theta).reshape(-1, 8), dtype=self.torch.float64, device="cuda")
         self.api.gb_add_templates(self.ctx.handle, self.table, th, src, -1.0, self.d_analyze, self.d)
+        if self.noise == "median":
+            self.api.gb_noise_estimate(self.table, self.d, self.ctx.T, self.w)
+            for p in self.analyze.plans.values():
+                p.prepare(self.d_analyze, self.w)
         for p in self.plans.values():
             p.prepare(self.d, self.w)
 
     def rho_analyze(self, theta):
         return _rho_of(self.analyze.loglik(theta)[1])
+
+    def close(self):
+        super().close()
+        self.analyze.close()
 
 
 # ---------------------------------------------------------------------------------------------
@@ -622,10 +642,15 @@ def global_search(backend_factory, table, T: float, seg_edges, d, rng: np.random
     seg = np.asarray(seg_edges, dtype=np.float64)
     results = {}
     d_run = d
+    progress = search_kw.get("progress")
     for parity, n_signals in runs:
         rows = np.arange(parity, len(t), 2)
+        if progress:
+            progress(f"run over the {'odd' if parity else 'even'} segments, up to {n_signals} signals each")
         be = backend_factory(rows, d_run)
         found_in, _ = local_search(be, seg[rows], rng, n_signals, **search_kw)
+        if hasattr(be, "close"):
+            be.close()
         results[parity] = [(rows[i], th) for i in range(len(rows)) for th in found_in[i]]
         srcs = np.array([th for _, th in results[parity]]).reshape(-1, 8)
         si, wi = overlapping_windows(t, srcs, T)

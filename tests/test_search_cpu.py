@@ -37,7 +37,7 @@ class OracleSearchBackend:
     for the windows ``rows`` of a workload (all by default) and analysed data ``d`` (the
     workload's by default, same layout)."""
 
-    def __init__(self, O, wl, rows=None, d=None):
+    def __init__(self, O, wl, rows=None, d=None, noise="psd"):
         self.O, self.wl = O, wl
         self.rows = list(range(wl.n_win)) if rows is None else [int(r) for r in rows]
         self.n_win = len(self.rows)
@@ -46,6 +46,8 @@ class OracleSearchBackend:
         self.d = wl.data if d is None else d
         self.an = [self._block(i) for i in self.rows]
         self.res = [a.copy() for a in self.an]
+        self.noise = noise
+        self.ww = [wl.window_data(i)[1] for i in self.rows]
 
     def _block(self, i):
         w = self.wl.windows[i]
@@ -61,14 +63,16 @@ class OracleSearchBackend:
                 h, fb = self.O.waveform(np.array(srcs), w.N, w.C, self.g)
                 I.add_templates(r, w.k0, h, fb, sign=-1.0)
             self.res[j] = r
+            if self.noise == "median":
+                from oracle import noise
+                self.ww[j] = noise.local_weights(r, self.wl.T)
 
     def _each(self, fn, theta, data):
         n = len(theta) // self.n_win
         outs = []
         for j, i in enumerate(self.rows):
             w = self.wl.windows[i]
-            _, ww = self.wl.window_data(i)
-            outs.append(fn(theta[j * n:(j + 1) * n], w.k0, w.W, w.N, w.C, data[j], ww, self.g))
+            outs.append(fn(theta[j * n:(j + 1) * n], w.k0, w.W, w.N, w.C, data[j], self.ww[j], self.g))
         return np.concatenate([o[0] for o in outs]), np.concatenate([o[1] for o in outs])
 
     def loglik(self, theta):
@@ -170,6 +174,18 @@ def test_local_search_cpu(oracle_lib):
     O = oracle_lib
     wl, seg = segments_workload(O)
     be = OracleSearchBackend(O, wl)
+    found_in, found_out = D.local_search(be, seg, np.random.default_rng(3), n_signals=2, n_searches=2,
+                                         pop=256, generations=100, polish_iterations=30)
+    check_search(O, wl, seg, found_in, found_out)
+
+
+def test_local_search_median_noise_cpu(oracle_lib):
+    """Algorithm 2 with the paper's dynamic local noise estimate (median periodogram of the
+    residual in each padded window, updated after every found signal) in place of the true PSD:
+    the same checks on the same three segments."""
+    O = oracle_lib
+    wl, seg = segments_workload(O)
+    be = OracleSearchBackend(O, wl, noise="median")
     found_in, found_out = D.local_search(be, seg, np.random.default_rng(3), n_signals=2, n_searches=2,
                                          pop=256, generations=100, polish_iterations=30)
     check_search(O, wl, seg, found_in, found_out)
