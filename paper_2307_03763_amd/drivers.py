@@ -896,7 +896,8 @@ def posterior_batch(ctx, table, T: float, d_residual, w, sources, seg_rows, boxe
 def match_delta(ctx, table, T: float, w, recovered, rec_rows, injected, n_near: int = 3) -> np.ndarray:
     """Scaled error of Sec. V, delta = <s_rec - s_inj | s_rec - s_inj> / <s_rec | s_rec>, of every
     recovered source against the ``n_near`` injected sources nearest in frequency, in the
-    recovered source's window; returns the smallest delta of each (inf with no injected source).
+    recovered source's window; returns the smallest delta of each (inf with no injected source)
+    and the index of the injected source that gives it (-1 with none).
     One window per (recovered, injected) pair holds the injected template as data, so the
     likelihood kernel's components give delta = -2 logL / <h|h>."""
     import torch
@@ -905,7 +906,7 @@ def match_delta(ctx, table, T: float, w, recovered, rec_rows, injected, n_near: 
     rec = np.atleast_2d(np.asarray(recovered, dtype=np.float64))
     inj = np.atleast_2d(np.asarray(injected, dtype=np.float64))
     if len(rec) == 0 or len(inj) == 0:
-        return np.full(len(rec), np.inf)
+        return np.full(len(rec), np.inf), np.full(len(rec), -1, dtype=np.int64)
     t = np.asarray(table, dtype=np.int64)
     order = np.argsort(inj[:, 0])
     f_sorted = inj[order, 0]
@@ -934,6 +935,8 @@ def match_delta(ctx, table, T: float, w, recovered, rec_rows, injected, n_near: 
     plan.close()
     delta = (-2.0 * l.cpu().numpy()) / c.cpu().numpy()[:, 1]
     best = np.full(len(rec), np.inf)
-    for (k, _), dl in zip(pairs, delta):
-        best[k] = min(best[k], dl)
-    return best
+    which = np.full(len(rec), -1, dtype=np.int64)
+    for (k, j), dl in zip(pairs, delta):
+        if dl < best[k]:
+            best[k], which[k] = dl, j
+    return best, which
