@@ -822,10 +822,11 @@ class GpuPosteriorBatchBackend:
     window holding d_posterior = d_residual + s(theta_MLE) (Algorithm 5); gb_fisher over the
     S windows, gb_mh_step with n proposals per window, gb_kde_logpdf with one set per source."""
 
-    def __init__(self, ctx, table, d_residual, w, sources, rows):
+    def __init__(self, ctx, table, d_residual, w, sources, rows, precision: Optional[int] = None):
         import torch
         from . import api
         self.api, self.torch = api, torch
+        self.precision = api.GB_FP64 if precision is None else precision
         self.device = torch.device("cuda")
         self.ctx = ctx
         t = np.asarray(table, dtype=np.int64)
@@ -854,7 +855,7 @@ class GpuPosteriorBatchBackend:
             tab = self.tab.copy()
             tab[:, 6] = np.arange(len(tab)) * n
             tab[:, 7] = n
-            p = self.api.Plan(self.ctx, tab, self.api.GB_FP64)
+            p = self.api.Plan(self.ctx, tab, self.precision)
             p.prepare(self.d, self.w)
             self.plans[n] = p
         return self.plans[n].mh_step(theta.contiguous(), log_g.contiguous(), u.contiguous(), T)
@@ -870,18 +871,19 @@ class GpuPosteriorBatchBackend:
 
 def posterior_batch(ctx, table, T: float, d_residual, w, sources, seg_rows, boxes, seed: int,
                     n: int = 10000, temps=(15.0, 10.0, 5.0, 3.0, 2.0, 1.0), fd_step: float = 1e-9,
-                    chunk: int = 256):
+                    chunk: int = 256, precision: Optional[int] = None):
     """Algorithm 5's posterior step for every recovered source: ``d_residual`` is the data minus
     all recovered sources (window layout of ``table``), ``seg_rows`` the window of each source;
     the sources run through annealed_posterior_batch ``chunk`` at a time, each on its window
-    plus its own template.  Returns (final-stage states [n_src, n, 8] (numpy), accepted
-    proposals per stage [n_src, n_stages], logL of the final states [n_src, n])."""
+    plus its own template; ``precision`` is the likelihood's (FP64 by default; the Fisher
+    matrix always uses FP64 templates).  Returns (final-stage states [n_src, n, 8] (numpy),
+    accepted proposals per stage [n_src, n_stages], logL of the final states [n_src, n])."""
     src = np.atleast_2d(np.asarray(sources, dtype=np.float64))
     rows = np.asarray(seg_rows, dtype=np.int64)
     states, accepted, logL = [], [], []
     for c0 in range(0, len(src), chunk):
         sl = slice(c0, min(len(src), c0 + chunk))
-        be = GpuPosteriorBatchBackend(ctx, table, d_residual, w, src[sl], rows[sl])
+        be = GpuPosteriorBatchBackend(ctx, table, d_residual, w, src[sl], rows[sl], precision)
         stages, _, _ = annealed_posterior_batch(be, src[sl], [boxes[r] for r in rows[sl]], seed + c0,
                                                 temps=temps, n=n, fd_step=fd_step)
         states.append(stages[-1]["states"].cpu().numpy())
@@ -896,8 +898,10 @@ def posterior_batch(ctx, table, T: float, d_residual, w, sources, seg_rows, boxe
 def match_delta(ctx, table, T: float, w, recovered, rec_rows, injected, n_near: int = 3) -> np.ndarray:
     """Scaled error of Sec. V, delta = <s_rec - s_inj | s_rec - s_inj> / <s_rec | s_rec>, of every
     recovered source against the ``n_near`` injected sources nearest in frequency, in the
-    recovered source's window; returns the smallest delta of each (inf with no injected source)
-    and the index of the injected source that gives it (-1 with none).
+    recovered source's window; returns the smallest delta of each (inf with no injected source),
+    the index of the injected source that gives it (-1 with none), and the largest overlap
+    O = <s_rec | s_inj> / sqrt(<s_rec | s_rec> <s_inj | s_inj>) over the same candidates (the
+    other match metric of Sec. V; -inf with none).
     One window per (recovered, injected) pair holds the injected template as data, so the
     likelihood kernel's components give delta = -2 logL / <h|h>."""
     import torch
@@ -906,7 +910,7 @@ def match_delta(ctx, table, T: float, w, recovered, rec_rows, injected, n_near: 
     rec = np.atleast_2d(np.asarray(recovered, dtype=np.float64))
     inj = np.atleast_2d(np.asarray(injected, dtype=np.float64))
     if len(rec) == 0 or len(inj) == 0:
-        return np.full(len(rec), np.inf), np.full(len(rec), -1, dtype=np.int64)
+        return np.full(len(rec), np.inf), np.full(len(rec), -1, dtype=np.int64), np.full(len(rec), -np.inf)
     t = np.asarray(table, dtype=np.int64)
     order = np.argsort(inj[:, 0])
     f_sorted = inj[order, 0]
@@ -933,10 +937,18 @@ def match_delta(ctx, table, T: float, w, recovered, rec_rows, injected, n_near: 
     plan.prepare(d_p, w_p)
     l, c = plan.loglik(torch.as_tensor(rec[[k for k, _ in pairs]], device=dev), comps=True)
     plan.close()
-    delta = (-2.0 * l.cpu().numpy()) / c.cpu().numpy()[:, 1]
+    l, c = l.cpu().numpy(), c.cpu().numpy()
+    delta = (-2.0 * l) / c[:, 1]
+    # <s_inj|s_inj> = -2 logL + 2 <s_inj|s_rec> - <s_rec|s_rec>
+    ii = -2.0 * l + 2.0 * c[:, 0] - c[:, 1]
+    with np.errstate(invalid="ignore", divide="ignore"):
+        ov = c[:, 0] / np.sqrt(c[:, 1] * ii)
     best = np.full(len(rec), np.inf)
     which = np.full(len(rec), -1, dtype=np.int64)
-    for (k, j), dl in zip(pairs, delta):
+    best_ov = np.full(len(rec), -np.inf)
+    for (k, j), dl, o in zip(pairs, delta, ov):
         if dl < best[k]:
             best[k], which[k] = dl, j
-    return best, which
+        if o > best_ov[k]:
+            best_ov[k] = o
+    return best, which, best_ov

@@ -106,17 +106,20 @@ def test_match_delta_gpu(oracle_lib):
     rec[:, 0] += rng.uniform(-0.4, 0.4, len(src)) / wl.T
     rec[:, 4] *= rng.uniform(0.8, 1.2, len(src))
     rec[0] = src[0]
-    got, which = D.match_delta(ctx, table, wl.T, dev(wl.weights), rec, rows, src)
-    assert abs(got[0]) < 1e-12 and which[0] == 0
+    got, which, ov = D.match_delta(ctx, table, wl.T, dev(wl.weights), rec, rows, src)
+    assert abs(got[0]) < 1e-12 and which[0] == 0 and abs(ov[0] - 1.0) < 1e-12
     for k in range(len(rec)):
         _, ww = wl.window_data(rows[k])
         h_r = _oracle_block(O, wl, rows[k], rec[k])
         near = np.argsort(np.abs(src[:, 0] - rec[k, 0]))[:3]
-        refs = [np.sum(ww * np.abs(h_r - _oracle_block(O, wl, rows[k], src[j])) ** 2) / np.sum(ww * np.abs(h_r) ** 2)
-                for j in near]
+        h_i = [_oracle_block(O, wl, rows[k], src[j]) for j in near]
+        refs = [np.sum(ww * np.abs(h_r - h) ** 2) / np.sum(ww * np.abs(h_r) ** 2) for h in h_i]
+        ovs = [np.sum(ww * (h_r * h.conj()).real) / np.sqrt(np.sum(ww * np.abs(h_r) ** 2) * np.sum(ww * np.abs(h) ** 2))
+               for h in h_i]
         ref = min(refs)
         assert abs(got[k] - ref) <= 1e-10 * max(ref, 1e-3), (k, got[k], ref)
         assert which[k] == near[int(np.argmin(refs))]
+        assert abs(ov[k] - max(ovs)) <= 1e-9, (k, ov[k], max(ovs))
 
 
 def test_posterior_batch_gpu(oracle_lib):
