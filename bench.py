@@ -696,7 +696,7 @@ def cpu_baseline(wl, seconds, logL_gpu, rho_w, log):
     order = sorted(range(wl.n_win), key=lambda i: (wl.windows[i].N, wl.windows[i].C))
     sample = order[:: max(1, len(order) // 16)][:16]
     lg = np.asarray(logL_gpu)
-    def run(n_cand):
+    def run(n_cand, sample):
         nonlocal_max = 0.0
         t = time.time()
         evals = 0
@@ -713,11 +713,17 @@ def cpu_baseline(wl, seconds, logL_gpu, rho_w, log):
             nonlocal_max = max(nonlocal_max, float(np.max(np.abs(dl) / np.maximum(1.0, np.abs(l - l[0])))))
         return evals, time.time() - t, nonlocal_max
 
-    ev1, dt1, _ = run(32)                       # pilot, then size the sample to `seconds`
-    n_cand = int(min(10000, max(32, 32 * (seconds - dt1) / max(dt1, 1e-3))))
-    evals, spent, max_dl = run(n_cand)
+    # pilot, then size the sample to `seconds`: more candidates per window up to all of a
+    # window's, then more windows (at most 64), spread over the (N, C) groups
+    ev1, dt1, _ = run(256, sample)
+    per = max(dt1, 1e-3) / (256 * len(sample))
+    n_cand = int(min(10000, max(256, seconds / (per * len(sample)))))
+    if n_cand == 10000:
+        n_w = int(min(64, len(order), max(16, seconds / (per * 10000))))
+        sample = order[:: max(1, len(order) // n_w)][:n_w]
+    evals, spent, max_dl = run(n_cand, sample)
     errs = {}
-    for i in sample:
+    for i in sample[:: max(1, len(sample) // 16)]:
         win = wl.windows[i]
         dd, ww = wl.window_data(i)
         th = wl.window_theta(i)[:64]

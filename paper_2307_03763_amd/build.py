@@ -20,6 +20,10 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 instructions stay off (hipcc would otherwise form them from float code)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # FP64 multiply-adds as the three-address v_fma_f64: with the two-address v_fmac_f64 form
+    # the compiler copies every loop-invariant polynomial coefficient into the destination
+    # first (132 extra moves per sample in the FP64 likelihood loop); same arithmetic
+    "-Xclang", "-target-feature", "-Xclang", "-fmacf64-inst",
     "-Wall", "-Wno-unused-function",
     "-I", os.path.join(ROOT, "include"),
 ]

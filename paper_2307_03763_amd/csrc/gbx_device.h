@@ -63,12 +63,11 @@ __device__ __forceinline__ cplx<R> mul_i(cplx<R> a) { return mk<R>(-a.y, a.x); }
 template <class R>
 __device__ __forceinline__ cplx<R> mul_mi(cplx<R> a) { return mk<R>(a.y, -a.x); }    // -i a
 
-// sin and cos of 2 pi x (x in cycles).  FP64: sincospi.  FP32: the hardware
-// transcendentals, which take their argument in revolutions; |x| <= 1 here.
 // sin and cos of 2 pi x, x in revolutions (FP64).  Quadrant reduction x = n/4 + r with
 // n = rint(4x) and |r| <= 1/8 (both steps exact for |x| < 2^50), the Taylor series of sin and
 // cos at theta = 2 pi r, |theta| <= pi/4 (first omitted terms: theta^17/17! < 5e-17 and
-// theta^18/18! < 3e-18), then a rotation by n quarter turns.
+// theta^18/18! < 3e-18), then a rotation by n quarter turns (n mod 4 formed in FP64, exact,
+// so that no 64-bit integer conversion is needed).
 __device__ __forceinline__ void sincos_rev(double x, double* s, double* c) {
   const double n = rint(4.0 * x);
   const double r = fma(n, -0.25, x);
@@ -92,11 +91,13 @@ __device__ __forceinline__ void sincos_rev(double x, double* s, double* c) {
   pc = fma(pc, t2, -0.5);                  // -1/2!
   const double cs = fma(pc, t2, 1.0);
   // e^{i 2 pi x} = i^n e^{i theta}
-  const int q = (int)(long long)n & 3;
+  const int q = (int)fma(floor(n * 0.25), -4.0, n);  // n mod 4, in {0, 1, 2, 3}
   const double a = (q & 1) ? cs : sn, b = (q & 1) ? sn : cs;
   *s = (q & 2) ? -a : a;
   *c = (q == 1 || q == 2) ? -b : b;
 }
+// FP32: the hardware transcendentals, which take their argument in revolutions (|x| <= 1 on
+// every call here).
 __device__ __forceinline__ void sincos_rev(float x, float* s, float* c) {
   *s = __builtin_amdgcn_sinf(x);
   *c = __builtin_amdgcn_cosf(x);

@@ -8,10 +8,11 @@ using namespace gbx;
 #define V(NN, LL, CC, OO) \
   Variant { GB_FP64, NN, LL, CC, 4, MODE_LOGLIK, OO, reinterpret_cast<const void*>(&k_batch<double, NN, LL, CC, 4, MODE_LOGLIK, OO>) }
 #define VC(NN, LL, OO) V(NN, LL, 2, OO), V(NN, LL, 3, OO)
-// per N: 4 and 8 samples per lane, two register budgets; the first entry is the default
+// per N: 4 and 8 samples per lane, three register budgets (2, 1 and 3 waves per SIMD); the
+// first entry is the default
 #define VN(OO) VC(64, 16, OO), VC(128, 32, OO), VC(256, 64, OO), VC(512, 128, OO), VC(1024, 256, OO), \
                VC(64, 8, OO), VC(128, 16, OO), VC(256, 32, OO), VC(512, 64, OO), VC(1024, 128, OO)
 
-static const Variant kTable[] = {VN(2), VN(1)};
+static const Variant kTable[] = {VN(2), VN(1), VN(3)};
 
 extern "C" VariantList gbx_variants_f64_loglik() { return VariantList{kTable, (int)(sizeof kTable / sizeof kTable[0])}; }
