@@ -196,6 +196,35 @@ gb_status gb_add_templates(gb_ctx* ctx, const gb_window* windows, int n_win, con
 gb_status gb_noise_estimate(const gb_window* windows, int n_win, const double* d, double T, double* w, double* S,
                             void* stream);
 
+/* One generation of the differential-evolution search (DE/rand/1/bin of Storn and Price, the
+ * optimiser the paper's search uses, Sec. III), trial step, for n_win windows with pop members
+ * each (pop >= 4), over the seven searched Table I coordinates in the order f0, fdot, sin(beta),
+ * lambda, cos(iota), psi, phi0 (the amplitude is not searched: the SNR does not depend on it).
+ * For member i of window w:
+ *   donors a, b, c: distinct and different from i, uniform; from u_idx[w][i][0..2] in [0, 1):
+ *     a = floor(u0 (pop-1)), then b = floor(u1 (pop-2)), c = floor(u2 (pop-3)), each stepped
+ *     past the indices already taken, in increasing order;
+ *   mutant m = x_a + F[w] (x_b - x_c), each product and sum rounded separately; lambda, psi and
+ *     phi0 wrap into [lo, hi) (exact remainder), the others reflect once at the walls and are
+ *     clipped to [lo, hi];
+ *   trial coordinate k = m_k where u_cross[w][i][k] < cr or k = floor(u_j[w][i] 7), else x_i,k.
+ * lo, hi: device [n_win][7] (the window's box); x: device [n_win][pop][7], the population;
+ * u_idx: device [n_win][pop][3]; u_cross: device [n_win][pop][7]; u_j: device [n_win][pop];
+ * F: device [n_win]; outputs trial_x [n_win][pop][7] and trial_theta [n_win * pop][8] (the
+ * parameters of each trial with amplitude `amp`, ready for gb_loglik).  Asynchronous;
+ * allocates nothing.  GB_EINVAL on pop < 4, cr outside [0, 1] or null arrays. */
+gb_status gb_de_trial(int n_win, int pop, const double* lo, const double* hi, const double* x, const double* u_idx,
+                      const double* u_cross, const double* u_j, const double* F, double cr, double amp,
+                      double* trial_x, double* trial_theta, void* stream);
+
+/* Selection step of the same generation: rho = <d|h>/sqrt(<h|h>) of every trial from its
+ * gb_loglik components (comps: device [n_win * pop][2]; a rho that is not a finite number counts
+ * as -inf); where rho exceeds s[w][i], the trial replaces member i of x and rho replaces s.
+ * best: device [n_win], the largest s of each window afterwards.  x and trial_x may be the same
+ * array (scoring an initial population with s = -inf).  Asynchronous; allocates nothing. */
+gb_status gb_de_select(int n_win, int pop, const double* comps, double* x, double* s, const double* trial_x,
+                       double* best, void* stream);
+
 /* Log density of weighted 2-D Gaussian kernel density estimates (the pairwise KDE proposals
  * of Sec. III G: (A, iota), (lambda, beta), (f, fdot)), summed over n_pairs pairs, for
  * n_sets independent sets (one per source, so that many sources' annealing stages share a

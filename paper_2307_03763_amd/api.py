@@ -24,7 +24,7 @@ PRECISION = {"fp64": GB_FP64, "mixed": GB_MIXED, "per_window": GB_PER_WINDOW}
 EXPORTS = ("gb_create", "gb_destroy", "gb_last_error", "gb_waveform", "gb_plan_create",
            "gb_plan_destroy", "gb_window_prepare", "gb_loglik", "gb_loglik_grad", "gb_mh_step",
            "gb_autotune", "gb_select_variant", "gb_fisher", "gb_kde_logpdf", "gb_add_templates",
-           "gb_noise_estimate")
+           "gb_noise_estimate", "gb_de_trial", "gb_de_select")
 
 
 class GbxError(RuntimeError):
@@ -87,6 +87,10 @@ def lib():
         L.gb_kde_logpdf.restype = st
         L.gb_noise_estimate.argtypes = [ctypes.POINTER(gb_window), i, _vp, d, _vp, _vp, _vp]
         L.gb_noise_estimate.restype = st
+        L.gb_de_trial.argtypes = [i, i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, d, d, _vp, _vp, _vp]
+        L.gb_de_trial.restype = st
+        L.gb_de_select.argtypes = [i, i, _vp, _vp, _vp, _vp, _vp, _vp]
+        L.gb_de_select.restype = st
         L.gb_add_templates.argtypes = [_vp, ctypes.POINTER(gb_window), i, _vp, ctypes.POINTER(ctypes.c_int32), i, d,
                                        _vp, _vp, _vp]
         L.gb_add_templates.restype = st
@@ -241,6 +245,44 @@ def gb_noise_estimate(table, d: torch.Tensor, T: float, w: Optional[torch.Tensor
                                    _dev(w, torch.float64, "w"), _dev(S, torch.float64, "S"), _stream(stream)),
            "gb_noise_estimate")
     return w, S
+
+
+def gb_de_trial(lo: torch.Tensor, hi: torch.Tensor, x: torch.Tensor, u_idx: torch.Tensor, u_cross: torch.Tensor,
+                u_j: torch.Tensor, F: torch.Tensor, cr: float, amp: float, trial_x: Optional[torch.Tensor] = None,
+                trial_theta: Optional[torch.Tensor] = None, stream=None):
+    """DE/rand/1/bin trials of every member: x [n_win, pop, 7], lo/hi [n_win, 7], u_idx
+    [n_win, pop, 3], u_cross [n_win, pop, 7], u_j [n_win, pop], F [n_win] -> (trial_x
+    [n_win, pop, 7], trial_theta [n_win * pop, 8])."""
+    n_win, pop = int(x.shape[0]), int(x.shape[1])
+    if (tuple(x.shape) != (n_win, pop, 7) or tuple(lo.shape) != (n_win, 7) or tuple(hi.shape) != (n_win, 7)
+            or tuple(u_idx.shape) != (n_win, pop, 3) or tuple(u_cross.shape) != (n_win, pop, 7)
+            or tuple(u_j.shape) != (n_win, pop) or tuple(F.shape) != (n_win,)):
+        raise ValueError("gb_de_trial: inconsistent shapes")
+    if trial_x is None:
+        trial_x = torch.empty_like(x)
+    if trial_theta is None:
+        trial_theta = torch.empty((n_win * pop, 8), dtype=torch.float64, device=x.device)
+    f = lambda t, n: _dev(t, torch.float64, n)
+    _check(lib().gb_de_trial(n_win, pop, f(lo, "lo"), f(hi, "hi"), f(x, "x"), f(u_idx, "u_idx"), f(u_cross, "u_cross"),
+                             f(u_j, "u_j"), f(F, "F"), float(cr), float(amp), f(trial_x, "trial_x"),
+                             f(trial_theta, "trial_theta"), _stream(stream)), "gb_de_trial")
+    return trial_x, trial_theta
+
+
+def gb_de_select(comps: torch.Tensor, x: torch.Tensor, s: torch.Tensor, trial_x: torch.Tensor,
+                 best: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Greedy DE selection in place on x [n_win, pop, 7] and s [n_win, pop] from the trials'
+    components comps [n_win * pop, 2]; returns best [n_win] (largest rho per window)."""
+    n_win, pop = int(x.shape[0]), int(x.shape[1])
+    if (tuple(comps.shape) != (n_win * pop, 2) or tuple(s.shape) != (n_win, pop) or tuple(trial_x.shape) != (n_win, pop, 7)
+            or tuple(x.shape) != (n_win, pop, 7)):
+        raise ValueError("gb_de_select: inconsistent shapes")
+    if best is None:
+        best = torch.empty(n_win, dtype=torch.float64, device=x.device)
+    f = lambda t, n: _dev(t, torch.float64, n)
+    _check(lib().gb_de_select(n_win, pop, f(comps, "comps"), f(x, "x"), f(s, "s"), f(trial_x, "trial_x"),
+                              f(best, "best"), _stream(stream)), "gb_de_select")
+    return best
 
 
 def gb_add_templates(ctx: int, table, theta: torch.Tensor, src_win, sign: float, d_in: torch.Tensor,

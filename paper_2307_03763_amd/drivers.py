@@ -41,7 +41,10 @@ class GpuBackend:
     """Batched logL / gradient through the HIP library for the windows of ``table`` (rows as in
     ``Workload.window_table``: k0, W, N, C, data_off, w_off, ...; an optional 9th column holds the
     per-window precision for GB_PER_WINDOW).  The candidate slices are rewritten per call; plans
-    are cached per (candidates per window, precision)."""
+    are cached per (candidates per window, precision).  The DE search runs on the device with
+    this backend (gb_de_trial / gb_de_select; population and scores stay in HBM)."""
+
+    device_de = True
 
     def __init__(self, ctx, table, d, w, precision_logl: int, precision_grad: Optional[int] = None):
         import torch
@@ -139,11 +142,13 @@ def _to_theta(x: np.ndarray) -> np.ndarray:
 
 def de_search(backend, boxes, rng: np.random.Generator, pop: int = 512, generations: int = 50,
               cr: float = 0.7, f_lo: float = 0.5, f_hi: float = 1.0, init: Optional[np.ndarray] = None,
-              keep: int = 1):
+              keep: int = 1, on_device: Optional[bool] = None):
     """Maximise rho over the seven non-amplitude parameters inside each window's Table I box.
 
     ``boxes`` is one PriorBox per window of the backend (or a single one for one window);
-    ``init`` optionally seeds member 0 of each population ([n_win, 8] or [8]).  Returns
+    ``init`` optionally seeds member 0 of each population ([n_win, 8] or [8]).  With a backend
+    that offers it (``device_de``) the generations run on the device (``on_device`` False keeps
+    them on the host: the same DE with NumPy's random streams).  Returns
     (theta [n_win, keep, 8] of the best ``keep`` members with A = A_max, rho [n_win, keep],
     history [generations + 1, n_win] of the best rho per generation)."""
     lo, hi = _box_arrays(boxes)
@@ -151,6 +156,11 @@ def de_search(backend, boxes, rng: np.random.Generator, pop: int = 512, generati
     n_win, dim = lo.shape
     if pop < 4 or not 1 <= keep <= pop:
         raise ValueError("DE/rand/1 needs pop >= 4 and 1 <= keep <= pop")
+    if on_device is None:
+        on_device = getattr(backend, "device_de", False)
+    if on_device:
+        x, s, history = _de_device(backend, lo, hi, rng, pop, generations, cr, f_lo, f_hi, init)
+        return _de_finish(backend, x, s, history, keep)
     x = lo[:, None, :] + (hi - lo)[:, None, :] * rng.random((n_win, pop, dim))
     if init is not None:
         x[:, 0, :] = I.to_table1(np.broadcast_to(init, (n_win, 8)))[:, list(SEARCH_DIMS)]
@@ -175,6 +185,51 @@ def de_search(backend, boxes, rng: np.random.Generator, pop: int = 512, generati
         x[better] = trial[better]
         s[better] = s_trial[better]
         history.append(s.max(axis=1))
+    return _de_finish(backend, x, s, np.array(history), keep)
+
+
+def _de_device(backend, lo, hi, rng, pop, generations, cr, f_lo, f_hi, init):
+    """The DE generations with the population, scores and random draws in device memory: per
+    generation one gb_de_trial, one gb_loglik of all trials and one gb_de_select, with no copy
+    to the host (the uniforms come from a torch generator seeded by ``rng``; F is drawn from
+    ``rng`` as in the host loop).  Returns (x, s, history) as NumPy arrays."""
+    torch, api = backend.torch, backend.api
+    dev = torch.device("cuda")
+    f64 = torch.float64
+    n_win, dim = lo.shape
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(int(rng.integers(0, 2 ** 62)))
+    lo_t = torch.as_tensor(np.ascontiguousarray(lo), dtype=f64, device=dev)
+    hi_t = torch.as_tensor(np.ascontiguousarray(hi), dtype=f64, device=dev)
+    x = lo_t[:, None, :] + (hi_t - lo_t)[:, None, :] * torch.rand((n_win, pop, dim), generator=gen, dtype=f64,
+                                                                   device=dev)
+    if init is not None:
+        x0 = I.to_table1(np.broadcast_to(np.asarray(init, dtype=np.float64), (n_win, 8)))[:, list(SEARCH_DIMS)]
+        x[:, 0, :] = torch.as_tensor(np.ascontiguousarray(x0), device=dev)
+    x = x.contiguous()
+    s = torch.full((n_win, pop), -np.inf, dtype=f64, device=dev)
+    plan = backend._plan(pop, backend.pl)
+    th0 = torch.as_tensor(np.ascontiguousarray(_to_theta(x.cpu().numpy()).reshape(n_win * pop, 8)), device=dev)
+    _, comps = plan.loglik(th0, comps=True)
+    hist = [api.gb_de_select(comps, x, s, x.clone())]
+    trial_x = torch.empty_like(x)
+    trial_th = torch.empty((n_win * pop, 8), dtype=f64, device=dev)
+    F = torch.empty(n_win, dtype=f64, device=dev)
+    for _ in range(generations):
+        u_idx = torch.rand((n_win, pop, 3), generator=gen, dtype=f64, device=dev)
+        u_cross = torch.rand((n_win, pop, dim), generator=gen, dtype=f64, device=dev)
+        u_j = torch.rand((n_win, pop), generator=gen, dtype=f64, device=dev)
+        F.fill_(float(rng.uniform(f_lo, f_hi)))
+        api.gb_de_trial(lo_t, hi_t, x, u_idx, u_cross, u_j, F, cr, REF_AMP, trial_x, trial_th)
+        _, comps = plan.loglik(trial_th, comps=True)
+        hist.append(api.gb_de_select(comps, x, s, trial_x))
+    return x.cpu().numpy(), s.cpu().numpy(), torch.stack(hist).cpu().numpy()
+
+
+def _de_finish(backend, x, s, history, keep):
+    """The best ``keep`` members of every window with A = A_max, their rho, and the history."""
+    n_win, pop, _ = x.shape
+    wi = np.arange(n_win)[:, None]
     order = np.argsort(-s, axis=1, kind="stable")[:, :keep]
     th = _to_theta(x[wi, order])                               # [n_win, keep, 8]
     # A_max of the kept members: one more batched call, padded to the population size so
@@ -184,7 +239,7 @@ def de_search(backend, boxes, rng: np.random.Generator, pop: int = 512, generati
     _, comps = backend.loglik(pad.reshape(n_win * pop, 8))
     comps = comps.reshape(n_win, pop, 2)[:, :keep, :]
     th[..., 4] = REF_AMP * comps[..., 0] / comps[..., 1]
-    return th, s[wi, order], np.array(history)
+    return th, s[wi, order], history
 
 
 def _table1_jacobian(theta: np.ndarray) -> np.ndarray:

@@ -45,11 +45,12 @@ def env(oracle_lib):
 
 
 def test_de_search_gpu_follows_oracle(env):
-    banner("drivers: DE search on two C4 windows, FP64 scoring, GPU vs oracle-driven")
+    banner("drivers: DE search on two C4 windows, FP64 scoring, GPU vs oracle-driven (host generations)")
     api, D, O, wl = env["api"], env["D"], env["O"], env["c4"]
     be, *_ = _gpu_backend(api, D, wl, [0, 1], api.GB_FP64)
     boxes = [wl.window_box(0), wl.window_box(1)]
-    th_g, rho_g, hist_g = D.de_search(be, boxes, np.random.default_rng(7), pop=256, generations=40, keep=4)
+    th_g, rho_g, hist_g = D.de_search(be, boxes, np.random.default_rng(7), pop=256, generations=40, keep=4,
+                                      on_device=False)
     th_o, rho_o, hist_o = D.de_search(OracleBackend(O, wl, [0, 1]), boxes, np.random.default_rng(7),
                                       pop=256, generations=40, keep=4)
     np.testing.assert_allclose(hist_g, hist_o, rtol=1e-10)
@@ -64,7 +65,7 @@ def test_search_gpu_finds_sources(env):
     be, *_ = _gpu_backend(api, D, wl, [0, 1], api.GB_FP64, api.GB_MIXED)
     boxes = [wl.window_box(0), wl.window_box(1)]
     th, l = D.search(be, boxes, np.random.default_rng(7), pop=256, generations=120, keep=8,
-                     polish_iterations=40)
+                     polish_iterations=40, n_searches=3)
     for i in range(2):
         one = OracleBackend(O, wl, [i])
         l_or, c_or = one.loglik(th[i][None, :])
