@@ -289,7 +289,7 @@ def polish(backend, theta0: np.ndarray, scale: np.ndarray, iterations: int = 20,
         if not active.any():
             hist.append(cur.copy())
             continue
-        p = np.einsum("wkij,wkj->wki", H, gx)
+        p = np.matmul(H, gx[..., None])[..., 0]
         bad = np.sum(p * gx, axis=-1) <= 0.0
         if bad.any():                                           # not an ascent direction
             H[bad] = np.eye(8)
@@ -316,9 +316,10 @@ def polish(backend, theta0: np.ndarray, scale: np.ndarray, iterations: int = 20,
         upd = move & (sy > 1e-12 * np.linalg.norm(sk, axis=-1) * np.linalg.norm(yk, axis=-1))
         if upd.any():
             r = 1.0 / sy[upd]
-            V = np.eye(8)[None] - r[:, None, None] * np.einsum("bi,bj->bij", sk[upd], yk[upd])
-            H[upd] = (np.einsum("bij,bjk,blk->bil", V, H[upd], V)
-                      + r[:, None, None] * np.einsum("bi,bj->bij", sk[upd], sk[upd]))
+            su, yu = sk[upd], yk[upd]
+            V = np.eye(8)[None] - r[:, None, None] * (su[:, :, None] * yu[:, None, :])
+            H[upd] = (np.matmul(np.matmul(V, H[upd]), V.transpose(0, 2, 1))
+                      + r[:, None, None] * (su[:, :, None] * su[:, None, :]))
         cur = np.where(move, best, cur)
         th, x, gx = th_new, x_new, gx_new
         hist.append(cur.copy())
