@@ -64,7 +64,10 @@ def test_search_gpu_finds_sources(env):
     api, D, O, wl = env["api"], env["D"], env["O"], env["c4"]
     be, *_ = _gpu_backend(api, D, wl, [0, 1], api.GB_FP64, api.GB_MIXED)
     boxes = [wl.window_box(0), wl.window_box(1)]
-    th, l = D.search(be, boxes, np.random.default_rng(7), pop=256, generations=120, keep=8,
+    # window 0 holds one weak source (SNR 18) in a wide box: DE with 256 members reaches SNR
+    # 6-11 after 120 generations and 14-16 after 600 (host and device generations alike), so
+    # the search runs 400 generations and the paper's three restarts
+    th, l = D.search(be, boxes, np.random.default_rng(7), pop=256, generations=400, keep=8,
                      polish_iterations=40, n_searches=3)
     for i in range(2):
         one = OracleBackend(O, wl, [i])
