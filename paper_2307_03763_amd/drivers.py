@@ -804,7 +804,7 @@ class PairKDEBatch:
         dev = self.u.device
         out = torch.empty((S, n, 8), dtype=torch.float64, device=dev)
         filled = torch.zeros(S, dtype=torch.int64, device=dev)
-        for _ in range(1000):
+        for _ in range(200):
             sel = torch.nonzero(filled < n).reshape(-1)
             if len(sel) == 0:
                 break
@@ -819,12 +819,19 @@ class PairKDEBatch:
             dst = filled[sel][s_idx] + rank[s_idx, c_idx] - 1
             out[sel[s_idx], dst] = cand[s_idx, c_idx]
             filled[sel] += got
-        if bool((filled < n).any().item()):
-            raise RuntimeError("KDE proposals keep leaving the prior box")
+        # a source whose KDE keeps proposing outside the prior box (its chain pressed against a
+        # wall) falls back to proposals uniform in its reduced box for this stage
+        fallback = filled < n
+        if bool(fallback.any().item()):
+            fb = torch.nonzero(fallback).reshape(-1)
+            r = torch.rand((len(fb), n, 8), generator=gen, dtype=torch.float64, device=dev)
+            out[fb] = self.lo_b[fb][:, None, :] + (self.hi_b[fb] - self.lo_b[fb])[:, None, :] * r
         x = torch.stack([out[:, :, [a, b]] for a, b in KDE_PAIRS], dim=2)                   # [S, n, 3, 2]
         pts = torch.stack([self.pts[:, :, [a, b]] for a, b in KDE_PAIRS], dim=1)            # [S, 3, m, 2]
         wts = self.w[:, None, :].expand(S, len(KDE_PAIRS), self.w.shape[1]).contiguous()
         log_g = backend.kde_logpdf(pts.contiguous(), wts, self.chol.contiguous(), x.contiguous())
+        log_g[fallback] = 0.0
+        self.fallback = fallback
         return out, log_g
 
 

@@ -414,8 +414,12 @@ def workload_c2(template_fn: Optional[TemplateFn], n_cand: int = 10000, noise: b
 
 
 def reduced_box(theta_mle: np.ndarray, box: PriorBox, sigma: Optional[np.ndarray]):
-    """Theta_reduced of Sec. III G in Table I coordinates, intersected with the prior box."""
+    """Theta_reduced of Sec. III G in Table I coordinates, intersected with the prior box.  The
+    maximum is first brought into the prior box in its bounded coordinates (an unconstrained
+    polish can end just outside it), so that the reduced box is never empty."""
     u = to_table1(theta_mle)
+    for i in (0, 1, 2, 4, 5):
+        u[i] = min(max(u[i], box.lo[i]), box.hi[i])
     s = sigma if sigma is not None else 1e-3 * box.width
     lo = u - 4 * s
     hi = u + 4 * s
@@ -423,7 +427,7 @@ def reduced_box(theta_mle: np.ndarray, box: PriorBox, sigma: Optional[np.ndarray
     lo[1], hi[1] = box.lo[1], box.hi[1]
     lo[6], hi[6] = u[6] - math.pi / 1000, u[6] + math.pi / 1000
     lo[7], hi[7] = u[7] - 2 * math.pi / 1000, u[7] + 2 * math.pi / 1000
-    for i in (2, 3, 4, 5):
+    for i in (0, 2, 3, 4, 5):
         lo[i] = max(lo[i], box.lo[i])
         hi[i] = min(hi[i], box.hi[i])
     return lo, hi
