@@ -68,7 +68,7 @@ def parse():
     ap.add_argument("--no-posterior", action="store_true")
     ap.add_argument("--posterior-sources", type=int, default=3)
     ap.add_argument("--no-pipeline", action="store_true")
-    ap.add_argument("--pipeline-segments", type=int, nargs=2, default=(2400, 2496), metavar=("FIRST", "END"),
+    ap.add_argument("--pipeline-segments", type=int, nargs=2, default=(2000, 3000), metavar=("FIRST", "END"),
                     help="the contiguous block of the 4000 full-band segments that the pipeline leg analyses")
     ap.add_argument("--pipeline-full", action="store_true", help="the pipeline leg over all 4000 segments")
     ap.add_argument("--pipeline-only", action="store_true", help="run the pipeline leg alone and print its JSON")
@@ -590,10 +590,10 @@ def posterior_leg(n_sources, log):
 def pipeline_leg(segments, log, precision: str = "mixed", **search_kw):
     """Algorithm 5 end to end over a contiguous block of the full-band workload (4000 segments
     over 0.3-30 mHz, 20,000 GBs, T = 2^22*15 s, PSD noise): the global search (Algorithm 3 with
-    the three runs of Table II; per signal three searches of DE with 512 members x 50
-    generations plus the gradient polish, four joint sweeps; mixed gradient, the likelihood in
-    ``precision``), the residual, and the annealed posterior (6 x 10,000) of every recovered
-    source, batched, its likelihood in ``precision`` too.  Wall-clock seconds per
+    the three runs of Table II; per signal three searches of DE with 512 members x 300
+    generations on the device plus the gradient polish, four joint sweeps; mixed gradient, the
+    likelihood in ``precision``), the residual, and the annealed posterior (6 x 10,000) of every
+    recovered source, batched, its likelihood in ``precision`` too.  Wall-clock seconds per
     phase (host work included); recovered sources scored with the match metric of Sec. V
     (delta < 0.3 against the nearest injected sources) and injected sources counted by their
     optimal SNR in their segment's window."""
@@ -640,7 +640,7 @@ def pipeline_leg(segments, log, precision: str = "mixed", **search_kw):
 
     torch.cuda.synchronize()
     t0 = time.time()
-    kw = dict(n_searches=3, pop=512, generations=150, polish_iterations=20, joint_sweeps=4)
+    kw = dict(n_searches=3, pop=512, generations=300, polish_iterations=20, joint_sweeps=4)
     kw.update(search_kw)
     found, found_seg = D.global_search(factory, table, T, segs, d, np.random.default_rng(2023), subtract,
                                        progress=lambda m: log(f"pipeline: {m}"), **kw)
