@@ -72,6 +72,10 @@ def parse():
                     help="the contiguous block of the 4000 full-band segments that the pipeline leg analyses")
     ap.add_argument("--pipeline-full", action="store_true", help="the pipeline leg over all 4000 segments")
     ap.add_argument("--pipeline-only", action="store_true", help="run the pipeline leg alone and print its JSON")
+    ap.add_argument("--pipeline-catalogue", metavar="NPZ",
+                    help="also write the pipeline's catalogue (recovered parameters, their segment, delta, "
+                         "matched injection; the injected set with optimal SNRs; posterior samples' mean and "
+                         "standard deviation) to this .npz file")
     ap.add_argument("--traffic", nargs=4, metavar=("K_FETCH_DIR", "K_WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="print the profiles/hbm_traffic.txt line from rocprofv3 --pmc outputs and exit")
     ap.add_argument("--tune-from", metavar="BENCH_JSON",
@@ -110,7 +114,7 @@ def main():
     log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
     if args.pipeline_only:
         print(json.dumps({"pipeline": pipeline_leg(None if args.pipeline_full else tuple(args.pipeline_segments),
-                                                   log)}), flush=True)
+                                                   log, catalogue=args.pipeline_catalogue)}), flush=True)
         return
 
     # ---------------------------------------------------------------- workload (resident in HBM)
@@ -294,7 +298,8 @@ def main():
 
     pipe = None
     if not args.no_pipeline:
-        pipe = pipeline_leg(None if args.pipeline_full else tuple(args.pipeline_segments), log)
+        pipe = pipeline_leg(None if args.pipeline_full else tuple(args.pipeline_segments), log,
+                            catalogue=args.pipeline_catalogue)
 
     cpu = None
     if not args.no_cpu:
@@ -587,7 +592,7 @@ def posterior_leg(n_sources, log):
             "context": "paper: 1.8 s per signal for the same six stages on a Quadro RTX 4000 Mobile"}
 
 
-def pipeline_leg(segments, log, precision: str = "mixed", **search_kw):
+def pipeline_leg(segments, log, precision: str = "mixed", catalogue=None, **search_kw):
     """Algorithm 5 end to end over a contiguous block of the full-band workload (4000 segments
     over 0.3-30 mHz, 20,000 GBs, T = 2^22*15 s, PSD noise): the global search (Algorithm 3 with
     the three runs of Table II; per signal three searches of DE with 512 members x 300
@@ -658,6 +663,11 @@ def pipeline_leg(segments, log, precision: str = "mixed", **search_kw):
     delta, which, overlap = D.match_delta(ctx, table, T, w, found, found_seg, inj)
     matched = delta < 0.3
     inj_matched = np.unique(which[matched])
+    if catalogue:
+        np.savez(catalogue, recovered=found, recovered_segment=found_seg, delta=delta, matched_injection=which,
+                 overlap=overlap, injected=inj, injected_segment=inj_seg, injected_rho=rho_opt, segments=segs,
+                 posterior_mean=(states.mean(axis=1) if len(states) else np.zeros((0, 8))),
+                 posterior_std=(states.std(axis=1) if len(states) else np.zeros((0, 8))))
     return {
         "workload": f"full band 0.3-30 mHz in 4000 segments, 20,000 GBs, T=2^22*15 s, PSD noise; segments "
                     f"{'all' if segments is None else f'{segments[0]}..{segments[1] - 1}'} "
