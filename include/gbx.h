@@ -204,8 +204,10 @@ gb_status gb_noise_estimate(const gb_window* windows, int n_win, const double* d
  *   donors a, b, c: distinct and different from i, uniform; from u_idx[w][i][0..2] in [0, 1):
  *     a = floor(u0 (pop-1)), then b = floor(u1 (pop-2)), c = floor(u2 (pop-3)), each stepped
  *     past the indices already taken, in increasing order;
- *   mutant m = x_a + F[w] (x_b - x_c), each product and sum rounded separately; lambda, psi and
- *     phi0 wrap into [lo, hi) (exact remainder), the others reflect once at the walls and are
+ *   mutant m = x_a + F[w] (x_b - x_c) (DE/rand/1; base NULL), or m = x_base[w] + F[w] (x_a - x_b)
+ *     (DE/best/1, the window's best member as the base: base is a device int32 [n_win], for
+ *     instance gb_de_select's best_idx), each product and sum rounded separately; lambda, psi
+ *     and phi0 wrap into [lo, hi) (exact remainder), the others reflect at the walls and are
  *     clipped to [lo, hi];
  *   trial coordinate k = m_k where u_cross[w][i][k] < cr or k = floor(u_j[w][i] 7), else x_i,k.
  * lo, hi: device [n_win][7] (the window's box); x: device [n_win][pop][7], the population;
@@ -214,16 +216,17 @@ gb_status gb_noise_estimate(const gb_window* windows, int n_win, const double* d
  * parameters of each trial with amplitude `amp`, ready for gb_loglik).  Asynchronous;
  * allocates nothing.  GB_EINVAL on pop < 4, cr outside [0, 1] or null arrays. */
 gb_status gb_de_trial(int n_win, int pop, const double* lo, const double* hi, const double* x, const double* u_idx,
-                      const double* u_cross, const double* u_j, const double* F, double cr, double amp,
-                      double* trial_x, double* trial_theta, void* stream);
+                      const double* u_cross, const double* u_j, const double* F, const int32_t* base, double cr,
+                      double amp, double* trial_x, double* trial_theta, void* stream);
 
 /* Selection step of the same generation: rho = <d|h>/sqrt(<h|h>) of every trial from its
  * gb_loglik components (comps: device [n_win * pop][2]; a rho that is not a finite number counts
  * as -inf); where rho exceeds s[w][i], the trial replaces member i of x and rho replaces s.
- * best: device [n_win], the largest s of each window afterwards.  x and trial_x may be the same
- * array (scoring an initial population with s = -inf).  Asynchronous; allocates nothing. */
+ * best: device [n_win], the largest s of each window afterwards; best_idx: device int32 [n_win]
+ * or NULL, the smallest member index holding it.  x and trial_x may be the same array (scoring
+ * an initial population with s = -inf).  Asynchronous; allocates nothing. */
 gb_status gb_de_select(int n_win, int pop, const double* comps, double* x, double* s, const double* trial_x,
-                       double* best, void* stream);
+                       double* best, int32_t* best_idx, void* stream);
 
 /* Log density of weighted 2-D Gaussian kernel density estimates (the pairwise KDE proposals
  * of Sec. III G: (A, iota), (lambda, beta), (f, fdot)), summed over n_pairs pairs, for

@@ -1,20 +1,22 @@
 """Plain reference of one differential-evolution generation -- TEST INFRASTRUCTURE ONLY.
 
 The paper's search step (Sec. III, Algorithm 2) maximises the SNR with differential evolution
-(Storn and Price), strategy DE/rand/1/bin.  Written from that definition, with every random
-number given as an input:
+(Storn and Price), strategies DE/rand/1/bin and DE/best/1/bin.  Written from that definition,
+with every random number given as an input:
 
 * donors       -- for member i, three members a, b, c distinct from i and from each other, each
                   uniform over the members still free: a = floor(u0 (pop - 1)), b = floor(u1
                   (pop - 2)), c = floor(u2 (pop - 3)), each then stepped past the indices
                   already taken, in increasing order;
-* trial        -- mutant x_a + F (x_b - x_c) (each product and sum rounded on its own), brought
+* trial        -- mutant x_a + F (x_b - x_c) (DE/rand/1), or x_best + F (x_a - x_b) with the
+                  window's best member as the base (DE/best/1, SciPy's default strategy; each
+                  product and sum rounded on its own), brought
                   back into the window's box (lambda, psi, phi0 wrap around their range, the
                   other coordinates reflect once at a wall and are clipped), then binomial
                   crossover: coordinate k comes from the mutant when u_cross_k < cr or
                   k = floor(u_j 7), else from x_i; and the trial's physical parameters;
 * select       -- greedy replacement by rho = <d|h> / sqrt(<h|h>) (not a finite number:
-                  -inf), and the best rho of each window.
+                  -inf), the best rho of each window and the first member holding it.
 Coordinates: f0, fdot, sin(beta), lambda, cos(iota), psi, phi0 (Table I without the
 amplitude, on which the SNR does not depend).
 Only tests/, the smoke check and the benchmark's CPU-baseline leg may use this module.
@@ -77,13 +79,17 @@ def to_theta(x: np.ndarray, amp: float) -> np.ndarray:
     return th
 
 
-def trial(lo, hi, x, u_idx, u_cross, u_j, F, cr: float, amp: float):
-    """One DE/rand/1/bin trial per member.  Returns (trial_x [n_win, pop, 7],
-    trial_theta [n_win * pop, 8])."""
+def trial(lo, hi, x, u_idx, u_cross, u_j, F, cr: float, amp: float, base=None):
+    """One DE/rand/1/bin trial per member (DE/best/1/bin with base [n_win], the index of each
+    window's best member).  Returns (trial_x [n_win, pop, 7], trial_theta [n_win * pop, 8])."""
     n_win, pop, _ = x.shape
     d = donors(u_idx, pop)
     w = np.arange(n_win)[:, None]
-    xa, xb, xc = x[w, d[..., 0]], x[w, d[..., 1]], x[w, d[..., 2]]
+    if base is None:
+        xa, xb, xc = x[w, d[..., 0]], x[w, d[..., 1]], x[w, d[..., 2]]
+    else:
+        xa = np.broadcast_to(x[np.arange(n_win), np.asarray(base)][:, None, :], x.shape)
+        xb, xc = x[w, d[..., 0]], x[w, d[..., 1]]
     diff = xb - xc
     step = np.asarray(F)[:, None, None] * diff
     m = fold(xa + step, lo, hi)
@@ -99,10 +105,10 @@ def rho_of(comps: np.ndarray) -> np.ndarray:
 
 
 def select(comps, x, s, trial_x):
-    """Greedy selection; returns new (x, s, best [n_win])."""
+    """Greedy selection; returns new (x, s, best [n_win], index of the first best member)."""
     n_win, pop, _ = x.shape
     r = rho_of(np.asarray(comps).reshape(n_win, pop, 2))
     better = r > s
     x2 = np.where(better[..., None], trial_x, x)
     s2 = np.where(better, r, s)
-    return x2, s2, s2.max(axis=1)
+    return x2, s2, s2.max(axis=1), np.argmax(s2, axis=1)

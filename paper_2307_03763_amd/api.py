@@ -87,9 +87,9 @@ def lib():
         L.gb_kde_logpdf.restype = st
         L.gb_noise_estimate.argtypes = [ctypes.POINTER(gb_window), i, _vp, d, _vp, _vp, _vp]
         L.gb_noise_estimate.restype = st
-        L.gb_de_trial.argtypes = [i, i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, d, d, _vp, _vp, _vp]
+        L.gb_de_trial.argtypes = [i, i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, d, d, _vp, _vp, _vp]
         L.gb_de_trial.restype = st
-        L.gb_de_select.argtypes = [i, i, _vp, _vp, _vp, _vp, _vp, _vp]
+        L.gb_de_select.argtypes = [i, i, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
         L.gb_de_select.restype = st
         L.gb_add_templates.argtypes = [_vp, ctypes.POINTER(gb_window), i, _vp, ctypes.POINTER(ctypes.c_int32), i, d,
                                        _vp, _vp, _vp]
@@ -249,10 +249,11 @@ def gb_noise_estimate(table, d: torch.Tensor, T: float, w: Optional[torch.Tensor
 
 def gb_de_trial(lo: torch.Tensor, hi: torch.Tensor, x: torch.Tensor, u_idx: torch.Tensor, u_cross: torch.Tensor,
                 u_j: torch.Tensor, F: torch.Tensor, cr: float, amp: float, trial_x: Optional[torch.Tensor] = None,
-                trial_theta: Optional[torch.Tensor] = None, stream=None):
-    """DE/rand/1/bin trials of every member: x [n_win, pop, 7], lo/hi [n_win, 7], u_idx
-    [n_win, pop, 3], u_cross [n_win, pop, 7], u_j [n_win, pop], F [n_win] -> (trial_x
-    [n_win, pop, 7], trial_theta [n_win * pop, 8])."""
+                trial_theta: Optional[torch.Tensor] = None, base: Optional[torch.Tensor] = None, stream=None):
+    """DE/rand/1/bin trials of every member (DE/best/1/bin with base [n_win] int32, the best
+    member of each window): x [n_win, pop, 7], lo/hi [n_win, 7], u_idx [n_win, pop, 3],
+    u_cross [n_win, pop, 7], u_j [n_win, pop], F [n_win] -> (trial_x [n_win, pop, 7],
+    trial_theta [n_win * pop, 8])."""
     n_win, pop = int(x.shape[0]), int(x.shape[1])
     if (tuple(x.shape) != (n_win, pop, 7) or tuple(lo.shape) != (n_win, 7) or tuple(hi.shape) != (n_win, 7)
             or tuple(u_idx.shape) != (n_win, pop, 3) or tuple(u_cross.shape) != (n_win, pop, 7)
@@ -262,17 +263,22 @@ def gb_de_trial(lo: torch.Tensor, hi: torch.Tensor, x: torch.Tensor, u_idx: torc
         trial_x = torch.empty_like(x)
     if trial_theta is None:
         trial_theta = torch.empty((n_win * pop, 8), dtype=torch.float64, device=x.device)
+    if base is not None and tuple(base.shape) != (n_win,):
+        raise ValueError("gb_de_trial: base must be [n_win]")
     f = lambda t, n: _dev(t, torch.float64, n)
     _check(lib().gb_de_trial(n_win, pop, f(lo, "lo"), f(hi, "hi"), f(x, "x"), f(u_idx, "u_idx"), f(u_cross, "u_cross"),
-                             f(u_j, "u_j"), f(F, "F"), float(cr), float(amp), f(trial_x, "trial_x"),
-                             f(trial_theta, "trial_theta"), _stream(stream)), "gb_de_trial")
+                             f(u_j, "u_j"), f(F, "F"), None if base is None else _dev(base, torch.int32, "base"),
+                             float(cr), float(amp), f(trial_x, "trial_x"), f(trial_theta, "trial_theta"),
+                             _stream(stream)), "gb_de_trial")
     return trial_x, trial_theta
 
 
 def gb_de_select(comps: torch.Tensor, x: torch.Tensor, s: torch.Tensor, trial_x: torch.Tensor,
-                 best: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+                 best: Optional[torch.Tensor] = None, best_idx: Optional[torch.Tensor] = None,
+                 stream=None) -> torch.Tensor:
     """Greedy DE selection in place on x [n_win, pop, 7] and s [n_win, pop] from the trials'
-    components comps [n_win * pop, 2]; returns best [n_win] (largest rho per window)."""
+    components comps [n_win * pop, 2]; returns best [n_win] (largest rho per window) and, if
+    best_idx [n_win] int32 is given, writes the smallest index holding it there."""
     n_win, pop = int(x.shape[0]), int(x.shape[1])
     if (tuple(comps.shape) != (n_win * pop, 2) or tuple(s.shape) != (n_win, pop) or tuple(trial_x.shape) != (n_win, pop, 7)
             or tuple(x.shape) != (n_win, pop, 7)):
@@ -280,8 +286,11 @@ def gb_de_select(comps: torch.Tensor, x: torch.Tensor, s: torch.Tensor, trial_x:
     if best is None:
         best = torch.empty(n_win, dtype=torch.float64, device=x.device)
     f = lambda t, n: _dev(t, torch.float64, n)
+    if best_idx is not None and tuple(best_idx.shape) != (n_win,):
+        raise ValueError("gb_de_select: best_idx must be [n_win]")
     _check(lib().gb_de_select(n_win, pop, f(comps, "comps"), f(x, "x"), f(s, "s"), f(trial_x, "trial_x"),
-                              f(best, "best"), _stream(stream)), "gb_de_select")
+                              f(best, "best"), None if best_idx is None else _dev(best_idx, torch.int32, "best_idx"),
+                              _stream(stream)), "gb_de_select")
     return best
 
 

@@ -689,7 +689,8 @@ extern "C" gb_status gb_noise_estimate(const gb_window* windows, int n_win, cons
 
 extern "C" gb_status gb_de_trial(int n_win, int pop, const double* lo, const double* hi, const double* x,
                                  const double* u_idx, const double* u_cross, const double* u_j, const double* F,
-                                 double cr, double amp, double* trial_x, double* trial_theta, void* stream) {
+                                 const int32_t* base, double cr, double amp, double* trial_x, double* trial_theta,
+                                 void* stream) {
   if (n_win < 0 || pop < 4 || !(cr >= 0.0 && cr <= 1.0)) return fail(GB_EINVAL, "gb_de_trial: bad sizes or rate");
   if (n_win == 0) return GB_OK;
   if (!lo || !hi || !x || !u_idx || !u_cross || !u_j || !F || !trial_x || !trial_theta)
@@ -697,18 +698,18 @@ extern "C" gb_status gb_de_trial(int n_win, int pop, const double* lo, const dou
   const int64_t n = (int64_t)n_win * pop;
   if ((n + 255) / 256 > 0x7fffffff) return fail(GB_EINVAL, "gb_de_trial: population too large");
   hipLaunchKernelGGL(k_de_trial, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, n_win, pop, lo,
-                     hi, x, u_idx, u_cross, u_j, F, cr, amp, trial_x, trial_theta);
+                     hi, x, u_idx, u_cross, u_j, F, base, cr, amp, trial_x, trial_theta);
   HIPCHK(hipGetLastError());
   return GB_OK;
 }
 
 extern "C" gb_status gb_de_select(int n_win, int pop, const double* comps, double* x, double* s,
-                                  const double* trial_x, double* best, void* stream) {
+                                  const double* trial_x, double* best, int32_t* best_idx, void* stream) {
   if (n_win < 0 || pop < 1) return fail(GB_EINVAL, "gb_de_select: bad sizes");
   if (n_win == 0) return GB_OK;
   if (!comps || !x || !s || !trial_x || !best) return fail(GB_EINVAL, "gb_de_select: null array");
   hipLaunchKernelGGL(k_de_select, dim3((unsigned)n_win), dim3(256), 0, (hipStream_t)stream, pop, comps, x, s, trial_x,
-                     best);
+                     best, best_idx);
   HIPCHK(hipGetLastError());
   return GB_OK;
 }

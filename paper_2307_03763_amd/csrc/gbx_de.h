@@ -22,16 +22,18 @@ __device__ __forceinline__ int de_pick(double u, int n) {
 
 // One trial per (window, member) thread.  Donors a, b, c: uniform over the population without
 // the member and each other, from three uniforms (each draw counts the free slots and skips the
-// taken indices in increasing order).  Mutant a + F (b - c), folded back into the box (periodic
-// coordinates wrap, the others reflect at the walls and are clipped); binomial crossover with
-// rate cr, the coordinate floor(u_j 7) always from the mutant.  The arithmetic is not contracted
-// into fused multiply-adds, so that it rounds as the plain reference does.
+// taken indices in increasing order).  Mutant a + F (b - c) (DE/rand/1), or, with base given,
+// x_base[w] + F (a - b) (DE/best/1: the window's best member plus a difference of two donors),
+// folded back into the box (periodic coordinates wrap, the others reflect at the walls and are
+// clipped); binomial crossover with rate cr, the coordinate floor(u_j 7) always from the mutant.
+// The arithmetic is not contracted into fused multiply-adds, so that it rounds as the plain
+// reference does.
 __global__ void __launch_bounds__(256) k_de_trial(int n_win, int pop, const double* __restrict__ lo,
                                                   const double* __restrict__ hi, const double* __restrict__ x,
                                                   const double* __restrict__ u_idx, const double* __restrict__ u_cross,
                                                   const double* __restrict__ u_j, const double* __restrict__ F,
-                                                  double cr, double amp, double* __restrict__ trial_x,
-                                                  double* __restrict__ trial_theta) {
+                                                  const int32_t* __restrict__ base, double cr, double amp,
+                                                  double* __restrict__ trial_x, double* __restrict__ trial_theta) {
 #pragma clang fp contract(off)
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= (int64_t)n_win * pop) return;
@@ -56,9 +58,11 @@ __global__ void __launch_bounds__(256) k_de_trial(int n_win, int pop, const doub
   }
   const int jr = de_pick(u_j[g], kDeDim);
   const double f = F[w];
-  const double* xa = x + ((int64_t)w * pop + a) * kDeDim;
-  const double* xb = x + ((int64_t)w * pop + b) * kDeDim;
-  const double* xc = x + ((int64_t)w * pop + c) * kDeDim;
+  // DE/best/1: base member plus the difference of the first two donors
+  const int m0 = base ? base[w] : a, m1 = base ? a : b, m2 = base ? b : c;
+  const double* xa = x + ((int64_t)w * pop + m0) * kDeDim;
+  const double* xb = x + ((int64_t)w * pop + m1) * kDeDim;
+  const double* xc = x + ((int64_t)w * pop + m2) * kDeDim;
   const double* xi = x + g * kDeDim;
   double v[kDeDim];
 #pragma unroll
@@ -98,14 +102,18 @@ __global__ void __launch_bounds__(256) k_de_trial(int n_win, int pop, const doub
 
 // Greedy selection, one workgroup per window: rho = <d|h> / sqrt(<h|h>) of every trial (not a
 // finite number: -inf); a trial replaces its member when its rho is larger.  best[w] = the
-// largest rho of the window's population afterwards.  x and trial_x may be the same array
-// (a first scoring of the initial population with s = -inf).
+// largest rho of the window's population afterwards, best_idx[w] (if given) the smallest index
+// holding it.  x and trial_x may be the same array (a first scoring of the initial population
+// with s = -inf).
 __global__ void __launch_bounds__(256) k_de_select(int pop, const double* __restrict__ comps, double* x, double* s,
-                                                   const double* trial_x, double* __restrict__ best) {
+                                                   const double* trial_x, double* __restrict__ best,
+                                                   int32_t* __restrict__ best_idx) {
   __shared__ double s_red[4];
+  __shared__ int s_idx[4];
   const int w = blockIdx.x;
   const int tid = threadIdx.x;
   double mx = -__builtin_inf();
+  int mi = 0x7fffffff;
   for (int i = tid; i < pop; i += blockDim.x) {
     const int64_t g = (int64_t)w * pop + i;
     const double r = comps[2 * g] / sqrt(comps[2 * g + 1]);
@@ -117,12 +125,36 @@ __global__ void __launch_bounds__(256) k_de_select(int pop, const double* __rest
 #pragma unroll
       for (int k = 0; k < kDeDim; ++k) x[kDeDim * g + k] = trial_x[kDeDim * g + k];
     }
-    mx = fmax(mx, si);
+    if (si > mx || (si == mx && i < mi)) {
+      mx = si;
+      mi = i;
+    }
   }
-  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
-  if ((tid & 63) == 0) s_red[tid >> 6] = mx;
+  // (value, index) maximum: larger value first, then the smaller index
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ov = __shfl_xor(mx, o, 64);
+    const int oi = __shfl_xor(mi, o, 64);
+    if (ov > mx || (ov == mx && oi < mi)) {
+      mx = ov;
+      mi = oi;
+    }
+  }
+  if ((tid & 63) == 0) {
+    s_red[tid >> 6] = mx;
+    s_idx[tid >> 6] = mi;
+  }
   __syncthreads();
-  if (tid == 0) best[w] = fmax(fmax(s_red[0], s_red[1]), fmax(s_red[2], s_red[3]));
+  if (tid == 0) {
+    double v = s_red[0];
+    int k = s_idx[0];
+    for (int q = 1; q < 4; ++q)
+      if (s_red[q] > v || (s_red[q] == v && s_idx[q] < k)) {
+        v = s_red[q];
+        k = s_idx[q];
+      }
+    best[w] = v;
+    if (best_idx) best_idx[w] = k < pop ? k : 0;
+  }
 }
 
 }  // namespace gbx

@@ -142,24 +142,28 @@ def _to_theta(x: np.ndarray) -> np.ndarray:
 
 def de_search(backend, boxes, rng: np.random.Generator, pop: int = 512, generations: int = 50,
               cr: float = 0.7, f_lo: float = 0.5, f_hi: float = 1.0, init: Optional[np.ndarray] = None,
-              keep: int = 1, on_device: Optional[bool] = None):
+              keep: int = 1, on_device: Optional[bool] = None, strategy: str = "rand1"):
     """Maximise rho over the seven non-amplitude parameters inside each window's Table I box.
 
     ``boxes`` is one PriorBox per window of the backend (or a single one for one window);
     ``init`` optionally seeds member 0 of each population ([n_win, 8] or [8]).  With a backend
     that offers it (``device_de``) the generations run on the device (``on_device`` False keeps
-    them on the host: the same DE with NumPy's random streams).  Returns
+    them on the host: the same DE with NumPy's random streams).  ``strategy``: "rand1"
+    (DE/rand/1/bin) or "best1" (DE/best/1/bin, SciPy's default: mutants around each window's
+    best member).  Returns
     (theta [n_win, keep, 8] of the best ``keep`` members with A = A_max, rho [n_win, keep],
     history [generations + 1, n_win] of the best rho per generation)."""
     lo, hi = _box_arrays(boxes)
     lo, hi = lo[:, list(SEARCH_DIMS)], hi[:, list(SEARCH_DIMS)]
     n_win, dim = lo.shape
     if pop < 4 or not 1 <= keep <= pop:
-        raise ValueError("DE/rand/1 needs pop >= 4 and 1 <= keep <= pop")
+        raise ValueError("DE needs pop >= 4 and 1 <= keep <= pop")
+    if strategy not in ("rand1", "best1"):
+        raise ValueError("strategy must be 'rand1' or 'best1'")
     if on_device is None:
         on_device = getattr(backend, "device_de", False)
     if on_device:
-        x, s, history = _de_device(backend, lo, hi, rng, pop, generations, cr, f_lo, f_hi, init)
+        x, s, history = _de_device(backend, lo, hi, rng, pop, generations, cr, f_lo, f_hi, init, strategy == "best1")
         return _de_finish(backend, x, s, history, keep)
     x = lo[:, None, :] + (hi - lo)[:, None, :] * rng.random((n_win, pop, dim))
     if init is not None:
@@ -175,7 +179,11 @@ def de_search(backend, boxes, rng: np.random.Generator, pop: int = 512, generati
     for _ in range(generations):
         r = _three_others(rng, n_win, pop)
         fscale = rng.uniform(f_lo, f_hi)
-        mutant = x[wi, r[..., 0]] + fscale * (x[wi, r[..., 1]] - x[wi, r[..., 2]])
+        if strategy == "best1":
+            base = x[np.arange(n_win), np.argmax(s, axis=1)][:, None, :]
+            mutant = base + fscale * (x[wi, r[..., 0]] - x[wi, r[..., 1]])
+        else:
+            mutant = x[wi, r[..., 0]] + fscale * (x[wi, r[..., 1]] - x[wi, r[..., 2]])
         mutant = _fold_into_box(mutant, lo, hi)
         cross = rng.random((n_win, pop, dim)) < cr
         cross[wi, np.arange(pop)[None, :], rng.integers(0, dim, (n_win, pop))] = True
@@ -188,7 +196,7 @@ def de_search(backend, boxes, rng: np.random.Generator, pop: int = 512, generati
     return _de_finish(backend, x, s, np.array(history), keep)
 
 
-def _de_device(backend, lo, hi, rng, pop, generations, cr, f_lo, f_hi, init):
+def _de_device(backend, lo, hi, rng, pop, generations, cr, f_lo, f_hi, init, best1=False):
     """The DE generations with the population, scores and random draws in device memory: per
     generation one gb_de_trial, one gb_loglik of all trials and one gb_de_select, with no copy
     to the host (the uniforms come from a torch generator seeded by ``rng``; F is drawn from
@@ -211,7 +219,8 @@ def _de_device(backend, lo, hi, rng, pop, generations, cr, f_lo, f_hi, init):
     plan = backend._plan(pop, backend.pl)
     th0 = torch.as_tensor(np.ascontiguousarray(_to_theta(x.cpu().numpy()).reshape(n_win * pop, 8)), device=dev)
     _, comps = plan.loglik(th0, comps=True)
-    hist = [api.gb_de_select(comps, x, s, x.clone())]
+    best_idx = torch.zeros(n_win, dtype=torch.int32, device=dev)
+    hist = [api.gb_de_select(comps, x, s, x.clone(), best_idx=best_idx)]
     trial_x = torch.empty_like(x)
     trial_th = torch.empty((n_win * pop, 8), dtype=f64, device=dev)
     F = torch.empty(n_win, dtype=f64, device=dev)
@@ -220,9 +229,10 @@ def _de_device(backend, lo, hi, rng, pop, generations, cr, f_lo, f_hi, init):
         u_cross = torch.rand((n_win, pop, dim), generator=gen, dtype=f64, device=dev)
         u_j = torch.rand((n_win, pop), generator=gen, dtype=f64, device=dev)
         F.fill_(float(rng.uniform(f_lo, f_hi)))
-        api.gb_de_trial(lo_t, hi_t, x, u_idx, u_cross, u_j, F, cr, REF_AMP, trial_x, trial_th)
+        api.gb_de_trial(lo_t, hi_t, x, u_idx, u_cross, u_j, F, cr, REF_AMP, trial_x, trial_th,
+                        base=best_idx if best1 else None)
         _, comps = plan.loglik(trial_th, comps=True)
-        hist.append(api.gb_de_select(comps, x, s, trial_x))
+        hist.append(api.gb_de_select(comps, x, s, trial_x, best_idx=best_idx))
     return x.cpu().numpy(), s.cpu().numpy(), torch.stack(hist).cpu().numpy()
 
 
@@ -327,7 +337,8 @@ def polish(backend, theta0: np.ndarray, scale: np.ndarray, iterations: int = 20,
 
 
 def search(backend, boxes, rng: np.random.Generator, pop: int = 512, generations: int = 50,
-           keep: int = 8, polish_iterations: int = 20, scale_frac: float = 1e-3, n_searches: int = 1):
+           keep: int = 8, polish_iterations: int = 20, scale_frac: float = 1e-3, n_searches: int = 1,
+           strategy: str = "rand1"):
     """Maximum-likelihood search of Sec. III D for every window of the backend: DE over the box,
     then the BFGS polish of the ``keep`` best members (scale: ``scale_frac`` of the box widths),
     repeated ``n_searches`` times from fresh populations in case a search ends at a local
@@ -338,7 +349,7 @@ def search(backend, boxes, rng: np.random.Generator, pop: int = 512, generations
     best_l = np.full(n_win, -np.inf)
     scale = (scale_frac * (hi - lo))[:, None, :]
     for _ in range(n_searches):
-        th, _, _ = de_search(backend, boxes, rng, pop=pop, generations=generations, keep=keep)
+        th, _, _ = de_search(backend, boxes, rng, pop=pop, generations=generations, keep=keep, strategy=strategy)
         th, hist = polish(backend, th, scale, iterations=polish_iterations)
         l_end = hist[-1]                                       # [n_win, keep]
         j = np.argmax(l_end, axis=1)
@@ -561,7 +572,8 @@ def _rho_of(comps):
 
 def local_search(backend, seg_edges, rng: np.random.Generator, n_signals: int, rho_threshold: float = 9.0,
                  n_searches: int = 3, pop: int = 512, generations: int = 50, keep: int = 8,
-                 polish_iterations: int = 20, scale_frac: float = 1e-3, joint_sweeps: int = 2, progress=None):
+                 polish_iterations: int = 20, scale_frac: float = 1e-3, joint_sweeps: int = 2, progress=None,
+                 strategy: str = "rand1"):
     """Algorithm 2 for every window of the backend at once (each window = one padded segment;
     seg_edges [n_win, 2] = the unpadded segment's edges in Hz).  Per signal: n_searches DE +
     polish searches on the residual (the first one ends the window when rho on the analysed data
@@ -591,7 +603,7 @@ def local_search(backend, seg_edges, rng: np.random.Generator, n_signals: int, r
         best_rho_an = np.full(n_win, -np.inf)
         for j in range(n_searches):
             th, _ = search(backend, boxes, rng, pop=pop, generations=generations, keep=keep,
-                           polish_iterations=polish_iterations, scale_frac=scale_frac)
+                           polish_iterations=polish_iterations, scale_frac=scale_frac, strategy=strategy)
             rho_res = _rho_of(backend.loglik(th)[1])
             rho_an = backend.rho_analyze(th)
             if j == 0:

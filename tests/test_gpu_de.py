@@ -26,10 +26,11 @@ def _boxes(rng, n_win):
     return lo, hi
 
 
-@pytest.mark.parametrize("n_win,pop", [(3, 4), (5, 37), (64, 512)])
-def test_de_step_matches_oracle(n_win, pop):
+@pytest.mark.parametrize("n_win,pop,best1", [(3, 4, False), (5, 37, False), (64, 512, False), (3, 4, True),
+                                             (64, 512, True)])
+def test_de_step_matches_oracle(n_win, pop, best1):
     from oracle import de
-    banner(f"gb_de_trial / gb_de_select: {n_win} windows x {pop} members")
+    banner(f"gb_de_trial / gb_de_select: {n_win} windows x {pop} members, {'best' if best1 else 'rand'}/1")
     rng = np.random.default_rng(n_win * 1000 + pop)
     lo, hi = _boxes(rng, n_win)
     x = lo[:, None, :] + (hi - lo)[:, None, :] * rng.random((n_win, pop, 7))
@@ -40,8 +41,10 @@ def test_de_step_matches_oracle(n_win, pop):
     u_idx[:, 1, :] = np.nextafter(1.0, 0.0)
     u_cross, u_j = rng.random((n_win, pop, 7)), rng.random((n_win, pop))
     F = rng.uniform(0.5, 2.5, n_win)                 # large steps: many mutants outside the box
-    tx, th = api.gb_de_trial(dev(lo), dev(hi), dev(x), dev(u_idx), dev(u_cross), dev(u_j), dev(F), 0.7, 1e-22)
-    rx, rth = de.trial(lo, hi, x, u_idx, u_cross, u_j, F, 0.7, 1e-22)
+    base = rng.integers(0, pop, n_win).astype(np.int32) if best1 else None
+    tx, th = api.gb_de_trial(dev(lo), dev(hi), dev(x), dev(u_idx), dev(u_cross), dev(u_j), dev(F), 0.7, 1e-22,
+                             base=None if base is None else torch.as_tensor(base, device="cuda"))
+    rx, rth = de.trial(lo, hi, x, u_idx, u_cross, u_j, F, 0.7, 1e-22, base=base)
     tx, th = tx.cpu().numpy(), th.cpu().numpy()
     assert np.array_equal(tx, rx)
     plain = [0, 1, 3, 4, 6, 7]
@@ -58,16 +61,18 @@ def test_de_step_matches_oracle(n_win, pop):
     comps[::13, 1] = -1.0
     s = rng.normal(size=(n_win, pop))
     s[:, ::5] = -np.inf
+    s[0, :] = 5.0                                    # a window of ties
     xg, sg = dev(x), dev(s)
-    best = api.gb_de_select(dev(comps), xg, sg, dev(tx)).cpu().numpy()
-    rx2, rs2, rbest = de.select(comps, x, s, tx)
+    bi = torch.empty(n_win, dtype=torch.int32, device="cuda")
+    best = api.gb_de_select(dev(comps), xg, sg, dev(tx), best_idx=bi).cpu().numpy()
+    rx2, rs2, rbest, rbi = de.select(comps, x, s, tx)
     assert np.array_equal(xg.cpu().numpy(), rx2) and np.array_equal(sg.cpu().numpy(), rs2)
-    assert np.array_equal(best, rbest)
+    assert np.array_equal(best, rbest) and np.array_equal(bi.cpu().numpy(), rbi)
 
 
 def test_de_generations_on_likelihood(oracle_lib):
     from oracle import de
-    banner("ten DE generations on the likelihood of four ragged windows, GPU vs oracle step")
+    banner("ten DE generations (rand/1 and best/1 in turn) on four ragged windows, GPU vs oracle step")
     wl = I.workload_c3(oracle_lib.template_fn(), n_win=4, n_cand=1)
     ctx = api.context_for(wl.T)
     pop = 96
@@ -81,19 +86,22 @@ def test_de_generations_on_likelihood(oracle_lib):
     s = np.full((wl.n_win, pop), -np.inf)
     _, c = plan.loglik(dev(de.to_theta(x, D.REF_AMP).reshape(-1, 8)), comps=True)
     xg, sg = dev(x), dev(s)
-    api.gb_de_select(c, xg, sg, xg.clone())
-    x, s, _ = de.select(c.cpu().numpy(), x, s, x)
-    for _ in range(10):
+    bi = torch.empty(wl.n_win, dtype=torch.int32, device="cuda")
+    api.gb_de_select(c, xg, sg, xg.clone(), best_idx=bi)
+    x, s, _, rbi = de.select(c.cpu().numpy(), x, s, x)
+    for g in range(10):
         u_idx, u_cross, u_j = rng.random((wl.n_win, pop, 3)), rng.random((wl.n_win, pop, 7)), rng.random((wl.n_win, pop))
         F = np.full(wl.n_win, rng.uniform(0.5, 1.0))
-        tx, th = api.gb_de_trial(dev(lo), dev(hi), xg, dev(u_idx), dev(u_cross), dev(u_j), dev(F), 0.7, D.REF_AMP)
+        use_best = g % 2 == 1                        # alternate the two strategies
+        tx, th = api.gb_de_trial(dev(lo), dev(hi), xg, dev(u_idx), dev(u_cross), dev(u_j), dev(F), 0.7, D.REF_AMP,
+                                 base=bi if use_best else None)
         _, c = plan.loglik(th, comps=True)
-        best = api.gb_de_select(c, xg, sg, tx)
-        rtx, _ = de.trial(lo, hi, x, u_idx, u_cross, u_j, F, 0.7, D.REF_AMP)
+        best = api.gb_de_select(c, xg, sg, tx, best_idx=bi)
+        rtx, _ = de.trial(lo, hi, x, u_idx, u_cross, u_j, F, 0.7, D.REF_AMP, base=rbi if use_best else None)
         assert np.array_equal(tx.cpu().numpy(), rtx)
-        x, s, rbest = de.select(c.cpu().numpy(), x, s, rtx)
+        x, s, rbest, rbi = de.select(c.cpu().numpy(), x, s, rtx)
         assert np.array_equal(xg.cpu().numpy(), x) and np.array_equal(sg.cpu().numpy(), s)
-        assert np.array_equal(best.cpu().numpy(), rbest)
+        assert np.array_equal(best.cpu().numpy(), rbest) and np.array_equal(bi.cpu().numpy(), rbi)
     be.close()
 
 

@@ -7,9 +7,10 @@
 * Folding: reflection at either wall, wrapping of periodic coordinates, points inside kept.
 * Crossover: with cr = 0 exactly the forced coordinate comes from the mutant; with cr = 1 all;
   F = 0 makes the mutant the first donor.
-* Selection: strictly larger rho replaces; NaN never does; best is the maximum.
+* Selection: strictly larger rho replaces; NaN never does; best is the maximum, held first by
+  the reported member.
 * The whole step maximises a known function: rho = -|x - x*|^2 (fed in as comps = (rho, 1))
-  reaches x* from a uniform start.
+  reaches x* from a uniform start, with DE/rand/1 and with DE/best/1.
 """
 
 import numpy as np
@@ -110,10 +111,14 @@ def test_select():
     tx = np.ones((1, 4, 7))
     s = np.array([[1.0, 1.0, 1.0, -np.inf]])
     comps = np.array([[2.0, 1.0], [1.0, 1.0], [np.nan, 1.0], [1.0, 0.0]])   # rho 2, 1 (tie), NaN, inf
-    x2, s2, best = de.select(comps, x, s, tx)
+    x2, s2, best, bi = de.select(comps, x, s, tx)
     assert np.array_equal(s2, np.array([[2.0, 1.0, 1.0, -np.inf]]))
     assert np.all(x2[0, 0] == 1.0) and np.all(x2[0, 1:] == 0.0)
-    assert best[0] == 2.0
+    assert best[0] == 2.0 and bi[0] == 0
+    # ties: the first member holding the best value
+    _, _, _, bi = de.select(np.array([[0.0, 1.0]] * 4), np.zeros((1, 4, 7)), np.array([[1.0, 3.0, 3.0, 0.0]]),
+                            np.ones((1, 4, 7)))
+    assert bi[0] == 1
 
 
 def test_de_maximises_known_function():
@@ -130,11 +135,15 @@ def test_de_maximises_known_function():
         r = -np.sum((xx - target[:, None, :]) ** 2, axis=-1)
         return np.stack([r.ravel(), np.ones(r.size)], axis=1)
 
-    s = np.full((n_win, pop), -np.inf)
-    x, s, best = de.select(comps_of(x), x, s, x)
-    for _ in range(300):
-        tx, _ = de.trial(lo, hi, x, rng.random((n_win, pop, 3)), rng.random((n_win, pop, 7)), rng.random((n_win, pop)),
-                         np.full(n_win, rng.uniform(0.5, 1.0)), 0.7, 1e-22)
-        x, s, best = de.select(comps_of(tx), x, s, tx)
-    top = x[np.arange(n_win), np.argmax(s, axis=1)]
-    assert np.max(np.abs(top - target)) < 1e-3 and np.all(best > -1e-6)
+    x0 = x
+    for strategy in ("rand1", "best1"):
+        x = x0.copy()
+        s = np.full((n_win, pop), -np.inf)
+        x, s, best, bi = de.select(comps_of(x), x, s, x)
+        for _ in range(300):
+            tx, _ = de.trial(lo, hi, x, rng.random((n_win, pop, 3)), rng.random((n_win, pop, 7)),
+                             rng.random((n_win, pop)), np.full(n_win, rng.uniform(0.5, 1.0)), 0.7, 1e-22,
+                             base=bi if strategy == "best1" else None)
+            x, s, best, bi = de.select(comps_of(tx), x, s, tx)
+        top = x[np.arange(n_win), bi]
+        assert np.max(np.abs(top - target)) < 1e-3 and np.all(best > -1e-6), strategy
