@@ -142,7 +142,7 @@ def _to_theta(x: np.ndarray) -> np.ndarray:
 
 def de_search(backend, boxes, rng: np.random.Generator, pop: int = 512, generations: int = 50,
               cr: float = 0.7, f_lo: float = 0.5, f_hi: float = 1.0, init: Optional[np.ndarray] = None,
-              keep: int = 1, on_device: Optional[bool] = None, strategy: str = "rand1"):
+              keep: int = 1, on_device: Optional[bool] = None, strategy: str = "best1"):
     """Maximise rho over the seven non-amplitude parameters inside each window's Table I box.
 
     ``boxes`` is one PriorBox per window of the backend (or a single one for one window);
@@ -338,7 +338,7 @@ def polish(backend, theta0: np.ndarray, scale: np.ndarray, iterations: int = 20,
 
 def search(backend, boxes, rng: np.random.Generator, pop: int = 512, generations: int = 50,
            keep: int = 8, polish_iterations: int = 20, scale_frac: float = 1e-3, n_searches: int = 1,
-           strategy: str = "rand1"):
+           strategy: str = "best1"):
     """Maximum-likelihood search of Sec. III D for every window of the backend: DE over the box,
     then the BFGS polish of the ``keep`` best members (scale: ``scale_frac`` of the box widths),
     repeated ``n_searches`` times from fresh populations in case a search ends at a local
@@ -573,7 +573,7 @@ def _rho_of(comps):
 def local_search(backend, seg_edges, rng: np.random.Generator, n_signals: int, rho_threshold: float = 9.0,
                  n_searches: int = 3, pop: int = 512, generations: int = 50, keep: int = 8,
                  polish_iterations: int = 20, scale_frac: float = 1e-3, joint_sweeps: int = 2, progress=None,
-                 strategy: str = "rand1"):
+                 strategy: str = "best1"):
     """Algorithm 2 for every window of the backend at once (each window = one padded segment;
     seg_edges [n_win, 2] = the unpadded segment's edges in Hz).  Per signal: n_searches DE +
     polish searches on the residual (the first one ends the window when rho on the analysed data
