@@ -1013,10 +1013,11 @@ def match_delta(ctx, table, T: float, w, recovered, rec_rows, injected, n_near: 
     l, c = plan.loglik(torch.as_tensor(rec[[k for k, _ in pairs]], device=dev), comps=True)
     plan.close()
     l, c = l.cpu().numpy(), c.cpu().numpy()
-    delta = (-2.0 * l) / c[:, 1]
-    # <s_inj|s_inj> = -2 logL + 2 <s_inj|s_rec> - <s_rec|s_rec>
+    # <s_inj|s_inj> = -2 logL + 2 <s_inj|s_rec> - <s_rec|s_rec>; a recovered template with no
+    # power in its window gives no match (delta not a number)
     ii = -2.0 * l + 2.0 * c[:, 0] - c[:, 1]
     with np.errstate(invalid="ignore", divide="ignore"):
+        delta = (-2.0 * l) / c[:, 1]
         ov = c[:, 0] / np.sqrt(c[:, 1] * ii)
     best = np.full(len(rec), np.inf)
     which = np.full(len(rec), -1, dtype=np.int64)
