@@ -196,8 +196,8 @@ gb_status gb_add_templates(gb_ctx* ctx, const gb_window* windows, int n_win, con
 gb_status gb_noise_estimate(const gb_window* windows, int n_win, const double* d, double T, double* w, double* S,
                             void* stream);
 
-/* One generation of the differential-evolution search (DE/rand/1/bin of Storn and Price, the
- * optimiser the paper's search uses, Sec. III), trial step, for n_win windows with pop members
+/* One generation of the differential-evolution search (DE/best/1/bin or DE/rand/1/bin of Storn
+ * and Price, the optimiser the paper's search uses, Sec. III), trial step, for n_win windows with pop members
  * each (pop >= 4), over the seven searched Table I coordinates in the order f0, fdot, sin(beta),
  * lambda, cos(iota), psi, phi0 (the amplitude is not searched: the SNR does not depend on it).
  * For member i of window w:
@@ -206,7 +206,8 @@ gb_status gb_noise_estimate(const gb_window* windows, int n_win, const double* d
  *     past the indices already taken, in increasing order;
  *   mutant m = x_a + F[w] (x_b - x_c) (DE/rand/1; base NULL), or m = x_base[w] + F[w] (x_a - x_b)
  *     (DE/best/1, the window's best member as the base: base is a device int32 [n_win], for
- *     instance gb_de_select's best_idx), each product and sum rounded separately; lambda, psi
+ *     instance gb_de_select's best_idx; an index outside [0, pop) is clamped into it), each
+ *     product and sum rounded separately; lambda, psi
  *     and phi0 wrap into [lo, hi) (exact remainder), the others reflect at the walls and are
  *     clipped to [lo, hi];
  *   trial coordinate k = m_k where u_cross[w][i][k] < cr or k = floor(u_j[w][i] 7), else x_i,k.

@@ -59,7 +59,7 @@ __global__ void __launch_bounds__(256) k_de_trial(int n_win, int pop, const doub
   const int jr = de_pick(u_j[g], kDeDim);
   const double f = F[w];
   // DE/best/1: base member plus the difference of the first two donors
-  const int m0 = base ? base[w] : a, m1 = base ? a : b, m2 = base ? b : c;
+  const int m0 = base ? min(max(base[w], 0), pop - 1) : a, m1 = base ? a : b, m2 = base ? b : c;
   const double* xa = x + ((int64_t)w * pop + m0) * kDeDim;
   const double* xb = x + ((int64_t)w * pop + m1) * kDeDim;
   const double* xc = x + ((int64_t)w * pop + m2) * kDeDim;
