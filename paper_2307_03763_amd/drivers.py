@@ -70,6 +70,16 @@ class GpuBackend:
             self.plans[key] = p
         return self.plans[key]
 
+    def _sub_plan(self, rows, n: int, prec: int):
+        """A plan over the windows ``rows`` only, n candidates each (not cached: the caller
+        closes it)."""
+        t = self.table[np.asarray(rows)].copy()
+        t[:, 6] = np.arange(len(t)) * n
+        t[:, 7] = n
+        p = self.api.Plan(self.ctx, t, prec)
+        p.prepare(self.d, self.w)
+        return p
+
     def _n(self, theta) -> int:
         if len(theta) % self.n_win:
             raise ValueError("theta rows must be a multiple of the window count")
@@ -142,7 +152,8 @@ def _to_theta(x: np.ndarray) -> np.ndarray:
 
 def de_search(backend, boxes, rng: np.random.Generator, pop: int = 512, generations: int = 50,
               cr: float = 0.7, f_lo: float = 0.5, f_hi: float = 1.0, init: Optional[np.ndarray] = None,
-              keep: int = 1, on_device: Optional[bool] = None, strategy: str = "best1"):
+              keep: int = 1, on_device: Optional[bool] = None, strategy: str = "best1", tol: float = 0.0,
+              check_every: int = 50):
     """Maximise rho over the seven non-amplitude parameters inside each window's Table I box.
 
     ``boxes`` is one PriorBox per window of the backend (or a single one for one window);
@@ -150,7 +161,10 @@ def de_search(backend, boxes, rng: np.random.Generator, pop: int = 512, generati
     that offers it (``device_de``) the generations run on the device (``on_device`` False keeps
     them on the host: the same DE with NumPy's random streams).  ``strategy``: "rand1"
     (DE/rand/1/bin) or "best1" (DE/best/1/bin, SciPy's default: mutants around each window's
-    best member).  Returns
+    best member).  ``tol`` > 0 stops a window once its population has converged in SciPy's
+    sense, std(rho) <= tol |mean(rho)| (SciPy's default tol is 0.01), checked every
+    ``check_every`` generations; a stopped window keeps its population (on the device it also
+    leaves the batch).  Returns
     (theta [n_win, keep, 8] of the best ``keep`` members with A = A_max, rho [n_win, keep],
     history [generations + 1, n_win] of the best rho per generation)."""
     lo, hi = _box_arrays(boxes)
@@ -163,7 +177,8 @@ def de_search(backend, boxes, rng: np.random.Generator, pop: int = 512, generati
     if on_device is None:
         on_device = getattr(backend, "device_de", False)
     if on_device:
-        x, s, history = _de_device(backend, lo, hi, rng, pop, generations, cr, f_lo, f_hi, init, strategy == "best1")
+        x, s, history = _de_device(backend, lo, hi, rng, pop, generations, cr, f_lo, f_hi, init, strategy == "best1",
+                                   tol, check_every)
         return _de_finish(backend, x, s, history, keep)
     x = lo[:, None, :] + (hi - lo)[:, None, :] * rng.random((n_win, pop, dim))
     if init is not None:
@@ -176,7 +191,8 @@ def de_search(backend, boxes, rng: np.random.Generator, pop: int = 512, generati
     s = score(x)
     history = [s.max(axis=1)]
     wi = np.arange(n_win)[:, None]
-    for _ in range(generations):
+    stopped = np.zeros(n_win, dtype=bool)
+    for g in range(1, generations + 1):
         r = _three_others(rng, n_win, pop)
         fscale = rng.uniform(f_lo, f_hi)
         if strategy == "best1":
@@ -189,18 +205,33 @@ def de_search(backend, boxes, rng: np.random.Generator, pop: int = 512, generati
         cross[wi, np.arange(pop)[None, :], rng.integers(0, dim, (n_win, pop))] = True
         trial = np.where(cross, mutant, x)
         s_trial = score(trial)
-        better = s_trial > s
+        better = (s_trial > s) & ~stopped[:, None]
         x[better] = trial[better]
         s[better] = s_trial[better]
         history.append(s.max(axis=1))
+        if tol > 0 and g % check_every == 0:
+            with np.errstate(invalid="ignore"):
+                stopped |= _de_converged(s, tol)
+            if stopped.all():
+                history += [history[-1]] * (generations - g)
+                break
     return _de_finish(backend, x, s, np.array(history), keep)
 
 
-def _de_device(backend, lo, hi, rng, pop, generations, cr, f_lo, f_hi, init, best1=False):
+def _de_converged(s, tol: float) -> np.ndarray:
+    """SciPy's convergence test per window: std(rho) <= tol |mean(rho)| over the population."""
+    m = s.mean(axis=1)
+    return np.isfinite(m) & (s.std(axis=1) <= tol * np.abs(m))
+
+
+def _de_device(backend, lo, hi, rng, pop, generations, cr, f_lo, f_hi, init, best1=False, tol=0.0,
+               check_every=50):
     """The DE generations with the population, scores and random draws in device memory: per
     generation one gb_de_trial, one gb_loglik of all trials and one gb_de_select, with no copy
     to the host (the uniforms come from a torch generator seeded by ``rng``; F is drawn from
-    ``rng`` as in the host loop).  Returns (x, s, history) as NumPy arrays."""
+    ``rng`` as in the host loop).  With tol > 0, every ``check_every`` generations the windows
+    whose population has converged leave the batch (their members are kept) and the rest run on
+    a plan of their own.  Returns (x, s, history) as NumPy arrays."""
     torch, api = backend.torch, backend.api
     dev = torch.device("cuda")
     f64 = torch.float64
@@ -220,20 +251,56 @@ def _de_device(backend, lo, hi, rng, pop, generations, cr, f_lo, f_hi, init, bes
     th0 = torch.as_tensor(np.ascontiguousarray(_to_theta(x.cpu().numpy()).reshape(n_win * pop, 8)), device=dev)
     _, comps = plan.loglik(th0, comps=True)
     best_idx = torch.zeros(n_win, dtype=torch.int32, device=dev)
-    hist = [api.gb_de_select(comps, x, s, x.clone(), best_idx=best_idx)]
+    hist = torch.full((generations + 1, n_win), np.nan, dtype=f64, device=dev)
+    hist[0] = api.gb_de_select(comps, x, s, x.clone(), best_idx=best_idx)
+    # the active windows' arrays (the whole batch until some window converges)
+    act = torch.arange(n_win, device=dev)
+    xa, sa, ba, lo_a, hi_a, plan_a, own_plan = x, s, best_idx, lo_t, hi_t, plan, False
     trial_x = torch.empty_like(x)
     trial_th = torch.empty((n_win * pop, 8), dtype=f64, device=dev)
     F = torch.empty(n_win, dtype=f64, device=dev)
-    for _ in range(generations):
-        u_idx = torch.rand((n_win, pop, 3), generator=gen, dtype=f64, device=dev)
-        u_cross = torch.rand((n_win, pop, dim), generator=gen, dtype=f64, device=dev)
-        u_j = torch.rand((n_win, pop), generator=gen, dtype=f64, device=dev)
+    for g in range(1, generations + 1):
+        na = len(act)
+        u_idx = torch.rand((na, pop, 3), generator=gen, dtype=f64, device=dev)
+        u_cross = torch.rand((na, pop, dim), generator=gen, dtype=f64, device=dev)
+        u_j = torch.rand((na, pop), generator=gen, dtype=f64, device=dev)
         F.fill_(float(rng.uniform(f_lo, f_hi)))
-        api.gb_de_trial(lo_t, hi_t, x, u_idx, u_cross, u_j, F, cr, REF_AMP, trial_x, trial_th,
-                        base=best_idx if best1 else None)
-        _, comps = plan.loglik(trial_th, comps=True)
-        hist.append(api.gb_de_select(comps, x, s, trial_x, best_idx=best_idx))
-    return x.cpu().numpy(), s.cpu().numpy(), torch.stack(hist).cpu().numpy()
+        api.gb_de_trial(lo_a, hi_a, xa, u_idx, u_cross, u_j, F[:na], cr, REF_AMP, trial_x[:na], trial_th[:na * pop],
+                        base=ba if best1 else None)
+        _, comps = plan_a.loglik(trial_th[:na * pop], comps=True)
+        hist[g, act] = api.gb_de_select(comps, xa, sa, trial_x[:na], best_idx=ba)
+        if tol > 0 and g % check_every == 0 and g < generations:
+            m = sa.mean(dim=1)
+            conv = torch.isfinite(m) & (sa.std(dim=1, unbiased=False) <= tol * m.abs())
+            n_conv = int(conv.sum().item())
+            if n_conv:
+                if xa is not x:                        # write the converged windows back
+                    x[act[conv]] = xa[conv]
+                    s[act[conv]] = sa[conv]
+                if own_plan:
+                    plan_a.close()
+                if n_conv == na:
+                    act = act[:0]
+                    break
+                keep_w = ~conv
+                if xa is x:                            # the first compaction: copy out the active rows
+                    xa, sa, ba = x[keep_w].contiguous(), s[keep_w].contiguous(), best_idx[keep_w].contiguous()
+                else:
+                    xa, sa, ba = xa[keep_w].contiguous(), sa[keep_w].contiguous(), ba[keep_w].contiguous()
+                act = act[keep_w]
+                lo_a, hi_a = lo_t[act].contiguous(), hi_t[act].contiguous()
+                plan_a, own_plan = backend._sub_plan(act.cpu().numpy(), pop, backend.pl), True
+    if len(act) and xa is not x:
+        x[act] = xa
+        s[act] = sa
+    if own_plan and len(act):
+        plan_a.close()
+    # a window that left the batch keeps its best value for the remaining generations
+    h = hist.cpu().numpy()
+    for g in range(1, generations + 1):
+        miss = np.isnan(h[g])
+        h[g, miss] = h[g - 1, miss]
+    return x.cpu().numpy(), s.cpu().numpy(), h
 
 
 def _de_finish(backend, x, s, history, keep):
@@ -338,7 +405,7 @@ def polish(backend, theta0: np.ndarray, scale: np.ndarray, iterations: int = 20,
 
 def search(backend, boxes, rng: np.random.Generator, pop: int = 512, generations: int = 50,
            keep: int = 8, polish_iterations: int = 20, scale_frac: float = 1e-3, n_searches: int = 1,
-           strategy: str = "best1"):
+           strategy: str = "best1", tol: float = 0.0):
     """Maximum-likelihood search of Sec. III D for every window of the backend: DE over the box,
     then the BFGS polish of the ``keep`` best members (scale: ``scale_frac`` of the box widths),
     repeated ``n_searches`` times from fresh populations in case a search ends at a local
@@ -349,7 +416,8 @@ def search(backend, boxes, rng: np.random.Generator, pop: int = 512, generations
     best_l = np.full(n_win, -np.inf)
     scale = (scale_frac * (hi - lo))[:, None, :]
     for _ in range(n_searches):
-        th, _, _ = de_search(backend, boxes, rng, pop=pop, generations=generations, keep=keep, strategy=strategy)
+        th, _, _ = de_search(backend, boxes, rng, pop=pop, generations=generations, keep=keep, strategy=strategy,
+                             tol=tol)
         th, hist = polish(backend, th, scale, iterations=polish_iterations)
         l_end = hist[-1]                                       # [n_win, keep]
         j = np.argmax(l_end, axis=1)
@@ -573,7 +641,7 @@ def _rho_of(comps):
 def local_search(backend, seg_edges, rng: np.random.Generator, n_signals: int, rho_threshold: float = 9.0,
                  n_searches: int = 3, pop: int = 512, generations: int = 50, keep: int = 8,
                  polish_iterations: int = 20, scale_frac: float = 1e-3, joint_sweeps: int = 2, progress=None,
-                 strategy: str = "best1"):
+                 strategy: str = "best1", tol: float = 0.0):
     """Algorithm 2 for every window of the backend at once (each window = one padded segment;
     seg_edges [n_win, 2] = the unpadded segment's edges in Hz).  Per signal: n_searches DE +
     polish searches on the residual (the first one ends the window when rho on the analysed data
@@ -603,7 +671,8 @@ def local_search(backend, seg_edges, rng: np.random.Generator, n_signals: int, r
         best_rho_an = np.full(n_win, -np.inf)
         for j in range(n_searches):
             th, _ = search(backend, boxes, rng, pop=pop, generations=generations, keep=keep,
-                           polish_iterations=polish_iterations, scale_frac=scale_frac, strategy=strategy)
+                           polish_iterations=polish_iterations, scale_frac=scale_frac, strategy=strategy,
+                           tol=tol)
             rho_res = _rho_of(backend.loglik(th)[1])
             rho_an = backend.rho_analyze(th)
             if j == 0:

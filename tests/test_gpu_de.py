@@ -119,3 +119,24 @@ def test_device_de_search_finds_sources(oracle_lib):
         if len(w.sources):
             assert abs(th[i, 0, 0] - w.sources[0, 0]) * wl.T < 1.0, (i, th[i, 0, 0] * wl.T, w.sources[0, 0] * wl.T)
     be.close()
+
+
+def test_device_de_convergence_stop(oracle_lib):
+    banner("device DE with SciPy's convergence stop: windows leave the batch as they converge")
+    from tests.test_search_cpu import segments_workload
+    wl, seg = segments_workload(oracle_lib)
+    ctx = api.context_for(wl.T)
+    be = D.GpuBackend(ctx, wl.window_table(), dev(wl.data, torch.complex128), dev(wl.weights), api.GB_MIXED)
+    boxes = [wl.window_box(i) for i in range(wl.n_win)]
+    th, rho, hist = D.de_search(be, boxes, np.random.default_rng(5), pop=128, generations=600, keep=2,
+                                tol=0.01, check_every=10)
+    assert th.shape == (wl.n_win, 2, 8) and hist.shape == (601, wl.n_win)
+    assert np.all(np.isfinite(hist)) and np.all(np.diff(hist, axis=0) >= 0)
+    # the windows with a loud source converged on it and stopped early: their best rho is flat
+    # over the last generations
+    for i, w in enumerate(wl.windows):
+        if len(w.sources):
+            assert abs(th[i, 0, 0] - w.sources[0, 0]) * wl.T < 1.0
+            assert hist[-1, i] == hist[-100, i]
+    assert np.allclose(rho[:, 0], hist[-1])
+    be.close()
