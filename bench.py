@@ -595,8 +595,9 @@ def posterior_leg(n_sources, log):
 def pipeline_leg(segments, log, precision: str = "mixed", catalogue=None, **search_kw):
     """Algorithm 5 end to end over a contiguous block of the full-band workload (4000 segments
     over 0.3-30 mHz, 20,000 GBs, T = 2^22*15 s, PSD noise): the global search (Algorithm 3 with
-    the three runs of Table II; per signal three searches of DE/best/1/bin with 512 members x
-    1000 generations on the device plus the gradient polish, four joint sweeps; mixed gradient, the
+    the three runs of Table II; per signal three searches of DE/best/1/bin with 512 members x up
+    to 1000 generations on the device (SciPy's convergence stop) plus the gradient polish, four
+    joint sweeps; mixed gradient, the
     likelihood in ``precision``), the residual, and the annealed posterior (6 x 10,000) of every
     recovered source, batched, its likelihood in ``precision`` too.  Wall-clock seconds per
     phase (host work included); recovered sources scored with the match metric of Sec. V
@@ -645,7 +646,8 @@ def pipeline_leg(segments, log, precision: str = "mixed", catalogue=None, **sear
 
     torch.cuda.synchronize()
     t0 = time.time()
-    kw = dict(n_searches=3, pop=512, generations=1000, polish_iterations=20, joint_sweeps=4, strategy="best1")
+    kw = dict(n_searches=3, pop=512, generations=1000, polish_iterations=20, joint_sweeps=4, strategy="best1",
+              tol=0.01)
     kw.update(search_kw)
     found, found_seg = D.global_search(factory, table, T, segs, d, np.random.default_rng(2023), subtract,
                                        progress=lambda m: log(f"pipeline: {m}"), **kw)
@@ -685,7 +687,8 @@ def pipeline_leg(segments, log, precision: str = "mixed", catalogue=None, **sear
         "seconds_posterior_per_source": round((t2 - t1) / max(1, len(found)), 5),
         "posterior_accepted_median": (np.median(acc, axis=0).astype(int).tolist() if len(acc) else None),
         "search": f"Algorithm 3, runs (even, 3), (odd, 10), (even, 10); {kw['n_searches']} searches per signal, "
-                  f"DE/{kw['strategy'][:-1]}/1/bin {kw['pop']} x {kw['generations']}, "
+                  f"DE/{kw['strategy'][:-1]}/1/bin {kw['pop']} x up to {kw['generations']} "
+                  f"(stop at spread {kw['tol']} of the mean), "
                   f"polish {kw['polish_iterations']} iterations, "
                   f"{kw['joint_sweeps']} joint sweeps, rho threshold 9",
         "precision": f"likelihood {precision} (search and posterior), gradient mixed, templates for "
