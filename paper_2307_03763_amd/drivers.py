@@ -632,12 +632,6 @@ class GpuPosteriorBackend:
 # ---------------------------------------------------------------------------------------------
 # Search within frequency segments (Algorithm 2), for many segments at once
 
-def _rho_of(comps):
-    with np.errstate(invalid="ignore", divide="ignore"):
-        r = comps[:, 0] / np.sqrt(comps[:, 1])
-    return np.where(np.isfinite(r), r, -np.inf)
-
-
 def local_search(backend, seg_edges, rng: np.random.Generator, n_signals: int, rho_threshold: float = 9.0,
                  n_searches: int = 3, pop: int = 512, generations: int = 50, keep: int = 8,
                  polish_iterations: int = 20, scale_frac: float = 1e-3, joint_sweeps: int = 2, progress=None,
@@ -673,7 +667,7 @@ def local_search(backend, seg_edges, rng: np.random.Generator, n_signals: int, r
             th, _ = search(backend, boxes, rng, pop=pop, generations=generations, keep=keep,
                            polish_iterations=polish_iterations, scale_frac=scale_frac, strategy=strategy,
                            tol=tol)
-            rho_res = _rho_of(backend.loglik(th)[1])
+            rho_res = _snr(backend.loglik(th)[1])
             rho_an = backend.rho_analyze(th)
             if j == 0:
                 active &= ~(rho_an <= rho_threshold - 2.0)
@@ -741,7 +735,7 @@ class GpuSearchBackend(GpuBackend):
             p.prepare(self.d, self.w)
 
     def rho_analyze(self, theta):
-        return _rho_of(self.analyze.loglik(theta)[1])
+        return _snr(self.analyze.loglik(theta)[1])
 
     def close(self):
         super().close()
