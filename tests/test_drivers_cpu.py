@@ -150,3 +150,14 @@ def test_polish_batched_equals_separate(c4_two):
         th_s, h_s = D.polish(OracleBackend(O, wl, [i]), starts[i], sig[i], iterations=15)
         np.testing.assert_array_equal(th_b[i], th_s)
         np.testing.assert_array_equal(h_b[:, i], h_s)
+
+
+def test_de_convergence_stop(c1):
+    """SciPy's stopping rule (std(rho) <= tol |mean(rho)|): the window stops early, keeps its
+    best member (the injection, within a bin) and its history stays flat afterwards."""
+    O, wl, be, box, src, _ = c1
+    th, rho, hist = D.de_search(be, box, np.random.default_rng(2), pop=64, generations=400, tol=0.01,
+                                check_every=10)
+    assert hist.shape == (401, 1) and np.all(np.diff(hist[:, 0]) >= 0)
+    assert hist[-1, 0] == hist[-150, 0]            # stopped well before the last generation
+    assert abs(th[0, 0, 0] - src[0]) * wl.T < 1.0
