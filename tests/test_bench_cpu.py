@@ -1,0 +1,78 @@
+"""Host logic of the benchmark (CPU): the work model behind the roofline figure, the reading of
+rocprofv3 output (kernel names, the timed-region filter, CSV dispatch records), and the lookup
+of committed counter results."""
+
+import json
+import math
+import os
+
+import pytest
+
+import bench
+
+
+def test_flop_model_examples():
+    # the worked example of the design notes: N = 256, C = 2, overlap 256
+    assert bench.flops_per_eval(256, 2, 256, False) == pytest.approx(1.18e5, rel=0.01)
+    assert bench.flops_per_eval(256, 2, 256, True) == pytest.approx(3.7e5, rel=0.01)
+    # the pieces: slow series per sample (+12 with T), one DFT per channel, 20 per bin and channel
+    N, C, ov = 512, 3, 700
+    f = bench.flops_per_eval(N, C, ov, False)
+    assert f == 351 * N + C * 5 * N * math.log2(N) + 20 * C * ov
+    g = bench.flops_per_eval(N, C, ov, True)
+    assert g - f == C * 5 * N * math.log2(N) + 900 * N + 6 * C * ov
+    assert bench.sincos_per_eval(N, False) == 4 * N and bench.sincos_per_eval(N, True) == 9 * N
+
+
+def test_kernel_key():
+    assert bench._kernel_key("void gbx::k_batch<double, 512, 128, 3, 4, 1, 1>(gbx::BatchArgs)") == \
+        "k_batch<double,512,128,3,4,1,1>"
+    assert bench._kernel_key("k_mh_chain(gbx::ChainWin const*)") == "k_mh_chain"
+
+
+def _bench_line(kern, n, region):
+    return {"roofline": {"kernel": kern, "launches_in_region": n}, "timed_region_ns": region}
+
+
+def test_timed_region_filter():
+    k = "k_batch<float,512,64,3,4,2,1>"
+    disp = [(k, 100, 200, None), (k, 300, 400, None), (k, 500, 600, None), ("other", 150, 160, None),
+            (k, 1100, 1200, None), (k, 1300, 1400, None)]
+    # the first clock's window holds 3 launches (wrong count), the second's exactly 2
+    line = _bench_line(k, 2, {"monotonic": [50, 650], "boottime": [1050, 1450]})
+    sel = bench._in_region(disp, line)
+    assert [d[1] for d in sel] == [1100, 1300]
+    with pytest.raises(ValueError):
+        bench._in_region(disp, _bench_line(k, 5, {"monotonic": [50, 650]}))
+
+
+def test_dispatches_from_csv(tmp_path):
+    run = tmp_path / "run" / "host"
+    run.mkdir(parents=True)
+    (run / "x_kernel_trace.csv").write_text(
+        "Kernel_Name,Start_Timestamp,End_Timestamp\n"
+        "\"void gbx::k_batch<float, 64, 16, 2, 4, 1, 2>(gbx::BatchArgs)\",10,20\n"
+        "k_mh_chain(gbx::ChainWin const*),30,40\n")
+    d = bench._dispatches(str(tmp_path / "run"))
+    assert d == [("k_batch<float,64,16,2,4,1,2>", 10, 20, None), ("k_mh_chain", 30, 40, None)]
+    with pytest.raises(FileNotFoundError):
+        bench._dispatches(str(tmp_path / "empty"))
+
+
+def test_committed_traffic_lookup(tmp_path, monkeypatch):
+    h = bench.kernel_source_hash()
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    (prof / "hbm_traffic.txt").write_text(
+        "# comment line kernel_src=x kernel=k bytes=1 evals=1\n"
+        f"kernel_src={h} kernel=k_batch<float,512,64,3,4,2,1> evals=400000 bytes=80000000\n"
+        f"kernel_src=0000 kernel=k_batch<float,256,32,2,4,2,2> evals=100 bytes=100\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: h)
+    # exact kernel, scaled to the evaluations of a launch
+    assert bench.committed_traffic("k_batch<float,512,64,3,4,2,1>", 200000) == 40000000.0
+    # the other persistent-grid variant of the family (same machine code)
+    assert bench.committed_traffic("k_batch<float,512,64,3,4,2,2>", 400000) == 80000000.0
+    # another family, or counters taken on other kernel sources: none
+    assert bench.committed_traffic("k_batch<float,512,64,2,4,2,1>", 400000) is None
+    assert bench.committed_traffic("k_batch<float,256,32,2,4,2,2>", 100) is None
