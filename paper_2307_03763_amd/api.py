@@ -396,6 +396,29 @@ class Plan:
             pass
 
 
+class LogLikelihood(torch.autograd.Function):
+    """logL of every candidate of a prepared plan as a differentiable torch function: the
+    forward pass runs gb_loglik_grad (likelihood and the hand-written adjoint gradient in one
+    launch) and keeps the gradient; the backward pass scales it by the incoming cotangent.
+    The plan's windows need a gradient-capable precision (mixed; the FP64 gradient is off)."""
+
+    @staticmethod
+    def forward(ctx, theta: torch.Tensor, plan: "Plan") -> torch.Tensor:
+        logL, grad = plan.loglik_grad(theta.detach().contiguous())
+        ctx.save_for_backward(grad)
+        return logL
+
+    @staticmethod
+    def backward(ctx, grad_out: torch.Tensor):
+        (grad,) = ctx.saved_tensors
+        return grad_out[:, None] * grad, None
+
+
+def loglik(plan: "Plan", theta: torch.Tensor) -> torch.Tensor:
+    """Differentiable logL of theta [rows, 8] on a prepared plan (see LogLikelihood)."""
+    return LogLikelihood.apply(theta, plan)
+
+
 def context_for(T: float):
     """Context with the synthetic setting's constellation constants."""
     from . import inputs as I

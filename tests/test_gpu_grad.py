@@ -5,6 +5,8 @@ Scale of a gradient component: |dlogL/dtheta_i| <= ||d - h|| ||d_i h|| <= sqrt(F
 up to a factor of order one, so errors are measured against s_i = sqrt(F_ii (<d|d> + <h|h>)).
 Bars: FP64 1e-9 s_i; mixed precision 1e-5 s_i.
 
+The torch.autograd wrapper (api.loglik) returns the library's gradient through the chain rule.
+
 The FP64 gradient is switched off in the library (its kernels faulted on the GPU while a CPU
 emulation of the same source is clean; cause not yet known), so its cases are skipped and a test
 checks that the call is refused with GB_EUNSUPPORTED before any kernel runs.
@@ -169,3 +171,25 @@ def test_fp64_gradient_is_refused(c3_grad):
         plan.loglik_grad(dev(wl.theta))
     assert e.value.status == api.GB_EUNSUPPORTED
     assert "FP64 gradient" in str(e.value)
+
+
+def test_autograd_function(oracle_lib):
+    banner("torch.autograd wrapper of the adjoint gradient (mixed plan)")
+    wl = _workload(oracle_lib, 2)
+    l, g, _, (ctx, plan, d, w, th) = _run(wl, api.GB_MIXED)
+    x = th.clone().requires_grad_(True)
+    out = api.loglik(plan, x)
+    assert out.requires_grad and torch.equal(out.detach().cpu(), torch.as_tensor(l))
+    weights = torch.linspace(0.5, 2.0, len(out), dtype=torch.float64, device=out.device)
+    (weights * out).sum().backward()
+    # the chain rule with the library's gradient, bit for bit (the kernels are deterministic)
+    assert torch.equal(x.grad.cpu(), (weights[:, None] * torch.as_tensor(g, device=out.device)).cpu())
+    # composes with other torch operations: d/dtheta of sum(exp(logL - max)) = softmax-weighted gradient
+    x.grad = None
+    y = api.loglik(plan, x)
+    z = torch.exp(y - y.max().detach()).sum()
+    z.backward()
+    ref = torch.exp(torch.as_tensor(l) - torch.as_tensor(l).max())[:, None] * torch.as_tensor(g)
+    np.testing.assert_allclose(x.grad.cpu().numpy(), ref.numpy(), rtol=1e-12, atol=0)
+    plan.close()
+    ctx.close()
