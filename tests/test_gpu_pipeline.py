@@ -1,0 +1,26 @@
+"""Algorithm 5 end to end on the GPU, as the benchmark's pipeline leg runs it, on a 30-segment
+block of the full-band workload (3.9-4.0 mHz): the global search (three even/odd runs, device
+DE, polish, joint refinement), the residual, the batched annealed posteriors and the match
+metric of Sec. V.  Regression bars from the measured behaviour (about 97% of the recovered
+sources matched, about 95% of the detectable injections found): at least 85% and 80%."""
+
+import sys
+
+import pytest
+
+import bench
+from tests.gpu_common import banner
+
+pytestmark = pytest.mark.gpu
+
+
+def test_pipeline_block():
+    banner("pipeline (Algorithm 5) on segments 2400-2429 of the full-band workload")
+    r = bench.pipeline_leg((2400, 2430), lambda m: print(f"[pipeline] {m}", file=sys.stderr, flush=True))
+    banner(f"  recovered {r['recovered']}, matched {r['matched_delta_lt_0.3']}, detectable {r['injected_snr_gt_9']} "
+           f"(found {r['injected_snr_gt_9_matched']}), search {r['seconds_search']} s, posteriors "
+           f"{r['seconds_posterior']} s")
+    assert r["recovered"] > 0
+    assert r["match_rate_delta"] >= 0.85
+    assert r["injected_snr_gt_9_matched"] >= 0.8 * r["injected_snr_gt_9"]
+    assert all(a > 0 for a in r["posterior_accepted_median"])
