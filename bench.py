@@ -25,6 +25,9 @@ METRIC = "GB logL evals/s + grad evals/s (ragged, mixed prec) vs plain FP64 on s
 PEAK_VALU_TFLOPS = 78.6     # MI355X vector FMA rate (FP64, and FP32 without packed math)
 PEAK_HBM_GBS = 8000.0
 COPY_N = 1 << 28            # copy calibration: 256 M doubles = 2 GiB read + 2 GiB written per launch
+N_SIMD = 256 * 4            # MI355X: 256 compute units of 4 SIMDs
+SQ_COUNTERS = ("SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_WAIT_ANY", "SQ_WAIT_INST_ANY",
+               "SQ_ACTIVE_INST_ANY", "SQ_ACTIVE_INST_VALU", "SQ_INSTS_VALU")
 
 
 # ------------------------------------------------------------------------------------------
@@ -82,6 +85,9 @@ def parse():
                     help="use the launch shapes that an earlier bench run chose (its output line)")
     ap.add_argument("--trace-summary", nargs=2, metavar=("BENCH_JSON", "TRACE_DIR"),
                     help="print the timed-region kernel summary of a rocprofv3 --kernel-trace and exit")
+    ap.add_argument("--counter-summary", nargs=2, metavar=("BENCH_JSON", "PMC_DIR"),
+                    help="print per-kernel issue statistics of the timed region from a rocprofv3 --pmc run of "
+                         "the SQ counters " + " ".join(SQ_COUNTERS) + " and exit")
     return ap.parse_args()
 
 
@@ -95,6 +101,9 @@ def main():
         return
     if args.trace_summary:
         print(trace_summary(*args.trace_summary))
+        return
+    if args.counter_summary:
+        print(counter_summary(*args.counter_summary))
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -450,6 +459,39 @@ def trace_summary(bench_json: str, trace_dir: str) -> str:
     dom = per[kern]
     lines.append(f"dominant kernel {kern}: rocprofv3 average {sum(dom) / len(dom):.4f} ms over {len(dom)} "
                  f"launches; bench HIP-event average {b['roofline']['launch_ms']:.4f} ms")
+    return "\n".join(lines)
+
+
+def counter_summary(bench_json: str, pmc_dir: str) -> str:
+    """Per-kernel issue statistics from one rocprofv3 --pmc run of SQ_COUNTERS over the bench
+    (its output line in bench_json), summed over the dispatches of each k_batch kernel inside
+    the timed region.  Per wave: the share of its cycles spent issuing VALU
+    instructions (SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES) and waiting (SQ_WAIT_ANY /
+    SQ_WAVE_CYCLES).  The persistent kernels launch exactly the waves that stay resident, so
+    waves per SIMD = waves per dispatch / N_SIMD, and that times the per-wave VALU share is the
+    share of the SIMD's cycles with a VALU instruction in flight."""
+    b = _last_json(bench_json)
+    per = {}
+    for ctr in SQ_COUNTERS:
+        tot = {}   # the counter has one value per shader engine: sum them per dispatch
+        for k, t0, t1, v in _dispatches(pmc_dir, ctr):
+            tot[(k, t0, t1)] = tot.get((k, t0, t1), 0.0) + v
+        for k, t0, t1, v in _in_region([key + (v,) for key, v in tot.items()], b):
+            if not k.startswith("k_batch"):
+                continue
+            d = per.setdefault(k, {"disp": set()})
+            d["disp"].add((t0, t1))
+            d[ctr] = d.get(ctr, 0.0) + v
+    lines = [f"{'kernel':<34} {'disp':>5} {'avg ms':>8} {'waves/SIMD':>10} {'VALU/wave':>9} {'wait/wave':>9} "
+             f"{'SIMD VALU busy':>14} {'VALU cyc/inst':>13}"]
+    for k, d in sorted(per.items(), key=lambda kv: -sum(t1 - t0 for t0, t1 in kv[1]["disp"])):
+        n = len(d["disp"])
+        ms = sum(t1 - t0 for t0, t1 in d["disp"]) * 1e-6 / n
+        wc = d["SQ_WAVE_CYCLES"]
+        wps = d["SQ_WAVES"] / n / N_SIMD
+        valu = d["SQ_ACTIVE_INST_VALU"] / wc
+        lines.append(f"{k:<34} {n:>5} {ms:>8.3f} {wps:>10.2f} {valu:>9.3f} {d['SQ_WAIT_ANY'] / wc:>9.3f} "
+                     f"{valu * wps:>14.3f} {d['SQ_ACTIVE_INST_VALU'] / d['SQ_INSTS_VALU']:>13.3f}")
     return "\n".join(lines)
 
 

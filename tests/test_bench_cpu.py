@@ -76,3 +76,33 @@ def test_committed_traffic_lookup(tmp_path, monkeypatch):
     # another family, or counters taken on other kernel sources: none
     assert bench.committed_traffic("k_batch<float,512,64,2,4,2,1>", 400000) is None
     assert bench.committed_traffic("k_batch<float,256,32,2,4,2,2>", 100) is None
+
+
+def test_counter_summary(tmp_path):
+    """Per-engine counter rows are summed per dispatch, only timed-region dispatches count, and
+    the SIMD busy share is waves per SIMD times the per-wave VALU share."""
+    k = "k_batch<float,512,64,3,4,2,1>"
+    run = tmp_path / "pmc" / "host"
+    run.mkdir(parents=True)
+    rows = ["Kernel_Name,Start_Timestamp,End_Timestamp,Counter_Name,Counter_Value"]
+    name = f"\"void gbx::{k.replace(',', ', ')}(gbx::BatchArgs)\""
+    # one dispatch before the region, two inside; each counter split over two engine rows
+    for t0, t1 in ((100, 200), (1_000_000, 5_000_000), (6_000_000, 12_000_000)):
+        per = {"SQ_WAVES": 2048, "SQ_WAVE_CYCLES": 1000.0, "SQ_BUSY_CYCLES": 1.0, "SQ_WAIT_ANY": 250.0,
+               "SQ_WAIT_INST_ANY": 1.0, "SQ_ACTIVE_INST_ANY": 1.0, "SQ_ACTIVE_INST_VALU": 400.0,
+               "SQ_INSTS_VALU": 200.0}
+        if t0 == 100:
+            per["SQ_ACTIVE_INST_VALU"] = 0.0
+        for c, v in per.items():
+            rows += [f"{name},{t0},{t1},{c},{v / 2}"] * 2
+    (run / "x_counter_collection.csv").write_text("\n".join(rows) + "\n")
+    bj = tmp_path / "b.json"
+    bj.write_text(json.dumps({"roofline": {"kernel": k, "launches_in_region": 2},
+                              "timed_region_ns": {"monotonic": [900, 13_000_000]}}) + "\n")
+    out = bench.counter_summary(str(bj), str(tmp_path / "pmc")).splitlines()
+    assert len(out) == 2 and out[1].split()[0] == k
+    f = out[1].split()
+    assert f[1] == "2" and float(f[2]) == pytest.approx(5.0)      # dispatches, avg ms
+    assert float(f[3]) == pytest.approx(2.0)                         # 2048 waves / 1024 SIMDs
+    assert float(f[4]) == pytest.approx(0.4) and float(f[5]) == pytest.approx(0.25)
+    assert float(f[6]) == pytest.approx(0.8) and float(f[7]) == pytest.approx(2.0)

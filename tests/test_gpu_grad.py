@@ -25,16 +25,17 @@ from tests.gpu_common import banner, dev, window_dd
 pytestmark = pytest.mark.gpu
 
 
-def _workload(oracle_lib, C):
-    """Gradient workload shaped like the paper's windows, small enough for the oracle."""
+def _workload(oracle_lib, C, f_lo=12e-3, f_span=4e-3):
+    """Gradient workload shaped like the paper's windows, small enough for the oracle.  C = 3
+    moves every window to a frequency in [f_lo, f_lo + f_span] above f*/2, so the T channel is
+    used."""
     wl = I.workload_c4(oracle_lib.template_fn(), n_win=6, n_cand=9)
     if C == 3:
-        # move every window above f*/2 so the T channel is used
         T = wl.T
         wins, thetas = [], []
         rng = np.random.default_rng(31)
         for w in wl.windows:
-            fc = 12e-3 + rng.uniform(0, 4e-3)
+            fc = f_lo + rng.uniform(0, f_span)
             q = int(fc * T)
             k0 = q - w.W // 2
             src = I.make_theta([(q + 0.3) / T], I.fdot_gr(fc, 0.5), 2e-22, I.random_angles(rng, 1))
@@ -78,8 +79,24 @@ FP64_GRAD_OFF = "FP64 gradient switched off: its kernels faulted on the GPU; cau
                                       (api.GB_MIXED, 1e-5)])
 def test_gradient_matches_oracle(oracle_lib, C, prec, bar):
     banner(f"gradient vs oracle C={C} prec={prec}")
+    _check_against_oracle(oracle_lib, _workload(oracle_lib, C), prec, bar)
+
+
+def test_gradient_high_frequency(oracle_lib):
+    """Windows at 30-60 mHz: above about c / (pi L) = 38 mHz a link's transfer argument
+    pi f L (1 +- k.n) / c can pass 2, and on those links the forward sinc and the adjoint's
+    sinc derivative switch from their series to their quotient forms; the windows below keep
+    the series everywhere."""
+    banner("gradient vs oracle, 30-60 mHz, C=3, mixed")
+    wl = _workload(oracle_lib, 3, f_lo=30e-3, f_span=30e-3)
+    f = np.array([w.sources[0, 0] for w in wl.windows])
+    f_series = 0.999 / (np.pi * I.ARM_L / I.C_LIGHT)      # below it every link argument is below 2
+    assert np.any(f < f_series) and np.any(f > 40e-3), f
+    _check_against_oracle(oracle_lib, wl, api.GB_MIXED, 1e-5)
+
+
+def _check_against_oracle(oracle_lib, wl, prec, bar):
     O = oracle_lib
-    wl = _workload(O, C)
     l, g, l2, _ = _run(wl, prec)
     worst = np.zeros(8)
     for i in range(wl.n_win):
