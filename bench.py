@@ -35,17 +35,18 @@ SQ_COUNTERS = ("SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_WAIT_ANY", "S
 # sample, counted from the gfx950 assembly of the kernels (one FMA = 2 flops), with the sin/cos
 # evaluations counted separately, not as flops; the DFT at the usual 5 N log2 N per channel
 def flops_per_eval(N: int, C: int, overlap: int, grad: bool) -> float:
-    per_sample = 339.0 + (12.0 if C == 3 else 0.0)          # slow series (response, TDI, channels)
+    per_sample = 324.0 + (10.0 if C == 3 else 0.0)          # slow series (response, TDI, channels)
     fft = C * 5.0 * N * math.log2(N)                          # one radix-2-equivalent DFT per channel
     red = 20.0 * C * overlap                                  # residual and four FP64 accumulations
     f = per_sample * N + fft + red
     if grad:
-        f += fft + 900.0 * N + 6.0 * C * overlap              # inverse DFT, per-sample adjoint, cotangent
+        f += fft + 825.0 * N + 6.0 * C * overlap              # inverse DFT, per-sample adjoint, cotangent
     return f
 
 
 def sincos_per_eval(N: int, grad: bool) -> float:
-    return (4.0 + (5.0 if grad else 0.0)) * N
+    # carrier, D and two spacecraft phases per sample; the adjoint recomputes the same four
+    return (4.0 + (4.0 if grad else 0.0)) * N
 
 
 def bytes_per_eval(C: int, overlap: int, grad: bool) -> float:

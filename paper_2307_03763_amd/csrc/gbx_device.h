@@ -34,6 +34,13 @@ enum {
   OB_FIELDS = 20
 };
 
+// Normalisation of channel c: A = (Z - X)/sqrt2, E = (X - 2Y + Z)/sqrt6, T = (X + Y + Z)/sqrt3
+// (Sec. II).  The slow series hold the X, Y, Z combinations without it; it is applied in FP64
+// with the amplitude after the DFT.
+__device__ __forceinline__ constexpr double chan_norm(int c) {
+  return c == 0 ? 0.70710678118654752440 : c == 1 ? 0.40824829046386301637 : 0.57735026918962576451;
+}
+
 template <class R>
 struct cplx {
   R x, y;
@@ -194,7 +201,8 @@ __device__ __forceinline__ Cand<R> make_cand(const double* th, double T) {
   return s;
 }
 
-// One sample of the slow series of channels A, E[, T] for unit amplitude at t = tab time m.
+// One sample of the slow series of channels A, E[, T] (without their normalisations) for unit
+// amplitude at t = tab time m.
 // ob64: FP64 orbit table [OB_FIELDS][N]; obR: the same in precision R (fields >= OB_N12).
 template <class R, int C>
 __device__ __forceinline__ void slow_sample(const Cand<R>& s, const double* __restrict__ ob64,
@@ -208,20 +216,28 @@ __device__ __forceinline__ void slow_sample(const Cand<R>& s, const double* __re
   R sp, cp;
   sincos_rev((R)p, &sp, &cp);
   const R fr = (R)f;
-  const R x = (R)kPi * fr * (R)Lc;  // pi f L / c
+  const R x = fr * (R)(kPi * Lc);  // pi f L / c
   R sD, cD;
   sincos_rev(-fr * (R)Lc, &sD, &cD);  // D = e^{-2 pi i f L/c}
 
-  R kn[3], Fp[3], Fx[3];
+  // projections on the arms; the arm vectors of the rigid triangle sum to zero, so the third
+  // arm's projections are minus the sum of the other two
+  R kn[3], un[3], vn[3], Fp[3], Fx[3];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
+  for (int a = 0; a < 2; ++a) {
     const int o = OB_N12 + 3 * a;
     const R n0 = obR[(o + 0) * N + m], n1 = obR[(o + 1) * N + m], n2 = obR[(o + 2) * N + m];
     kn[a] = s.k[0] * n0 + s.k[1] * n1 + s.k[2] * n2;
-    const R un = s.u[0] * n0 + s.u[1] * n1 + s.u[2] * n2;
-    const R vn = s.v[0] * n0 + s.v[1] * n1;
-    Fp[a] = un * un - vn * vn;
-    Fx[a] = (R)2 * un * vn;
+    un[a] = s.u[0] * n0 + s.u[1] * n1 + s.u[2] * n2;
+    vn[a] = s.v[0] * n0 + s.v[1] * n1;
+  }
+  kn[2] = -(kn[0] + kn[1]);
+  un[2] = -(un[0] + un[1]);
+  vn[2] = -(vn[0] + vn[1]);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    Fp[a] = un[a] * un[a] - vn[a] * vn[a];
+    Fx[a] = (R)2 * un[a] * vn[a];
   }
   // k . dx_o / c for spacecraft 1, 2, 3
   R kp[3];
@@ -261,10 +277,10 @@ __device__ __forceinline__ void slow_sample(const Cand<R>& s, const double* __re
   // at low frequency)
   const cplx<R> omd = mk<R>((R)2 * sD * sD, -((R)2 * cD * sD));
   const cplx<R> K = scal(mul_mi(omd * mk<R>(cp, sp)), x);
-  const R r2 = (R)0.70710678118654752440, r6 = (R)0.40824829046386301637, r3 = (R)0.57735026918962576451;
-  out[0] = K * scal(Z - X, r2);
-  out[1] = K * scal(X - scal(Y, (R)2) + Z, r6);
-  if (C == 3) out[C - 1] = K * scal(X + Y + Z, r3);
+  // the channels without their normalisations (chan_norm)
+  out[0] = K * (Z - X);
+  out[1] = K * (X - scal(Y, (R)2) + Z);
+  if (C == 3) out[C - 1] = K * (X + Y + Z);
 }
 
 // ------------------------------------------------------------------------------------
@@ -453,8 +469,8 @@ __device__ __forceinline__ void grad_sample_rev(const Cand<R>& s, const CandG<R>
   sincos_rev((R)p, &sp, &cp);
   sincos_rev(-fr * Lr, &sDm, &cDm);  // D = e^{-i phi_D}: (cDm, sDm), sDm = -sin(phi_D)
   const cplx<R> D = mk<R>(cDm, sDm);
-  const R phiD = twopi * fr * Lr;
-  const R x = pi * fr * Lr;
+  const R phiD = fr * (R)(2.0 * kPi * Lc);
+  const R x = fr * (R)(kPi * Lc);
   const R kappa = -(R)2 * x * sDm;                     // = phi_D sin(phi_D)
   const cplx<R> Ep = D * mk<R>(cp, sp);                 // e^{i psi}
   const cplx<R> K = scal(Ep, kappa);
@@ -466,21 +482,35 @@ __device__ __forceinline__ void grad_sample_rev(const Cand<R>& s, const CandG<R>
   cplx<R> E[3], P[3];
   const int opp[3] = {2, 0, 1};
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
+  for (int a = 0; a < 2; ++a) {
     const int o = OB_N12 + 3 * a;
     const R n0 = obR[(o + 0) * N + m], n1 = obR[(o + 1) * N + m], n2 = obR[(o + 2) * N + m];
     kn[a] = s.k[0] * n0 + s.k[1] * n1 + s.k[2] * n2;
     un[a] = s.u[0] * n0 + s.u[1] * n1 + s.u[2] * n2;
     vn[a] = s.v[0] * n0 + s.v[1] * n1;
     wn[a] = sg.wl[0] * n0 + sg.wl[1] * n1;
+  }
+  // the arm vectors of the rigid triangle sum to zero (as in the forward series)
+  kn[2] = -(kn[0] + kn[1]);
+  un[2] = -(un[0] + un[1]);
+  vn[2] = -(vn[0] + vn[1]);
+  wn[2] = -(wn[0] + wn[1]);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
     Fp[a] = un[a] * un[a] - vn[a] * vn[a];
     Fx[a] = (R)2 * un[a] * vn[a];
+    if (a == 0) continue;  // spacecraft 3 (arm 12) below
     const int q = OB_P1 + 3 * opp[a];
     const R p0 = obR[(q + 0) * N + m], p1 = obR[(q + 1) * N + m], p2 = obR[(q + 2) * N + m];
     kp[a] = s.k[0] * p0 + s.k[1] * p1 + s.k[2] * p2;
     up[a] = s.u[0] * p0 + s.u[1] * p1 + s.u[2] * p2;
     vp[a] = s.v[0] * p0 + s.v[1] * p1;
   }
+  // the offsets from the guiding centre sum to zero: spacecraft 3's projections are minus the
+  // sum of those of spacecraft 1 and 2 (as its phase factor is in the forward series)
+  kp[0] = -(kp[1] + kp[2]);
+  up[0] = -(up[1] + up[2]);
+  vp[0] = -(vp[1] + vp[2]);
   // spacecraft phase factors e^{i pi f k.dx / c}: arms 23 and 31 face spacecraft 1 and 2; the
   // offsets sum to zero, so the factor of spacecraft 3 (arm 12) is the conjugate of their product
 #pragma unroll
@@ -502,12 +532,12 @@ __device__ __forceinline__ void grad_sample_rev(const Cand<R>& s, const CandG<R>
     sinc_d(x * ((R)1 + kn[a]), &sv[2 * a + 1], &sd[2 * a + 1]);
   }
   const R s12 = sv[0], s21 = sv[1], s23 = sv[2], s32 = sv[3], s31 = sv[4], s13 = sv[5];
-  const R r2 = (R)0.70710678118654752440, r6 = (R)0.40824829046386301637, r3 = (R)0.57735026918962576451;
+  // channel cotangents (of the series without their normalisations) folded onto X, Y, Z
   const cplx<R> cA = conjg(sbar[0]), cE = conjg(sbar[1]);
   const cplx<R> cT = (C == 3) ? conjg(sbar[C - 1]) : mk<R>((R)0, (R)0);
-  const cplx<R> bX = scal(cA, -r2) + scal(cE, r6) + scal(cT, r3);
-  const cplx<R> bY = scal(cE, (R)-2 * r6) + scal(cT, r3);
-  const cplx<R> bZ = scal(cA, r2) + scal(cE, r6) + scal(cT, r3);
+  const cplx<R> bX = cE + cT - cA;
+  const cplx<R> bY = cT - scal(cE, (R)2);
+  const cplx<R> bZ = cA + cE + cT;
   auto G = [&](R a, R b) { return mk<R>(a + cDm * b, sDm * b); };  // a + D b
   cplx<R> Lam[3];
   Lam[0] = bY * G(s21, s12) - bX * G(s12, s21);
@@ -536,38 +566,51 @@ __device__ __forceinline__ void grad_sample_rev(const Cand<R>& s, const CandG<R>
   R gf = EQre * dkappa_f - J.y * dpsi_f;
   R gb = -J.y * dpsi_b;
   R gl = -J.y * dpsi_l;
-  // arm phases chi_a = pi f k.p_a and projections F+_a, Fx_a
+  // arm phases chi_a = pi f k.p_a and projections F+_a, Fx_a.  With rp = Re(K Lam_a E_a ap),
+  // rx = Re(K Lam_a E_a ax) and t1 = rp u.n + rx v.n, t2 = rp v.n - rx u.n:
+  //   beta:   rp dF+/dbeta + rx dFx/dbeta = -2 k.n t1,
+  //   lambda: rp dF+/dlambda + rx dFx/dlambda = -2 sin(beta) v.n t1 - 2 w.n t2;
+  // the per-arm terms are summed first and the candidate constants applied once
+  R hk = (R)0, hu = (R)0, hv = (R)0, bk = (R)0, lv = (R)0, lw = (R)0;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const R im = KLP[a].y;
-    gf -= im * pi * kp[a];
-    gb -= im * pi * fr * up[a];
-    gl -= im * pi * fr * sg.cb * vp[a];
-    const R rp = KLE[a].x * s.ap.x - KLE[a].y * s.ap.y;   // Re(K Lam_a E_a ap)
-    const R rx = KLE[a].x * s.ax.x - KLE[a].y * s.ax.y;   // Re(K Lam_a E_a ax)
-    const R dFp_b = -(R)2 * un[a] * kn[a], dFx_b = -(R)2 * kn[a] * vn[a];
-    const R dFp_l = -(R)2 * sg.sb * un[a] * vn[a] - (R)2 * vn[a] * wn[a];
-    const R dFx_l = -(R)2 * sg.sb * vn[a] * vn[a] + (R)2 * un[a] * wn[a];
-    gb += rp * dFp_b + rx * dFx_b;
-    gl += rp * dFp_l + rx * dFx_l;
+    hk += im * kp[a];
+    hu += im * up[a];
+    hv += im * vp[a];
+    const R rp = KLE[a].x * s.ap.x - KLE[a].y * s.ap.y;
+    const R rx = KLE[a].x * s.ax.x - KLE[a].y * s.ax.y;
+    const R t1 = rp * un[a] + rx * vn[a];
+    const R t2 = rp * vn[a] - rx * un[a];
+    bk += kn[a] * t1;
+    lv += vn[a] * t1;
+    lw += wn[a] * t2;
   }
-  // link sincs: the coefficient of s_rs in K Q is e_rs (K P_arm)
+  gf -= pi * hk;
+  gb -= (pi * fr) * hu + (R)2 * bk;
+  gl -= (pi * fr) * sg.cb * hv + (R)2 * (sg.sb * lv + lw);
+  // link sincs: the coefficient of s_rs in K Q is e_rs (K P_arm).  With r-, r+ the weights of
+  // the arm's links u = x (1 - k.n) and u = x (1 + k.n), their share is
+  //   f: pi L/c [(r- + r+) + k.n (r+ - r-)],  beta: x u.n (r+ - r-),  lambda: x cos(beta) v.n (r+ - r-)
   cplx<R> KP[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) KP[a] = K * P[a];
   const cplx<R> bXD = bX * D, bYD = bY * D, bZD = bZ * D;
   const cplx<R> el[6] = {bYD - bX, bY - bXD, bZD - bY, bZ - bYD, bXD - bZ, bX - bZD};
+  R ls = (R)0, lk = (R)0, lu = (R)0, lvn = (R)0;
 #pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int sgn = 0; sgn < 2; ++sgn) {
-      const int l = 2 * a + sgn;
-      const R pm = sgn ? (R)1 : (R)-1;  // u = x (1 + pm k.n)
-      const R rr = (el[l] * KP[a]).x * sd[l];
-      gf += rr * pi * Lr * ((R)1 + pm * kn[a]);
-      gb += rr * pm * x * un[a];
-      gl += rr * pm * x * sg.cb * vn[a];
-    }
+  for (int a = 0; a < 3; ++a) {
+    const R rm = (el[2 * a] * KP[a]).x * sd[2 * a];
+    const R rq = (el[2 * a + 1] * KP[a]).x * sd[2 * a + 1];
+    const R dr = rq - rm;
+    ls += rq + rm;
+    lk += kn[a] * dr;
+    lu += un[a] * dr;
+    lvn += vn[a] * dr;
+  }
+  gf += (pi * Lr) * (ls + lk);
+  gb += x * lu;
+  gl += (x * sg.cb) * lvn;
   // the delay inside Lam: d(KQ)/dD = sum_a (dLam_a/dD) K P_a, dD/df = -2 pi i (L/c) D
   const cplx<R> KcD = (scal(bY, s12) - scal(bX, s21)) * KP[0] + (scal(bZ, s23) - scal(bY, s32)) * KP[1] +
                       (scal(bX, s31) - scal(bZ, s13)) * KP[2];

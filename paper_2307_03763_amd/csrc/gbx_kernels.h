@@ -110,7 +110,8 @@ __device__ __forceinline__ void process_loglik(const BatchArgs& a, const DevWin&
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         const cplx<R> hv = buf[c * N + idx];
-        const double hre = (double)hv.x * scale, him = (double)hv.y * scale;
+        const double sc = scale * chan_norm(c);
+        const double hre = (double)hv.x * sc, him = (double)hv.y * sc;
         const int64_t g = off + (int64_t)c * w.W + kk;
         const double dre = a.d[2 * g], dim = a.d[2 * g + 1], wk = a.w[g];
         const double rre = dre - hre, rim = dim - him;
@@ -134,10 +135,11 @@ __device__ __forceinline__ void process_loglik(const BatchArgs& a, const DevWin&
 }
 
 // logL and its gradient for one template.  Forward: slow series, DFT, residual.  The
-// cotangent c_k = A T/(2N) w_k (d_k - h_k) replaces the template in LDS, an inverse DFT turns
-// it into the cotangent of every slow-series sample, and each lane contracts it with the
-// derivative of its samples (grad_sample_rev).  The amplitude and the three extrinsic angles
-// enter through closed forms; the carrier bin is held fixed.
+// cotangent c_k = A T/(2N) n_c w_k (d_k - h_k) (n_c the channel normalisation) replaces the
+// template in LDS, an inverse DFT turns it into the cotangent of every slow-series sample,
+// and each lane contracts it with the derivative of its samples (grad_sample_rev).  The
+// amplitude and the three extrinsic angles enter through closed forms; the carrier bin is
+// held fixed.
 template <class R, int N, int LPC, int C, int WPB>
 __device__ __forceinline__ void process_grad(const BatchArgs& a, const DevWin& w, int64_t row, bool active,
                                              int lane, cplx<R>* buf, double (*s_red)[16]) {
@@ -164,7 +166,8 @@ __device__ __forceinline__ void process_grad(const BatchArgs& a, const DevWin& w
       cplx<R> cot = mk<R>((R)0, (R)0);
       if (inw) {
         const cplx<R> hv = buf[c * N + idx];
-        const double hur = (double)hv.x * sc0, hui = (double)hv.y * sc0;
+        const double scu = sc0 * chan_norm(c), scn = scale * chan_norm(c);
+        const double hur = (double)hv.x * scu, hui = (double)hv.y * scu;
         const double hre = hur * s.amp, him = hui * s.amp;
         const int64_t g = off + (int64_t)c * w.W + kk;
         const double dre = a.d[2 * g], dim = a.d[2 * g + 1], wk = a.w[g];
@@ -172,7 +175,7 @@ __device__ __forceinline__ void process_grad(const BatchArgs& a, const DevWin& w
         v[0] += wk * (rre * rre + rim * rim);
         v[1] += wk * (dre * dre + dim * dim);
         v[2] += wk * (rre * hur + rim * hui);
-        cot = mk<R>((R)(scale * wk * rre), (R)(scale * wk * rim));
+        cot = mk<R>((R)(scn * wk * rre), (R)(scn * wk * rim));
       }
       buf[c * N + idx] = cot;
     }
@@ -283,8 +286,8 @@ __global__ void __launch_bounds__(WPB * 64) k_waveform(BatchArgs a) {
     for (int c = 0; c < C; ++c) {
       const cplx<R> hv = buf[c * N + idx];
       const int64_t g = (row * C + c) * N + i;
-      a.h_out[2 * g] = s.ok ? (double)hv.x * scale : nan;
-      a.h_out[2 * g + 1] = s.ok ? (double)hv.y * scale : nan;
+      a.h_out[2 * g] = s.ok ? (double)hv.x * (scale * chan_norm(c)) : nan;
+      a.h_out[2 * g + 1] = s.ok ? (double)hv.y * (scale * chan_norm(c)) : nan;
     }
   }
   if (lane == 0) a.first_bin[row] = s.q - N / 2;
