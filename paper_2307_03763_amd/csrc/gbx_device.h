@@ -283,10 +283,26 @@ __device__ __forceinline__ void slow_sample(const Cand<R>& s, const double* __re
   if (C == 3) out[C - 1] = K * (X + Y + Z);
 }
 
+// Synchronisation of the LPC lanes that share one template's LDS buffer.  A template wider
+// than a wave needs the workgroup barrier.  Within one wave, LDS operations complete in issue
+// order, so it is enough that the compiler moves no LDS access across the point (wave-scope
+// release and acquire fences around a wave barrier); the workgroup's other waves, which work
+// on other templates, are not held.
+template <int LPC>
+__device__ __forceinline__ void slot_sync() {
+  if (LPC > 64) {
+    __syncthreads();
+  } else {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
 // ------------------------------------------------------------------------------------
 // In-LDS Stockham FFT, radix 4 (plus one radix-2 pass when log2 N is odd), register-staged
-// in place: every pass reads all of a lane's elements, synchronises, butterflies, writes,
-// synchronises.  buf: [C][N] complex of one template; LPC lanes per template, E = N/LPC
+// in place: every pass reads all of a lane's elements, synchronises the template's lanes,
+// butterflies, writes, synchronises.  buf: [C][N] complex of one template; LPC lanes per template, E = N/LPC
 // elements per lane (E a multiple of 4).  DIR = -1 forward (e^{-2 pi i jm/N}), +1 inverse
 // (unnormalised).  tw[m] = e^{-2 pi i m / N}.
 template <class R, int N, int LPC, int C, int RADIX, int DIR>
@@ -302,7 +318,7 @@ __device__ __forceinline__ void stockham_pass(cplx<R>* buf, int lane, int Ns, co
 #pragma unroll
       for (int r = 0; r < RADIX; ++r) v[c][b][r] = buf[c * N + j + r * (N / RADIX)];
     }
-  __syncthreads();
+  slot_sync<LPC>();
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     const int j = lane + LPC * b;
@@ -335,7 +351,7 @@ __device__ __forceinline__ void stockham_pass(cplx<R>* buf, int lane, int Ns, co
       }
     }
   }
-  __syncthreads();
+  slot_sync<LPC>();
 }
 
 template <int N>

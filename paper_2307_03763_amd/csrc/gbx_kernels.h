@@ -87,7 +87,7 @@ __device__ __forceinline__ void template_to_lds(const Cand<R>& s, const BatchArg
 #pragma unroll
     for (int c = 0; c < C; ++c) buf[c * N + m] = o[c];
   }
-  __syncthreads();
+  slot_sync<LPC>();
   fft_lds<R, N, LPC, C, -1>(buf, lane, (const cplx<R>*)a.tw);
 }
 
@@ -131,7 +131,7 @@ __device__ __forceinline__ void process_loglik(const BatchArgs& a, const DevWin&
       a.comps[2 * row + 1] = s.ok ? acc[3] : nan;
     }
   }
-  __syncthreads();
+  slot_sync<LPC>();
 }
 
 // logL and its gradient for one template.  Forward: slow series, DFT, residual.  The
@@ -180,7 +180,7 @@ __device__ __forceinline__ void process_grad(const BatchArgs& a, const DevWin& w
       buf[c * N + idx] = cot;
     }
   }
-  __syncthreads();
+  slot_sync<LPC>();
   fft_lds<R, N, LPC, C, +1>(buf, lane, (const cplx<R>*)a.tw);
   GradAcc& ga = *reinterpret_cast<GradAcc*>(&v[3]);  // v[3..12]: per-sample accumulators
   const R* obR = (const R*)a.obR;
@@ -221,7 +221,7 @@ __device__ __forceinline__ void process_grad(const BatchArgs& a, const DevWin& w
       g[7] = -(apx * gui + apy * gur + axx * gvi + axy * gvr);
     }
   }
-  __syncthreads();
+  slot_sync<LPC>();
 }
 
 // Persistent batched kernel: workgroups take tiles from the plan's queue until it is empty.

@@ -12,6 +12,12 @@ using namespace gbx;
 #define VN(OO) VC(64, 16, OO), VC(128, 32, OO), VC(256, 64, OO), VC(512, 128, OO), VC(1024, 256, OO), \
                VC(64, 8, OO), VC(128, 16, OO), VC(256, 32, OO), VC(512, 64, OO), VC(1024, 128, OO)
 
-static const Variant kTable[] = {VN(1), VN(2)};
+// templates of 128 lanes (two waves) also in workgroups of two waves, one template each, so
+// that the template's barriers hold no other template's waves
+#define V2(NN, CC, OO) \
+  Variant { GB_MIXED, NN, 128, CC, 2, MODE_GRAD, OO, reinterpret_cast<const void*>(&k_batch<float, NN, 128, CC, 2, MODE_GRAD, OO>) }
+#define VW(OO) V2(512, 2, OO), V2(512, 3, OO), V2(1024, 2, OO), V2(1024, 3, OO)
+
+static const Variant kTable[] = {VN(1), VN(2), VW(1), VW(2)};
 
 extern "C" VariantList gbx_variants_mixed_grad() { return VariantList{kTable, (int)(sizeof kTable / sizeof kTable[0])}; }
