@@ -153,7 +153,7 @@ def _to_theta(x: np.ndarray) -> np.ndarray:
 def de_search(backend, boxes, rng: np.random.Generator, pop: int = 512, generations: int = 50,
               cr: float = 0.7, f_lo: float = 0.5, f_hi: float = 1.0, init: Optional[np.ndarray] = None,
               keep: int = 1, on_device: Optional[bool] = None, strategy: str = "best1", tol: float = 0.0,
-              check_every: int = 50):
+              check_every: int = 50, graph: bool = True):
     """Maximise rho over the seven non-amplitude parameters inside each window's Table I box.
 
     ``boxes`` is one PriorBox per window of the backend (or a single one for one window);
@@ -163,8 +163,10 @@ def de_search(backend, boxes, rng: np.random.Generator, pop: int = 512, generati
     (DE/rand/1/bin) or "best1" (DE/best/1/bin, SciPy's default: mutants around each window's
     best member).  ``tol`` > 0 stops a window once its population has converged in SciPy's
     sense, std(rho) <= tol |mean(rho)| (SciPy's default tol is 0.01), checked every
-    ``check_every`` generations; a stopped window keeps its population (on the device it also
-    leaves the batch).  Returns
+    ``check_every`` generations; a stopped window keeps its population (on the device the
+    converged windows leave the batch once a quarter of it has converged).  ``graph``: on the
+    device, replay each chunk of ``check_every`` generations from one captured HIP graph.
+    Returns
     (theta [n_win, keep, 8] of the best ``keep`` members with A = A_max, rho [n_win, keep],
     history [generations + 1, n_win] of the best rho per generation)."""
     lo, hi = _box_arrays(boxes)
@@ -178,7 +180,7 @@ def de_search(backend, boxes, rng: np.random.Generator, pop: int = 512, generati
         on_device = getattr(backend, "device_de", False)
     if on_device:
         x, s, history = _de_device(backend, lo, hi, rng, pop, generations, cr, f_lo, f_hi, init, strategy == "best1",
-                                   tol, check_every)
+                                   tol, check_every, graph)
         return _de_finish(backend, x, s, history, keep)
     x = lo[:, None, :] + (hi - lo)[:, None, :] * rng.random((n_win, pop, dim))
     if init is not None:
@@ -225,13 +227,24 @@ def _de_converged(s, tol: float) -> np.ndarray:
 
 
 def _de_device(backend, lo, hi, rng, pop, generations, cr, f_lo, f_hi, init, best1=False, tol=0.0,
-               check_every=50):
+               check_every=50, graph=True):
     """The DE generations with the population, scores and random draws in device memory: per
     generation one gb_de_trial, one gb_loglik of all trials and one gb_de_select, with no copy
-    to the host (the uniforms come from a torch generator seeded by ``rng``; F is drawn from
-    ``rng`` as in the host loop).  With tol > 0, every ``check_every`` generations the windows
-    whose population has converged leave the batch (their members are kept) and the rest run on
-    a plan of their own.  Returns (x, s, history) as NumPy arrays."""
+    to the host.
+
+    The generations run in chunks of ``check_every``. A chunk's uniforms come from a torch
+    generator seeded by ``rng`` and are drawn into fixed buffers before the chunk runs; its F
+    values (one per generation, from ``rng`` as in the host loop) are copied in one transfer.
+    gb_de_select writes each generation's best rho into the chunk's history rows. With
+    ``graph``, the chunk's launches are captured once in a HIP graph and every later chunk of the
+    same batch is one replay (the first chunk, and partial chunks, run eagerly); graph and eager
+    runs consume the same draws and give identical results.
+
+    With tol > 0, after every chunk the windows whose population has converged (std(rho) <= tol
+    |mean(rho)|) are noted. Once a quarter of the batch has converged (or all of it), those
+    windows leave the batch (their members are kept) and the rest run on a plan of their own,
+    with a new capture. Converged windows that stay in the batch until then keep evolving, which
+    greedy selection can only improve. Returns (x, s, history) as NumPy arrays."""
     torch, api = backend.torch, backend.api
     dev = torch.device("cuda")
     f64 = torch.float64
@@ -253,32 +266,68 @@ def _de_device(backend, lo, hi, rng, pop, generations, cr, f_lo, f_hi, init, bes
     best_idx = torch.zeros(n_win, dtype=torch.int32, device=dev)
     hist = torch.full((generations + 1, n_win), np.nan, dtype=f64, device=dev)
     hist[0] = api.gb_de_select(comps, x, s, x.clone(), best_idx=best_idx)
-    # the active windows' arrays (the whole batch until some window converges)
+    K = max(1, int(check_every))
+
+    def buffers(na):
+        return dict(ui=torch.empty((K, na, pop, 3), dtype=f64, device=dev),
+                    uc=torch.empty((K, na, pop, dim), dtype=f64, device=dev),
+                    uj=torch.empty((K, na, pop), dtype=f64, device=dev),
+                    F=torch.empty((K, na), dtype=f64, device=dev),
+                    best=torch.empty((K, na), dtype=f64, device=dev),
+                    tx=torch.empty((na, pop, dim), dtype=f64, device=dev),
+                    tth=torch.empty((na * pop, 8), dtype=f64, device=dev))
+
+    def chunk(B, k):
+        for j in range(k):
+            api.gb_de_trial(lo_a, hi_a, xa, B["ui"][j], B["uc"][j], B["uj"][j], B["F"][j], cr, REF_AMP, B["tx"],
+                            B["tth"], base=ba if best1 else None)
+            _, cj = plan_a.loglik(B["tth"], comps=True)
+            api.gb_de_select(cj, xa, sa, B["tx"], best=B["best"][j], best_idx=ba)
+
+    def capture(B):
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        gr = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gr, stream=side):
+            chunk(B, K)
+        torch.cuda.current_stream().wait_stream(side)
+        return gr
+
+    # the active windows' arrays (the whole batch until a compaction)
     act = torch.arange(n_win, device=dev)
     xa, sa, ba, lo_a, hi_a, plan_a, own_plan = x, s, best_idx, lo_t, hi_t, plan, False
-    trial_x = torch.empty_like(x)
-    trial_th = torch.empty((n_win * pop, 8), dtype=f64, device=dev)
-    F = torch.empty(n_win, dtype=f64, device=dev)
-    for g in range(1, generations + 1):
+    B, gr, eager_chunks, captures, replays = buffers(n_win), None, 0, 0, 0
+    g = 1
+    while g <= generations:
         na = len(act)
-        u_idx = torch.rand((na, pop, 3), generator=gen, dtype=f64, device=dev)
-        u_cross = torch.rand((na, pop, dim), generator=gen, dtype=f64, device=dev)
-        u_j = torch.rand((na, pop), generator=gen, dtype=f64, device=dev)
-        F.fill_(float(rng.uniform(f_lo, f_hi)))
-        api.gb_de_trial(lo_a, hi_a, xa, u_idx, u_cross, u_j, F[:na], cr, REF_AMP, trial_x[:na], trial_th[:na * pop],
-                        base=ba if best1 else None)
-        _, comps = plan_a.loglik(trial_th[:na * pop], comps=True)
-        hist[g, act] = api.gb_de_select(comps, xa, sa, trial_x[:na], best_idx=ba)
-        if tol > 0 and g % check_every == 0 and g < generations:
+        k = min(K, generations - g + 1)
+        B["ui"][:k].uniform_(generator=gen)
+        B["uc"][:k].uniform_(generator=gen)
+        B["uj"][:k].uniform_(generator=gen)
+        Fk = torch.as_tensor(rng.uniform(f_lo, f_hi, k), dtype=f64)
+        B["F"][:k].copy_(Fk[:, None].expand(k, na))
+        if graph and k == K and eager_chunks > 0:
+            if gr is None:
+                gr = capture(B)
+                captures += 1
+            gr.replay()
+            replays += 1
+        else:
+            chunk(B, k)
+            eager_chunks += 1
+        hist[g:g + k, act] = B["best"][:k]
+        g += k
+        if tol > 0 and g <= generations:
             m = sa.mean(dim=1)
             conv = torch.isfinite(m) & (sa.std(dim=1, unbiased=False) <= tol * m.abs())
             n_conv = int(conv.sum().item())
-            if n_conv:
+            if n_conv and (n_conv == na or 4 * n_conv >= na):
                 if xa is not x:                        # write the converged windows back
                     x[act[conv]] = xa[conv]
                     s[act[conv]] = sa[conv]
                 if own_plan:
                     plan_a.close()
+                gr = None
                 if n_conv == na:
                     act = act[:0]
                     break
@@ -290,6 +339,9 @@ def _de_device(backend, lo, hi, rng, pop, generations, cr, f_lo, f_hi, init, bes
                 act = act[keep_w]
                 lo_a, hi_a = lo_t[act].contiguous(), hi_t[act].contiguous()
                 plan_a, own_plan = backend._sub_plan(act.cpu().numpy(), pop, backend.pl), True
+                B = buffers(len(act))
+    gr = None
+    backend.de_chunks = dict(eager=eager_chunks, captures=captures, replays=replays)
     if len(act) and xa is not x:
         x[act] = xa
         s[act] = sa

@@ -140,3 +140,27 @@ def test_device_de_convergence_stop(oracle_lib):
             assert hist[-1, i] == hist[-100, i]
     assert np.allclose(rho[:, 0], hist[-1])
     be.close()
+
+
+def test_device_de_graph_matches_eager(oracle_lib):
+    """The device DE replayed from captured HIP graphs against the same DE launched eagerly. Both
+    consume the same draws, so populations, scores and the whole history must agree bit for bit,
+    over many chunk replays with eager host work (the convergence checks) between them,
+    compactions with re-captures, and a partial last chunk run eagerly."""
+    banner("device DE: HIP-graph chunks vs eager launches")
+    from tests.test_search_cpu import segments_workload
+    wl, seg = segments_workload(oracle_lib)
+    ctx = api.context_for(wl.T)
+    be = D.GpuBackend(ctx, wl.window_table(), dev(wl.data, torch.complex128), dev(wl.weights), api.GB_MIXED)
+    boxes = [wl.window_box(i) for i in range(wl.n_win)]
+    out, chunks = [], []
+    for graph in (True, False):
+        out.append(D.de_search(be, boxes, np.random.default_rng(5), pop=128, generations=205, keep=2, tol=0.01,
+                               check_every=10, graph=graph))
+        chunks.append(dict(be.de_chunks))
+    banner(f"  chunks with graphs: {chunks[0]}; eager: {chunks[1]}")
+    assert chunks[0]["replays"] >= 3 and chunks[0]["captures"] >= 1
+    assert chunks[1]["replays"] == 0 and chunks[1]["captures"] == 0
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
+    be.close()
