@@ -108,8 +108,8 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}, "
-              f"WORLD_SIZE={world}); multi-GPU sharding is described in DESIGN.md, not run.",
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE={world}); "
+              f"the library does not shard the likelihood path across GPUs.",
               flush=True)
         sys.exit(2)
 
@@ -156,7 +156,7 @@ def main():
     # ---------------------------------------------------------------- precision policy
     # SNR of the loudest injection of every window (FP64 components on the GPU); windows at or
     # below RHO_MIXED run in mixed precision, louder ones in FP64 (Sec. III G sampling needs
-    # logL differences to 1e-5; the mixed error grows like 6e-7 rho, see DESIGN.md)
+    # logL differences to 1e-5; the mixed error grows like 6e-7 rho)
     rho_w = window_snr(api, ctx, wl, d, w)
     prec_w = np.where(rho_w <= args.rho_mixed, api.GB_MIXED, api.GB_FP64)
     log(f"precision policy: rho <= {args.rho_mixed}: {int((prec_w == api.GB_MIXED).sum())} of {wl.n_win} windows mixed")
