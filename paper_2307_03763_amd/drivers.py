@@ -226,6 +226,11 @@ def _de_converged(s, tol: float) -> np.ndarray:
     return np.isfinite(m) & (s.std(axis=1) <= tol * np.abs(m))
 
 
+# Share of the device DE batch that must have converged before the converged windows leave it:
+# each compaction costs a new plan and a new graph capture, about one eager chunk.
+COMPACT_FRACTION = 0.25
+
+
 def _de_device(backend, lo, hi, rng, pop, generations, cr, f_lo, f_hi, init, best1=False, tol=0.0,
                check_every=50, graph=True):
     """The DE generations with the population, scores and random draws in device memory: per
@@ -243,8 +248,8 @@ def _de_device(backend, lo, hi, rng, pop, generations, cr, f_lo, f_hi, init, bes
     With tol > 0, after every chunk the windows whose population has converged (std(rho) <= tol
     |mean(rho)|) are noted. Once a quarter of the batch has converged (or all of it), those
     windows leave the batch (their members are kept) and the rest run on a plan of their own,
-    with a new capture. Converged windows that stay in the batch until then keep evolving, which
-    greedy selection can only improve. Returns (x, s, history) as NumPy arrays."""
+    with a new capture (COMPACT_FRACTION). Converged windows that stay in the batch until then
+    keep evolving, which greedy selection can only improve. Returns (x, s, history) as NumPy arrays."""
     torch, api = backend.torch, backend.api
     dev = torch.device("cuda")
     f64 = torch.float64
@@ -321,7 +326,7 @@ def _de_device(backend, lo, hi, rng, pop, generations, cr, f_lo, f_hi, init, bes
             m = sa.mean(dim=1)
             conv = torch.isfinite(m) & (sa.std(dim=1, unbiased=False) <= tol * m.abs())
             n_conv = int(conv.sum().item())
-            if n_conv and (n_conv == na or 4 * n_conv >= na):
+            if n_conv and (n_conv == na or n_conv >= COMPACT_FRACTION * na):
                 if xa is not x:                        # write the converged windows back
                     x[act[conv]] = xa[conv]
                     s[act[conv]] = sa[conv]
