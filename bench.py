@@ -1,8 +1,9 @@
 """Throughput of the batched Galactic-binary likelihood on one MI355X.
 
-One step = one pass of the hot path over the ragged batch: for every (N, C) group of windows
-(one persistent launch each) the Metropolis-Hastings stage (logL of every proposal, then the
-chain of every window) and the gradient of every candidate.  Inputs are synthetic and resident
+One step = one pass of the hot path over the ragged batch: the Metropolis-Hastings stage of
+every window in one call (logL of every proposal, one persistent launch per (N, C, precision)
+bucket, then the chain of every window in one launch) and the gradient of every candidate (one
+persistent launch per (N, C) group).  Inputs are synthetic and resident
 in HBM before the timed region.  Prints ONE JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--windows 256] [--cands 10000]
@@ -169,19 +170,30 @@ def main():
     E = lambda: torch.cuda.Event(enable_timing=True)
 
     def make_groups(prec_of_window, grad_prec_of_window):
-        """(plan for logL/MH, plan for gradients) per (N, C, precision) group; each plan is one
-        persistent launch over all of its windows."""
+        """The plans of one step and the per-group likelihood plans.
+
+        step: the MH stage of every window as one plan with per-window precision (one
+        persistent likelihood launch per (N, C, precision) bucket, then one chain launch over
+        all windows), followed by one gradient plan per (N, C, precision) group (one persistent
+        launch each, so that each is timed on its own). mh_groups: one plan per (N, C,
+        precision) group of the MH windows, used only to time each likelihood launch alone."""
+        tab = np.concatenate([table, np.asarray(prec_of_window, dtype=np.int64)[:, None]], axis=1)
+        p_all = api.Plan(ctx, tab, api.GB_PER_WINDOW)
+        p_all.prepare(d, w)
+        step = [(("mh", 0, 0, -1), list(range(wl.n_win)), p_all,
+                 torch.empty(wl.n_win, dtype=torch.int64, device="cuda"))]
+        mh_groups = []
         groups = {}
         for i, win in enumerate(wl.windows):
             groups.setdefault(("mh", win.N, win.C, int(prec_of_window[i])), []).append(i)
             groups.setdefault(("gr", win.N, win.C, int(grad_prec_of_window[i])), []).append(i)
-        out = []
         for key in sorted(groups, key=lambda k: (k[0], -k[1], -k[2], k[3])):
             idx = groups[key]
             p = api.Plan(ctx, table[idx], key[3])
             p.prepare(d, w)
-            out.append((key, idx, p, torch.empty(len(idx), dtype=torch.int64, device="cuda")))
-        return out
+            entry = (key, idx, p, None)
+            (step if key[0] == "gr" else mh_groups).append(entry)
+        return step, mh_groups
 
     def run_steps(groups, steps, warmup, region=None):
         def one(ev):
@@ -221,44 +233,38 @@ def main():
     # adaptive ragged (the headline); gradients run in mixed precision (the FP64 gradient is
     # switched off in this version of the library)
     grad_prec = np.full(wl.n_win, api.GB_MIXED)
-    groups_ad = make_groups(prec_w, grad_prec)
+    step_ad, mh_ad = make_groups(prec_w, grad_prec)
     region = TimedRegion()
-    ms_ad, per_ad = run_steps(groups_ad, args.steps, args.warmup, region)
-    # the likelihood kernel alone for every MH group (an MH stage is that kernel plus the
+    ms_ad, per_ad = run_steps(step_ad, args.steps, args.warmup, region)
+    # the likelihood kernel alone for every MH group (the MH stage is those kernels plus the
     # chain kernel): the same launches through gb_loglik, still inside the profiled region
-    kb_ms = per_ad.copy()
-    for j, (key, idx, p, _) in enumerate(groups_ad):
-        if key[0] != "mh":
-            continue
+    kern = [(key, idx, float(t)) for (key, idx, _, _), t in zip(step_ad, per_ad) if key[0] == "gr"]
+    for key, idx, p, _ in mh_ad:
         ev = [[E(), E()] for _ in range(args.steps)]
         for s_ in range(args.steps):
             ev[s_][0].record(stream)
             api.gb_loglik(p.handle, d, w, th, logL, None, stream)
             ev[s_][1].record(stream)
         torch.cuda.synchronize()
-        kb_ms[j] = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+        kern.append((key, idx, float(np.mean([a.elapsed_time(b) for a, b in ev]))))
     region.pause()
-    adaptive = summary(groups_ad, ms_ad, per_ad)
-    adaptive["chain_ms_per_step"] = round(float(sum(per_ad[j] - kb_ms[j] for j, g in enumerate(groups_ad)
-                                                    if g[0][0] == "mh")), 4)
+    adaptive = summary(step_ad, ms_ad, per_ad)
     log(f"adaptive ragged: {ms_ad:.2f} ms/step {adaptive}")
 
     # mixed precision everywhere
     allmix = np.full(wl.n_win, api.GB_MIXED)
-    groups_mx = make_groups(allmix, allmix)
-    ms_mx, per_mx = run_steps(groups_mx, args.steps, args.warmup)
-    mixed = summary(groups_mx, ms_mx, per_mx)
+    step_mx, _ = make_groups(allmix, allmix)
+    ms_mx, per_mx = run_steps(step_mx, args.steps, args.warmup)
+    mixed = summary(step_mx, ms_mx, per_mx)
     log(f"mixed ragged: {ms_mx:.2f} ms/step {mixed}")
     logl_mixed = logL.cpu().numpy().copy()
 
     # dominant kernel of the headline step (largest k_batch time per step)
-    j_dom = int(np.argmax(kb_ms))
-    key, idx, _, _ = groups_ad[j_dom]
+    key, idx, dur_ms = max(kern, key=lambda e: e[2])
     kind, kN, kC, kP = key
     n_dom = int(sum(wl.n_cand[i] for i in idx))
     is_grad = kind == "gr"
     fl = sum(int(wl.n_cand[i]) * flops_per_eval(kN, kC, min(wl.windows[i].W, kN), is_grad) for i in idx)
-    dur_ms = float(kb_ms[j_dom])
     achieved_tf = fl / (dur_ms * 1e-3) / 1e12
     kname = tuned_kernel_name(tune, kP, is_grad, kN, kC)
     roofline = {"bound": "alu", "achieved": round(achieved_tf, 3), "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
@@ -325,8 +331,9 @@ def main():
                    "precision": f"adaptive: mixed (FP64 phase and accumulation, FP32 response and DFT) for "
                                 f"windows with injected SNR <= {args.rho_mixed}, FP64 otherwise",
                    "mixed_windows": int((prec_w == api.GB_MIXED).sum()),
-                   "step": "per (N, C, precision) group one persistent launch: MH stage (logL of all "
-                           "proposals + chains), then all gradients"},
+                   "step": "MH stage of all windows in one call (one persistent logL launch per (N, C, "
+                           "precision) bucket, then one chain launch over all windows), then the "
+                           "gradients, one persistent launch per (N, C) group"},
         "logl_evals_per_s": adaptive["logl_evals_per_s"],
         "grad_evals_per_s": adaptive["grad_evals_per_s"],
         "mixed_everywhere": mixed,

@@ -226,6 +226,25 @@ def _de_converged(s, tol: float) -> np.ndarray:
     return np.isfinite(m) & (s.std(axis=1) <= tol * np.abs(m))
 
 
+def _capture_graph(torch, gr, stream, body):
+    """Record body() into the HIP graph gr on stream.
+
+    The capture runs in relaxed mode, so no call outside the captured stream can invalidate it.
+    The cyclic garbage collector is held off while it runs: torch.cuda.graph collects garbage
+    just before the capture starts, and a later collection could otherwise destroy an
+    unreferenced plan or context inside the capture, whose device frees would interfere with
+    it."""
+    import gc
+    enabled = gc.isenabled()
+    gc.disable()
+    try:
+        with torch.cuda.graph(gr, stream=stream, capture_error_mode="relaxed"):
+            body()
+    finally:
+        if enabled:
+            gc.enable()
+
+
 # Share of the device DE batch that must have converged before the converged windows leave it:
 # each compaction costs a new plan and a new graph capture, about one eager chunk.
 COMPACT_FRACTION = 0.25
@@ -293,8 +312,7 @@ def _de_device(backend, lo, hi, rng, pop, generations, cr, f_lo, f_hi, init, bes
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
         gr = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(gr, stream=side):
-            chunk(B, K)
+        _capture_graph(torch, gr, side, lambda: chunk(B, K))
         torch.cuda.current_stream().wait_stream(side)
         return gr
 
@@ -542,8 +560,7 @@ class PosteriorStage:
         self.graph = torch.cuda.CUDAGraph()
         if self.gen is not torch.cuda.default_generators[torch.cuda.current_device()]:
             self.graph.register_generator_state(self.gen)   # the default one is registered by torch
-        with torch.cuda.graph(self.graph, stream=s):
-            self._body(s)
+        _capture_graph(torch, self.graph, s, lambda: self._body(s))
         torch.cuda.synchronize()
 
     def replay(self):

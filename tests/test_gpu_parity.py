@@ -7,6 +7,7 @@ max(1, |difference|)) grow like rho of the loudest source; mixed is used for rho
 where they stay below 1e-5, and the per-window adaptive plan meets 1e-5 everywhere.
 """
 
+import gc
 import math
 
 import numpy as np
@@ -267,8 +268,15 @@ def test_graph_capture_replays(c3_small):
     torch.cuda.current_stream().wait_stream(s)
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g, stream=s):
-        api.gb_loglik(plan.handle, d, w, th, out, None, s)
+    # the default (global) capture mode, so that any call the library makes which a capture
+    # does not allow fails here; the garbage collector is held off so that it cannot destroy
+    # an unrelated library object inside the capture
+    gc.disable()
+    try:
+        with torch.cuda.graph(g, stream=s):
+            api.gb_loglik(plan.handle, d, w, th, out, None, s)
+    finally:
+        gc.enable()
     for k in range(3):
         out.zero_()
         junk = torch.randn(1000, device="cuda").sum()   # eager work between replays
