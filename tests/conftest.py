@@ -1,3 +1,4 @@
+import gc
 import os
 import sys
 
@@ -19,3 +20,12 @@ def oracle_lib():
     oracle._lib = None
     oracle._load()
     return oracle
+
+
+@pytest.fixture(autouse=True)
+def _collect_garbage_between_tests():
+    """Destroy unreferenced library objects (plans and contexts, whose destructors free device
+    memory) between tests, instead of whenever the cyclic collector next runs, which could be
+    inside a later test's HIP-graph capture."""
+    yield
+    gc.collect()
