@@ -348,9 +348,9 @@ def _de_device(backend, lo, hi, rng, pop, generations, cr, f_lo, f_hi, init, bes
                 if xa is not x:                        # write the converged windows back
                     x[act[conv]] = xa[conv]
                     s[act[conv]] = sa[conv]
+                gr = None                              # the graph refers to the plan and buffers
                 if own_plan:
                     plan_a.close()
-                gr = None
                 if n_conv == na:
                     act = act[:0]
                     break
@@ -364,6 +364,7 @@ def _de_device(backend, lo, hi, rng, pop, generations, cr, f_lo, f_hi, init, bes
                 plan_a, own_plan = backend._sub_plan(act.cpu().numpy(), pop, backend.pl), True
                 B = buffers(len(act))
     gr = None
+    # how the chunks ran (eagerly, captured, replayed), for tests and diagnostics
     backend.de_chunks = dict(eager=eager_chunks, captures=captures, replays=replays)
     if len(act) and xa is not x:
         x[act] = xa
