@@ -300,11 +300,11 @@ __device__ __forceinline__ void slot_sync() {
 }
 
 // ------------------------------------------------------------------------------------
-// In-LDS Stockham FFT, radix 4 (plus one radix-2 pass when log2 N is odd), register-staged
-// in place: every pass reads all of a lane's elements, synchronises the template's lanes,
-// butterflies, writes, synchronises.  buf: [C][N] complex of one template; LPC lanes per template, E = N/LPC
-// elements per lane (E a multiple of 4).  DIR = -1 forward (e^{-2 pi i jm/N}), +1 inverse
-// (unnormalised).  tw[m] = e^{-2 pi i m / N}.
+// In-LDS Stockham FFT, radix 8, 4 and 2 (fft_lds picks the passes), register-staged in place:
+// every pass reads all of a lane's elements, synchronises the template's lanes, butterflies,
+// writes, synchronises.  buf: [C][N] complex of one template; LPC lanes per template, E = N/LPC
+// elements per lane (E a multiple of the radix).  DIR = -1 forward (e^{-2 pi i jm/N}), +1
+// inverse (unnormalised).  tw[m] = e^{-2 pi i m / N}.
 template <class R, int N, int LPC, int C, int RADIX, int DIR>
 __device__ __forceinline__ void stockham_pass(cplx<R>* buf, int lane, int Ns, const cplx<R>* __restrict__ tw) {
   constexpr int E = N / LPC;
@@ -340,7 +340,7 @@ __device__ __forceinline__ void stockham_pass(cplx<R>* buf, int lane, int Ns, co
       if (RADIX == 2) {
         buf[c * N + base] = a[0] + a[1];
         buf[c * N + base + Ns] = a[0] - a[1];
-      } else {
+      } else if (RADIX == 4) {
         const cplx<R> s0 = a[0] + a[2], d0 = a[0] - a[2];
         const cplx<R> s1 = a[1] + a[3], d1 = a[1] - a[3];
         const cplx<R> rot = (DIR < 0) ? mul_mi(d1) : mul_i(d1);
@@ -348,6 +348,26 @@ __device__ __forceinline__ void stockham_pass(cplx<R>* buf, int lane, int Ns, co
         buf[c * N + base + Ns] = d0 + rot;
         buf[c * N + base + 2 * Ns] = s0 - s1;
         buf[c * N + base + 3 * Ns] = d0 - rot;
+      } else {
+        // 8-point DFT: 4-point DFTs of the even and odd elements, combined with w8^q
+        // (w8 = e^{DIR 2 pi i / 8}): X_q = E_q + w8^q O_q, X_{q+4} = E_q - w8^q O_q
+        auto rot4 = [](cplx<R> z) { return (DIR < 0) ? mul_mi(z) : mul_i(z); };
+        const cplx<R> e0 = a[0] + a[4], e1 = a[0] - a[4], e2 = a[2] + a[6], e3 = rot4(a[2] - a[6]);
+        const cplx<R> o0 = a[1] + a[5], o1 = a[1] - a[5], o2 = a[3] + a[7], o3 = rot4(a[3] - a[7]);
+        const cplx<R> E0 = e0 + e2, E1 = e1 + e3, E2 = e0 - e2, E3 = e1 - e3;
+        const cplx<R> O0 = o0 + o2, O1 = o1 + o3, O2 = o0 - o2, O3 = o1 - o3;
+        const R h = (R)0.70710678118654752440;
+        const cplx<R> W1 = scal(O1 + rot4(O1), h);             // w8 O1 = (1 -+ i) O1 / sqrt2
+        const cplx<R> W2 = rot4(O2);                             // w8^2 = -+ i
+        const cplx<R> W3 = scal(rot4(O3) - O3, h);             // w8^3 = (-1 -+ i) / sqrt2
+        buf[c * N + base] = E0 + O0;
+        buf[c * N + base + Ns] = E1 + W1;
+        buf[c * N + base + 2 * Ns] = E2 + W2;
+        buf[c * N + base + 3 * Ns] = E3 + W3;
+        buf[c * N + base + 4 * Ns] = E0 - O0;
+        buf[c * N + base + 5 * Ns] = E1 - W1;
+        buf[c * N + base + 6 * Ns] = E2 - W2;
+        buf[c * N + base + 7 * Ns] = E3 - W3;
       }
     }
   }
@@ -363,18 +383,28 @@ struct Log2<1> {
   static constexpr int v = 0;
 };
 
+// Passes: radix 8 as often as it fits when a lane holds 8 elements (fewer LDS round trips and
+// twiddle products per element), then radix 4, and one radix-2 pass when an odd power of two
+// remains.  The mixed-radix Stockham indexing takes the radices in any order.
 template <class R, int N, int LPC, int C, int DIR>
 __device__ __forceinline__ void fft_lds(cplx<R>* buf, int lane, const cplx<R>* __restrict__ tw) {
   constexpr int LG = Log2<N>::v;
+  constexpr int N8 = (N / LPC) % 8 == 0 ? LG / 3 : 0;   // radix-8 passes
+  constexpr int REM = LG - 3 * N8;                     // log2 N left for radix 4 and 2
   int Ns = 1;
-  if (LG & 1) {
+  if (REM & 1) {
     stockham_pass<R, N, LPC, C, 2, DIR>(buf, lane, 1, tw);
     Ns = 2;
   }
 #pragma unroll
-  for (int p = 0; p < LG / 2; ++p) {
+  for (int p = 0; p < REM / 2; ++p) {
     stockham_pass<R, N, LPC, C, 4, DIR>(buf, lane, Ns, tw);
     Ns *= 4;
+  }
+#pragma unroll
+  for (int p = 0; p < N8; ++p) {
+    stockham_pass<R, N, LPC, C, 8, DIR>(buf, lane, Ns, tw);
+    Ns *= 8;
   }
 }
 
