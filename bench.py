@@ -651,7 +651,7 @@ def pipeline_leg(segments, log, precision: str = "mixed", catalogue=None, noise:
     (``noise``="psd" uses the true PSD); mixed gradient, the
     likelihood in ``precision``), the residual, and the annealed posterior (6 x 10,000) of every
     recovered source, batched, its likelihood in ``precision`` too.  Wall-clock seconds per
-    phase (host work included); recovered sources scored with the match metric of Sec. V
+    phase (host work included); recovered sources scored with the match metric of Sec. IV
     (delta < 0.3 against the nearest injected sources) and injected sources counted by their
     optimal SNR in their segment's window."""
     import numpy as np

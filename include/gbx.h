@@ -101,6 +101,13 @@ gb_status gb_plan_create(gb_ctx* ctx, const gb_window* windows, int n_win,
                          gb_precision precision, gb_plan** plan);
 void gb_plan_destroy(gb_plan* plan);
 
+/* Sizes a plan's calls read and write (host outputs; any may be NULL): rows = the largest
+ * cand_off + n_cand (the length of theta's first axis and of the per-candidate outputs),
+ * n_win = the number of windows (length of gb_mh_step's n_accept), data_len = the largest
+ * data_off + C W (elements of d and w the plan reads).  For callers that check their arrays
+ * before a call: the library cannot, as it receives raw pointers.  GB_EINVAL: null plan. */
+gb_status gb_plan_info(const gb_plan* plan, int64_t* rows, int* n_win, int64_t* data_len);
+
 /* <d|d> of every window (sum over channels and bins of w |d|^2), kept in the plan.  Must be
  * called after the data or weights change and before gb_loglik / gb_loglik_grad /
  * gb_mh_step, which reject other d, w pointers than the prepared ones.

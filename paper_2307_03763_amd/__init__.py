@@ -5,4 +5,4 @@ workloads) must stay importable without the HIP library, and the binding
 (``api``) loads ``libgbx.so`` only when first used and fails loudly if it is absent.
 """
 
-__all__ = ["api", "inputs", "torch_ops", "drivers"]
+__all__ = ["api", "inputs", "drivers"]

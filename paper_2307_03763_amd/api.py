@@ -22,7 +22,7 @@ GB_FP64, GB_MIXED, GB_PER_WINDOW = 0, 1, 2
 PRECISION = {"fp64": GB_FP64, "mixed": GB_MIXED, "per_window": GB_PER_WINDOW}
 
 EXPORTS = ("gb_create", "gb_destroy", "gb_last_error", "gb_waveform", "gb_plan_create",
-           "gb_plan_destroy", "gb_window_prepare", "gb_loglik", "gb_loglik_grad", "gb_mh_step",
+           "gb_plan_destroy", "gb_plan_info", "gb_window_prepare", "gb_loglik", "gb_loglik_grad", "gb_mh_step",
            "gb_autotune", "gb_select_variant", "gb_fisher", "gb_kde_logpdf", "gb_add_templates",
            "gb_noise_estimate", "gb_de_trial", "gb_de_select")
 
@@ -69,6 +69,9 @@ def lib():
         L.gb_plan_create.restype = st
         L.gb_plan_destroy.argtypes = [_vp]
         L.gb_plan_destroy.restype = None
+        L.gb_plan_info.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int),
+                                   ctypes.POINTER(ctypes.c_int64)]
+        L.gb_plan_info.restype = st
         L.gb_window_prepare.argtypes = [_vp, _vp, _vp, _vp]
         L.gb_window_prepare.restype = st
         L.gb_loglik.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
@@ -137,6 +140,8 @@ def gb_destroy(ctx: int):
 
 def gb_waveform(ctx: int, theta: torch.Tensor, N: int, C: int, precision: int = GB_FP64, stream=None):
     """Templates [B, C, N] complex128 and first bins [B] int64 (see include/gbx.h)."""
+    if theta.dim() != 2 or theta.shape[1] != 8:
+        raise ValueError(f"theta must be [B, 8], got {list(theta.shape)}")
     B = theta.shape[0]
     h = torch.empty((B, C, N), dtype=torch.complex128, device=theta.device)
     fb = torch.empty((B,), dtype=torch.int64, device=theta.device)
@@ -166,26 +171,78 @@ def gb_plan_destroy(plan: int):
     lib().gb_plan_destroy(plan)
 
 
+def gb_plan_info(plan: int):
+    """(rows, n_win, data_len) of a plan: the sizes its calls read and write."""
+    rows, n_win, data_len = ctypes.c_int64(), ctypes.c_int(), ctypes.c_int64()
+    _check(lib().gb_plan_info(plan, ctypes.byref(rows), ctypes.byref(n_win), ctypes.byref(data_len)), "gb_plan_info")
+    return rows.value, n_win.value, data_len.value
+
+
+def _data_len(wins) -> int:
+    """Elements of d and w that a window list reads: the largest data_off + C W."""
+    return max((int(w.data_off) + int(w.C) * int(w.W) for w in wins), default=0)
+
+
+def _check_len(t: torch.Tensor, n: int, name: str):
+    """The kernels index raw pointers: a tensor shorter than what the call reads or writes would
+    be an out-of-bounds device access, so it is refused before any launch."""
+    if t.numel() < n:
+        raise ValueError(f"{name} has {t.numel()} elements; the call reads or writes {n}")
+
+
+def _check_rows(t: torch.Tensor, rows: int, width: int, name: str):
+    if width == 1:
+        ok = t.dim() == 1 and t.shape[0] >= rows
+    else:
+        ok = t.dim() == 2 and t.shape[1] == width and t.shape[0] >= rows
+    if not ok:
+        shape = f"[>= {rows}]" if width == 1 else f"[>= {rows}, {width}]"
+        raise ValueError(f"{name} must be {shape}, got {list(t.shape)}")
+
+
+def _check_data(plan: int, d: torch.Tensor, w: torch.Tensor):
+    _, _, n = gb_plan_info(plan)
+    _check_len(_real_view(d), 2 * n, "d (as float64 pairs)")
+    _check_len(w, n, "w")
+
+
+def _check_cand(plan: int, theta: torch.Tensor, outs):
+    rows, _, _ = gb_plan_info(plan)
+    _check_rows(theta, rows, 8, "theta")
+    for t, width, name in outs:
+        if t is not None:
+            _check_rows(t, rows, width, name)
+
+
 def gb_window_prepare(plan: int, d: torch.Tensor, w: torch.Tensor, stream=None):
+    _check_data(plan, d, w)
     _check(lib().gb_window_prepare(plan, _dev(_real_view(d), torch.float64, "d"),
                                    _dev(w, torch.float64, "w"), _stream(stream)), "gb_window_prepare")
 
 
 def gb_loglik(plan: int, d, w, theta, logL, comps=None, stream=None):
-    _check(lib().gb_loglik(plan, _real_view(d).data_ptr(), w.data_ptr(), _dev(theta, torch.float64, "theta"),
+    _check_data(plan, d, w)
+    _check_cand(plan, theta, [(logL, 1, "logL"), (comps, 2, "comps")])
+    _check(lib().gb_loglik(plan, _dev(_real_view(d), torch.float64, "d"), _dev(w, torch.float64, "w"), _dev(theta, torch.float64, "theta"),
                            _dev(logL, torch.float64, "logL"),
                            None if comps is None else _dev(comps, torch.float64, "comps"),
                            _stream(stream)), "gb_loglik")
 
 
 def gb_loglik_grad(plan: int, d, w, theta, logL, grad, stream=None):
-    _check(lib().gb_loglik_grad(plan, _real_view(d).data_ptr(), w.data_ptr(),
+    _check_data(plan, d, w)
+    _check_cand(plan, theta, [(logL, 1, "logL"), (grad, 8, "grad")])
+    _check(lib().gb_loglik_grad(plan, _dev(_real_view(d), torch.float64, "d"), _dev(w, torch.float64, "w"),
                                 _dev(theta, torch.float64, "theta"), _dev(logL, torch.float64, "logL"),
                                 _dev(grad, torch.float64, "grad"), _stream(stream)), "gb_loglik_grad")
 
 
 def gb_mh_step(plan: int, d, w, theta, log_g, u, temperature: float, logL, chain, n_accept, stream=None):
-    _check(lib().gb_mh_step(plan, _real_view(d).data_ptr(), w.data_ptr(), _dev(theta, torch.float64, "theta"),
+    _check_data(plan, d, w)
+    _check_cand(plan, theta, [(log_g, 1, "log_g"), (u, 1, "u"), (logL, 1, "logL"), (chain, 1, "chain")])
+    _, n_win, _ = gb_plan_info(plan)
+    _check_rows(n_accept, n_win, 1, "n_accept")
+    _check(lib().gb_mh_step(plan, _dev(_real_view(d), torch.float64, "d"), _dev(w, torch.float64, "w"), _dev(theta, torch.float64, "theta"),
                             _dev(log_g, torch.float64, "log_g"), _dev(u, torch.float64, "u"),
                             float(temperature), _dev(logL, torch.float64, "logL"),
                             _dev(chain, torch.int32, "chain"), _dev(n_accept, torch.int64, "n_accept"),
@@ -208,8 +265,13 @@ def gb_fisher(ctx: int, theta: torch.Tensor, steps: torch.Tensor, table, w: torc
     """Fisher matrices [n, 8, 8] of the sources theta [n, 8] in Table I coordinates; table: one
     window row per source (as Workload.window_table)."""
     n = theta.shape[0]
-    F = torch.empty((n, 8, 8), dtype=torch.float64, device=theta.device)
     wins = windows_array(table)
+    if len(wins) != n:
+        raise ValueError("gb_fisher: one window row per source")
+    _check_rows(theta, n, 8, "theta")
+    _check_rows(steps, n, 8, "steps")
+    _check_len(w, _data_len(wins), "w")
+    F = torch.empty((n, 8, 8), dtype=torch.float64, device=theta.device)
     _check(lib().gb_fisher(ctx, _dev(theta, torch.float64, "theta"), _dev(steps, torch.float64, "steps"), n, wins,
                            _dev(w, torch.float64, "w"), _dev(F, torch.float64, "F"), _stream(stream)), "gb_fisher")
     return F
@@ -238,8 +300,10 @@ def gb_noise_estimate(table, d: torch.Tensor, T: float, w: Optional[torch.Tensor
     and the weights 4 / (T S) written into w (a copy of d's layout, new unless given).  Returns
     (w, S [n_win, 3])."""
     wins = windows_array(table)
+    _check_len(d, _data_len(wins), "d")
     if w is None:
         w = torch.zeros(d.shape, dtype=torch.float64, device=d.device)
+    _check_len(w, _data_len(wins), "w")
     S = torch.zeros((len(wins), 3), dtype=torch.float64, device=d.device)
     _check(lib().gb_noise_estimate(wins, len(wins), _dev(d, torch.complex128, "d"), float(T),
                                    _dev(w, torch.float64, "w"), _dev(S, torch.float64, "S"), _stream(stream)),
@@ -303,6 +367,11 @@ def gb_add_templates(ctx: int, table, theta: torch.Tensor, src_win, sign: float,
     if d_out is None:
         d_out = torch.empty_like(d_in)
     n_src = int(len(sw))
+    n = _data_len(wins)
+    _check_len(d_in, n, "d_in")
+    _check_len(d_out, n, "d_out")
+    if n_src:
+        _check_rows(theta, n_src, 8, "theta")
     th = theta if n_src else torch.zeros((1, 8), dtype=torch.float64, device=d_in.device)
     _check(lib().gb_add_templates(ctx, wins, len(wins), _dev(th, torch.float64, "theta"),
                                   sw.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), n_src, float(sign),

@@ -421,6 +421,18 @@ extern "C" gb_status gb_plan_create(gb_ctx* c, const gb_window* windows, int n_w
   return GB_OK;
 }
 
+extern "C" gb_status gb_plan_info(const gb_plan* p, int64_t* rows, int* n_win, int64_t* data_len) {
+  if (!p) return fail(GB_EINVAL, "gb_plan_info: null plan");
+  if (rows) *rows = p->rows;
+  if (n_win) *n_win = (int)p->wins.size();
+  if (data_len) {
+    int64_t m = 0;
+    for (const gb_window& w : p->wins) m = std::max(m, w.data_off + (int64_t)w.C * w.W);
+    *data_len = m;
+  }
+  return GB_OK;
+}
+
 extern "C" gb_status gb_window_prepare(gb_plan* p, const double* d, const double* w, void* stream) {
   if (!p) return fail(GB_EINVAL, "gb_window_prepare: null plan");
   if (p->wins.empty()) {
@@ -444,14 +456,18 @@ static gb_status run_batch(gb_plan* p, int mode, const double* d, const double* 
   if (d != p->prep_d || w != p->prep_w)
     return fail(GB_EINVAL, "%s: data/weights differ from the ones passed to gb_window_prepare", who);
   if (mode == MODE_GRAD && !grad) return fail(GB_EINVAL, "%s: null gradient array", who);
-  for (Bucket& b : p->buckets) {
-    if (b.n_tiles == 0) continue;
-    const Variant* v = b.v[mode];
-    if (!v && mode == MODE_GRAD && b.prec == GB_FP64)
+  // every bucket must have a kernel before any is launched, so a refused call writes nothing
+  for (const Bucket& b : p->buckets) {
+    if (b.n_tiles == 0 || b.v[mode]) continue;
+    if (mode == MODE_GRAD && b.prec == GB_FP64)
       return fail(GB_EUNSUPPORTED,
                   "%s: the FP64 gradient is switched off (its kernels faulted on the GPU; cause not yet known); "
                   "use GB_MIXED", who);
-    if (!v) return fail(GB_EUNSUPPORTED, "%s: no kernel variant for N=%d C=%d", who, b.N, b.C);
+    return fail(GB_EUNSUPPORTED, "%s: no kernel variant for N=%d C=%d", who, b.N, b.C);
+  }
+  for (Bucket& b : p->buckets) {
+    if (b.n_tiles == 0) continue;
+    const Variant* v = b.v[mode];
     BatchArgs a = base_args(p->ctx, b.N, b.prec);
     a.wins = p->d_wins;
     a.tiles = b.d_tiles;

@@ -5,7 +5,8 @@
   amplitude, every generation of every window is scored in one batched likelihood call by the
   SNR rho = <d|h> / sqrt(<h|h>) (Sec. III SNR equation, independent of the amplitude), and the
   kept members of each window get A_max = A <d|h> / <h|h> (Sec. III amplitude equation).
-  Mutation is DE/rand/1/bin with a scale factor dithered per generation.
+  Mutation is DE/best/1/bin by default (SciPy's default strategy: mutants around each window's
+  best member), or DE/rand/1/bin, with a scale factor dithered per generation.
 * ``polish`` -- refinement of many starting points at once by quasi-Newton (BFGS) ascent on
   logL: per iteration one batched gradient call, then one batched line search (all trial step
   lengths of all starts in one likelihood call).
@@ -1109,12 +1110,12 @@ def posterior_batch(ctx, table, T: float, d_residual, w, sources, seg_rows, boxe
 
 
 def match_delta(ctx, table, T: float, w, recovered, rec_rows, injected, n_near: int = 3) -> np.ndarray:
-    """Scaled error of Sec. V, delta = <s_rec - s_inj | s_rec - s_inj> / <s_rec | s_rec>, of every
+    """Scaled error of Sec. IV (matching recovered signals), delta = <s_rec - s_inj | s_rec - s_inj> / <s_rec | s_rec>, of every
     recovered source against the ``n_near`` injected sources nearest in frequency, in the
     recovered source's window; returns the smallest delta of each (inf with no injected source),
     the index of the injected source that gives it (-1 with none), and the largest overlap
     O = <s_rec | s_inj> / sqrt(<s_rec | s_rec> <s_inj | s_inj>) over the same candidates (the
-    other match metric of Sec. V; -inf with none).
+    other match metric of Sec. IV; -inf with none).
     One window per (recovered, injected) pair holds the injected template as data, so the
     likelihood kernel's components give delta = -2 logL / <h|h>."""
     import torch

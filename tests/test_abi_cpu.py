@@ -46,6 +46,7 @@ def test_argument_validation_without_device():
     assert L.gb_loglik_grad(None, None, None, None, None, None, None) == api.GB_EINVAL
     assert L.gb_mh_step(None, None, None, None, None, None, 1.0, None, None, None, None) == api.GB_EINVAL
     assert L.gb_window_prepare(None, None, None, None) == api.GB_EINVAL
+    assert L.gb_plan_info(None, None, None, None) == api.GB_EINVAL
 
 
 def test_struct_layouts_match_header():
@@ -53,3 +54,47 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(api.gb_config) == 32
     assert ctypes.sizeof(api.gb_window) == 48
     assert api.gb_window.data_off.offset == 24 and api.gb_window.n_cand.offset == 40
+
+
+class _NoLaunch:
+    """Stands in for the library: any call other than the size query fails the test."""
+
+    def __getattr__(self, name):
+        def call(*args):
+            raise AssertionError(f"{name} was called although an argument had the wrong size")
+        return call
+
+
+def test_binding_refuses_missized_tensors_before_any_call(monkeypatch):
+    """The kernels index raw pointers, so the binding checks every tensor against the plan's
+    rows, window count and data length before it calls the library (here with a stub library
+    that fails the test when reached, and host tensors: the size checks come first)."""
+    import torch
+    from paper_2307_03763_amd import api
+    rows, n_win, n = 10, 2, 100
+    monkeypatch.setattr(api, "gb_plan_info", lambda plan: (rows, n_win, n))
+    monkeypatch.setattr(api, "lib", lambda: _NoLaunch())
+    f64 = torch.float64
+    d = torch.zeros(n, dtype=torch.complex128)
+    w = torch.zeros(n, dtype=f64)
+    th = torch.zeros((rows, 8), dtype=f64)
+    one = torch.zeros(rows, dtype=f64)
+    cases = [
+        lambda: api.gb_window_prepare(1, d[:n - 1], w),
+        lambda: api.gb_window_prepare(1, d, w[:n - 1]),
+        lambda: api.gb_loglik(1, d, w, th[:rows - 1], one),
+        lambda: api.gb_loglik(1, d, w, th[:, :7].contiguous(), one),
+        lambda: api.gb_loglik(1, d, w, th, one[:rows - 1]),
+        lambda: api.gb_loglik(1, d, w, th, one, torch.zeros((rows, 3), dtype=f64)),
+        lambda: api.gb_loglik_grad(1, d, w, th, one, torch.zeros((rows - 1, 8), dtype=f64)),
+        lambda: api.gb_mh_step(1, d, w, th, one[:5], one, 1.0, one, one.to(torch.int32),
+                               torch.zeros(n_win, dtype=torch.int64)),
+        lambda: api.gb_mh_step(1, d, w, th, one, one, 1.0, one, one.to(torch.int32),
+                               torch.zeros(n_win - 1, dtype=torch.int64)),
+    ]
+    for c in cases:
+        with pytest.raises(ValueError):
+            c()
+    # correctly sized host tensors pass the size checks and are then refused as not on the device
+    with pytest.raises(TypeError):
+        api.gb_loglik(1, d, w, th, one, torch.zeros((rows, 2), dtype=f64))

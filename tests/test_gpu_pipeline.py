@@ -1,7 +1,7 @@
 """Algorithm 5 end to end on the GPU, as the benchmark's pipeline leg runs it, on a 30-segment
 block of the full-band workload (3.9-4.0 mHz): the global search (three even/odd runs, device
 DE, polish, joint refinement), the residual, the batched annealed posteriors and the match
-metric of Sec. V.  Regression bars from the measured behaviour (about 97% of the recovered
+metric of Sec. IV.  Regression bars from the measured behaviour (about 97% of the recovered
 sources matched, about 95% of the detectable injections found): at least 85% and 80%."""
 
 import sys

@@ -98,7 +98,7 @@ def _oracle_block(O, wl, i, sources, base=None):
 
 
 def test_match_delta_gpu(oracle_lib):
-    banner("match delta (Sec. V) of recovered against injected sources, against the oracle")
+    banner("match delta (Sec. IV) of recovered against injected sources, against the oracle")
     O = oracle_lib
     wl, segs, src, ctx, table, rows = _band_setup(O)
     rng = np.random.default_rng(9)

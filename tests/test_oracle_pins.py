@@ -397,3 +397,36 @@ def test_paper_numbers():
     bo = gv["broadening_orbit_rel"]["value"]
     assert abs(I.b_max(1e-2, 0.0) - (2 * bo * 1e-2 + 2 * gv["broadening_cartwheel_per_year"]["value"] / I.YEAR)) < 1e-20
     assert len(segs) == 4930
+
+
+def test_paper_schedule_and_boxes():
+    """The constants the drivers and the input generator take from the paper, against its printed
+    values: the six-temperature schedule and n_samples of Algorithm 4 (Sec. III G), the psi and
+    phi0 ranges of the reduced box (Sec. III G), and the Table I bounds on fdot and on the
+    amplitude through rho = 7 and 1000."""
+    import inspect
+    from paper_2307_03763_amd import drivers as D
+    gv = json.load(open(GOLDEN))
+    temps = tuple(gv["temperatures"]["value"])
+    n_s = gv["n_samples"]["value"]
+    for fn in (D.annealed_posterior, D.annealed_posterior_batch, D.posterior_batch):
+        p = inspect.signature(fn).parameters
+        assert tuple(p["temps"].default) == temps, fn.__name__
+        assert p["n"].default == n_s, fn.__name__
+    T = I.T2
+    f_lo, f_hi = 4.0e-3, 4.0e-3 + 2 * I.b_max(4.0e-3, T)
+    fc = 0.5 * (f_lo + f_hi)
+    box = I.table1_box(f_lo, f_hi, T)
+    lo_c = gv["fdot_lower_coeff"]
+    hi_c = gv["fdot_upper_coeff"]
+    assert box.lo[1] == pytest.approx(lo_c["value"] * fc ** lo_c["exponent"], rel=1e-14)
+    assert box.hi[1] == pytest.approx(hi_c["value"] * fc ** hi_c["exponent"], rel=1e-14)
+    s_a, _ = I.psd_aet(fc)
+    rho_lo, rho_hi = gv["snr_prior_bounds"]["value"]
+    assert 10 ** box.lo[4] == pytest.approx(I.a_of_rho(rho_lo, fc, T, s_a), rel=1e-12)
+    assert 10 ** box.hi[4] == pytest.approx(I.a_of_rho(rho_hi, fc, T, s_a), rel=1e-12)
+    # a maximum in the middle of the box: the psi and phi0 ranges are not clipped
+    th = I.from_table1(0.5 * (box.lo + box.hi))
+    lo, hi = I.reduced_box(th, box, 1e-6 * box.width)
+    assert hi[6] - lo[6] == pytest.approx(2 * gv["reduced_box_psi_halfwidth"]["value"], rel=1e-12)
+    assert hi[7] - lo[7] == pytest.approx(2 * gv["reduced_box_phi0_halfwidth"]["value"], rel=1e-12)
