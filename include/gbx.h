@@ -203,6 +203,17 @@ gb_status gb_add_templates(gb_ctx* ctx, const gb_window* windows, int n_win, con
 gb_status gb_noise_estimate(const gb_window* windows, int n_win, const double* d, double T, double* w, double* S,
                             void* stream);
 
+/* gb_noise_estimate without any device allocation, for callers that cannot allocate device
+ * memory (tight search loops that re-estimate the noise after every found signal, code that
+ * must not call hipMalloc).  Same arguments, results and synchronous behaviour as
+ * gb_noise_estimate.  The window list is staged in a fixed device array of the library (one
+ * per GPU, 16384 windows of 16 bytes = 256 KiB, held until the process ends), filled through a
+ * small host buffer on the stack.  Every call on one GPU shares that array, so calls that
+ * overlap on one GPU (several host threads or streams) race: serialise them.
+ * GB_EINVAL: more than 16384 windows (the staging limit), and the cases of gb_noise_estimate. */
+gb_status gb_noise_estimate_noalloc(const gb_window* windows, int n_win, const double* d, double T, double* w,
+                                    double* S, void* stream);
+
 /* One generation of the differential-evolution search (DE/best/1/bin or DE/rand/1/bin of Storn
  * and Price, the optimiser the paper's search uses, Sec. III), trial step, for n_win windows with pop members
  * each (pop >= 4), over the seven searched Table I coordinates in the order f0, fdot, sin(beta),

@@ -24,7 +24,7 @@ PRECISION = {"fp64": GB_FP64, "mixed": GB_MIXED, "per_window": GB_PER_WINDOW}
 EXPORTS = ("gb_create", "gb_destroy", "gb_last_error", "gb_waveform", "gb_plan_create",
            "gb_plan_destroy", "gb_plan_info", "gb_window_prepare", "gb_loglik", "gb_loglik_grad", "gb_mh_step",
            "gb_autotune", "gb_select_variant", "gb_fisher", "gb_kde_logpdf", "gb_add_templates",
-           "gb_noise_estimate", "gb_de_trial", "gb_de_select")
+           "gb_noise_estimate", "gb_noise_estimate_noalloc", "gb_de_trial", "gb_de_select")
 
 
 class GbxError(RuntimeError):
@@ -90,6 +90,8 @@ def lib():
         L.gb_kde_logpdf.restype = st
         L.gb_noise_estimate.argtypes = [ctypes.POINTER(gb_window), i, _vp, d, _vp, _vp, _vp]
         L.gb_noise_estimate.restype = st
+        L.gb_noise_estimate_noalloc.argtypes = [ctypes.POINTER(gb_window), i, _vp, d, _vp, _vp, _vp]
+        L.gb_noise_estimate_noalloc.restype = st
         L.gb_de_trial.argtypes = [i, i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, d, d, _vp, _vp, _vp]
         L.gb_de_trial.restype = st
         L.gb_de_select.argtypes = [i, i, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
@@ -309,6 +311,22 @@ def gb_noise_estimate(table, d: torch.Tensor, T: float, w: Optional[torch.Tensor
                                    _dev(w, torch.float64, "w"), _dev(S, torch.float64, "S"), _stream(stream)),
            "gb_noise_estimate")
     return w, S
+
+
+def gb_noise_estimate_noalloc(table, d: torch.Tensor, T: float, w: torch.Tensor, S: Optional[torch.Tensor] = None,
+                              stream=None):
+    """gb_noise_estimate into caller-supplied w (d's layout) and S [n_win, 3] (or None): the
+    library allocates no device memory (its window list is staged in a fixed device array;
+    at most 16384 windows)."""
+    wins = windows_array(table)
+    _check_len(d, _data_len(wins), "d")
+    _check_len(w, _data_len(wins), "w")
+    if S is not None and tuple(S.shape) != (len(wins), 3):
+        raise ValueError("gb_noise_estimate_noalloc: S must be [n_win, 3]")
+    _check(lib().gb_noise_estimate_noalloc(wins, len(wins), _dev(d, torch.complex128, "d"), float(T),
+                                           _dev(w, torch.float64, "w"),
+                                           None if S is None else _dev(S, torch.float64, "S"), _stream(stream)),
+           "gb_noise_estimate_noalloc")
 
 
 def gb_de_trial(lo: torch.Tensor, hi: torch.Tensor, x: torch.Tensor, u_idx: torch.Tensor, u_cross: torch.Tensor,

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -700,6 +701,74 @@ extern "C" gb_status gb_noise_estimate(const gb_window* windows, int n_win, cons
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   (void)hipFree(d_nw);
   if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? GB_ENOMEM : GB_EHIP, "gb_noise_estimate: %s", hipGetErrorString(e));
+  return GB_OK;
+}
+
+// ------------------------------------------------------------------------------- allocation-free noise estimate
+// gb_noise_estimate_noalloc stages its window list in this file-scope device array instead of
+// a per-call allocation.  Every GPU the library runs on holds its own copy until the process
+// ends.  In host code the array's name is only a stand-in: host code reaches the memory through
+// the per-device address that hipGetSymbolAddress returns (noise_scratch below).
+constexpr int kNoiseNoallocMaxWin = 16384;  // 16 B per window: 256 KiB per device
+static __device__ __align__(256) NoiseWin scratch[kNoiseNoallocMaxWin];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static NoiseWin* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's staging array, looked up once per device (with that
+// device current) and kept.
+static gb_status noise_scratch(NoiseWin** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(GB_EUNSUPPORTED, "gb_noise_estimate_noalloc: device %d >= %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(GB_EHIP, "gb_noise_estimate_noalloc: hipGetSymbolAddress: %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<NoiseWin*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return GB_OK;
+}
+
+extern "C" gb_status gb_noise_estimate_noalloc(const gb_window* windows, int n_win, const double* d, double T,
+                                               double* w, double* S, void* stream) {
+  if (n_win < 0 || (n_win > 0 && (!windows || !d || !w)) || !(T > 0.0) || !std::isfinite(T))
+    return fail(GB_EINVAL, "gb_noise_estimate_noalloc: bad arguments");
+  if (n_win > kNoiseNoallocMaxWin)
+    return fail(GB_EINVAL, "gb_noise_estimate_noalloc: %d windows exceed the staging limit of %d", n_win,
+                kNoiseNoallocMaxWin);
+  if (n_win == 0) return GB_OK;
+  for (int i = 0; i < n_win; ++i) {
+    const gb_window& g = windows[i];
+    if (g.W < 1 || g.W > kNoiseMaxW || (g.C != 2 && g.C != 3) || g.data_off < 0)
+      return fail(GB_EINVAL, "gb_noise_estimate_noalloc: window %d: W must be 1..%d, C 2 or 3, offset >= 0", i,
+                  kNoiseMaxW);
+  }
+  NoiseWin* stage = nullptr;
+  gb_status s = noise_scratch(&stage);
+  if (s != GB_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  // the window list goes to the device in chunks through a small host buffer on the stack; the
+  // stream is drained after each copy, so the buffer can be refilled
+  constexpr int kChunk = 256;
+  NoiseWin host[kChunk];
+  for (int i0 = 0; i0 < n_win; i0 += kChunk) {
+    const int n = std::min(kChunk, n_win - i0);
+    for (int i = 0; i < n; ++i) {
+      host[i].data_off = windows[i0 + i].data_off;
+      host[i].W = windows[i0 + i].W;
+      host[i].C = windows[i0 + i].C;
+    }
+    HIPCHK(hipMemcpyAsync(stage + i0, host, sizeof(NoiseWin) * n, hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  hipLaunchKernelGGL(k_noise_median, dim3((unsigned)n_win, 3), dim3(1024), 0, st, stage, d, T, w, S);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
   return GB_OK;
 }
 

@@ -56,6 +56,19 @@ def test_struct_layouts_match_header():
     assert api.gb_window.data_off.offset == 24 and api.gb_window.n_cand.offset == 40
 
 
+def test_noalloc_noise_estimate_validation_without_device():
+    """The allocation-free noise estimate refuses more windows than its staging array holds, and
+    bad windows, before touching HIP."""
+    from paper_2307_03763_amd import api
+    L = api.lib()
+    wins = api.windows_array([[1000, 64, 64, 2, 0, 0, 0, 1]] * 16385)
+    assert L.gb_noise_estimate_noalloc(wins, 16385, 1, 1.0, 1, None, None) == api.GB_EINVAL
+    assert b"16384" in L.gb_last_error()
+    bad = api.windows_array([[1000, 4097, 64, 2, 0, 0, 0, 1]])
+    assert L.gb_noise_estimate_noalloc(bad, 1, 1, 1.0, 1, None, None) == api.GB_EINVAL
+    assert L.gb_noise_estimate_noalloc(wins, 1, 1, -1.0, 1, None, None) == api.GB_EINVAL
+
+
 class _NoLaunch:
     """Stands in for the library: any call other than the size query fails the test."""
 
