@@ -258,6 +258,42 @@ def main():
     mixed = summary(step_mx, ms_mx, per_mx)
     log(f"mixed ragged: {ms_mx:.2f} ms/step {mixed}")
     logl_mixed = logL.cpu().numpy().copy()
+    # logL kernels alone (no chain) of the adaptive step: the MH groups timed through gb_loglik
+    ms_ad_logl = float(sum(t for key, _, t in kern if key[0] == "mh"))
+    adaptive["logl_only_evals_per_s"] = round(rows / (ms_ad_logl * 1e-3), 1)
+
+    def time_calls(fn, reps):
+        """Mean time of one call of fn (a sequence of launches on `stream`), HIP events."""
+        fn()
+        torch.cuda.synchronize()
+        ev = [[E(), E()] for _ in range(reps)]
+        for a, b in ev:
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        return float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+    # FP64 ragged: the headline's plan structure (one MH call over all windows: one persistent
+    # logL launch per (N, C) bucket, one chain launch) with every window in FP64, so that mixed
+    # against FP64 compares precision at equal batching
+    fp64r = None
+    if not args.no_fp64:
+        tab64 = np.concatenate([table, np.full((wl.n_win, 1), api.GB_FP64, dtype=np.int64)], axis=1)
+        p64 = api.Plan(ctx, tab64, api.GB_PER_WINDOW)
+        p64.prepare(d, w)
+        nacc64 = torch.empty(wl.n_win, dtype=torch.int64, device="cuda")
+        ms_64 = time_calls(lambda: api.gb_mh_step(p64.handle, d, w, th, log_g, u, args.temperature, logL, chain,
+                                                  nacc64, stream), args.steps)
+        ms_64l = time_calls(lambda: api.gb_loglik(p64.handle, d, w, th, logL, None, stream), args.steps)
+        fp64r = {"logl_evals_per_s": round(rows / (ms_64 * 1e-3), 1), "ms_mh_stage": round(ms_64, 3),
+                 "logl_only_evals_per_s": round(rows / (ms_64l * 1e-3), 1), "ms_logl_only": round(ms_64l, 3),
+                 "grad_evals_per_s": None,
+                 "note": "MH stage of all windows in one call, every window FP64 (the headline's batching); "
+                         "logl_only: the same likelihood launches without the chain; the FP64 gradient is "
+                         "switched off in this version, so the FP64 comparison is one of likelihoods"}
+        log(f"FP64 ragged: MH stage {ms_64:.2f} ms, logL only {ms_64l:.2f} ms")
+        p64.close()
 
     # dominant kernel of the headline step (largest k_batch time per step)
     key, idx, dur_ms = max(kern, key=lambda e: e[2])
@@ -300,11 +336,18 @@ def main():
         plain(ev)
         torch.cuda.synchronize()
         f_l = ev[0].elapsed_time(ev[1])
+
+        def plain_logl():
+            for p in win_plans:
+                api.gb_loglik(p.handle, d, w, th, logL, None, stream)
+        f_ll = time_calls(plain_logl, 2)
         fp64 = {"logl_evals_per_s": round(rows / (f_l * 1e-3), 1), "ms_mh_stage": round(f_l, 3),
+                "logl_only_evals_per_s": round(rows / (f_ll * 1e-3), 1), "ms_logl_only": round(f_ll, 3),
                 "grad_evals_per_s": None,
-                "note": "MH stage (logL of every proposal + chains) in FP64, one launch per window; "
-                        "the FP64 gradient is switched off in this version"}
-        log(f"plain FP64 per window: logL {fp64['logl_evals_per_s']:.3e}/s")
+                "note": "MH stage (logL of every proposal + its chain) in FP64, one likelihood launch and one "
+                        "chain launch per window; logl_only: the per-window likelihood launches alone; the "
+                        "FP64 gradient is switched off in this version, so the comparison is one of likelihoods"}
+        log(f"plain FP64 per window: logL {fp64['logl_evals_per_s']:.3e}/s, logL only {f_ll:.2f} ms")
         for p in win_plans:
             p.close()
 
@@ -317,9 +360,29 @@ def main():
         pipe = pipeline_leg(None if args.pipeline_full else tuple(args.pipeline_segments), log,
                             catalogue=args.pipeline_catalogue)
 
+    # gradient accuracy scale of every row: the mixed gradient's error against the gradient's own
+    # noise scale sqrt(F_ii) grows like sqrt(<d|d> + <h|h>) (the FP32 template error times the
+    # residual norm); rows with sqrt(<d|d> + <h|h>) <= GRAD_NORM_LIMIT stay within 1e-5 sqrt(F_ii)
+    pmx = api.Plan(ctx, table, api.GB_MIXED)
+    pmx.prepare(d, w)
+    _, comps_mx = pmx.loglik(th, comps=True)
+    dd_w = torch.as_tensor([float(np.sum(wl.window_data(i)[1] * np.abs(wl.window_data(i)[0]) ** 2))
+                            for i in range(wl.n_win)], device="cuda")
+    win_of_row = torch.as_tensor(np.repeat(np.arange(wl.n_win), wl.n_cand), device="cuda")
+    norm_row = torch.sqrt(dd_w[win_of_row] + comps_mx[:, 1])
+    n_within = int((norm_row <= GRAD_NORM_LIMIT).sum())
+    pmx.close()
+    grad_acc = {"bar": "|g_gpu - g_oracle|_i <= 1e-5 sqrt(F_ii), F the Fisher matrix at the candidate",
+                "rows_with_norm_within_limit": n_within, "rows": rows,
+                "norm_limit": f"sqrt(<d|d> + <h|h>) <= {GRAD_NORM_LIMIT:g}",
+                "model": "error ~ (2e-7 .. 1.1e-6) sqrt(<d|d> + <h|h>) sqrt(F_ii), largest in the amplitude "
+                         "and inclination components (FP32 template error times the residual norm)",
+                "grad_evals_per_s_within_bar": round(n_within / (float(sum(t for (k, *_), t in zip(step_ad, per_ad)
+                                                                           if k[0] == "gr")) * 1e-3), 1)}
+
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(wl, args.cpu_seconds, logl_mixed, rho_w, log)
+        cpu = cpu_baseline(wl, args.cpu_seconds, logl_mixed, rho_w, log, grad, grad_acc)
 
     value = adaptive["value"]
     out = {
@@ -336,10 +399,15 @@ def main():
                            "gradients, one persistent launch per (N, C) group"},
         "logl_evals_per_s": adaptive["logl_evals_per_s"],
         "grad_evals_per_s": adaptive["grad_evals_per_s"],
+        "logl_only_evals_per_s": adaptive["logl_only_evals_per_s"],
+        "grad_accuracy": grad_acc,
         "mixed_everywhere": mixed,
+        "fp64_ragged": fp64r,
         "fp64_plain": fp64,
         "speedup_vs_fp64": (round(adaptive["logl_evals_per_s"] / fp64["logl_evals_per_s"], 3) if fp64 else None),
-        "speedup_basis": "logL evals/s of the MH stage, adaptive ragged vs plain FP64 per window",
+        "speedup_basis": "logL evals/s of the MH stage, adaptive ragged vs plain FP64 per window: precision "
+                         "and batching together; 'speedups' separates them",
+        "speedups": speedups(adaptive, mixed, fp64r, fp64),
         "roofline": roofline,
         "posterior": post,
         "pipeline": pipe,
@@ -352,6 +420,40 @@ def main():
                    "(about 3.3e4 logL/s including chain and KDE); different hardware and work",
     }
     print(json.dumps(out), flush=True)
+
+
+GRAD_NORM_LIMIT = 25.0      # sqrt(<d|d> + <h|h>) below which mixed gradients meet 1e-5 sqrt(F_ii)
+
+
+def speedups(adaptive, mixed, fp64r, fp64p):
+    """Likelihood-rate ratios, each named by the effect it measures."""
+    if not fp64r or not fp64p:
+        return None
+    r = lambda a, b: round(a / b, 3)
+    return {
+        "precision_at_equal_batching (MH stage, adaptive ragged / FP64 ragged)":
+            r(adaptive["logl_evals_per_s"], fp64r["logl_evals_per_s"]),
+        "precision_at_equal_batching (MH stage, all-mixed ragged / FP64 ragged)":
+            r(mixed["logl_evals_per_s"], fp64r["logl_evals_per_s"]),
+        "precision_at_equal_batching (logL kernels only, adaptive ragged / FP64 ragged)":
+            r(adaptive["logl_only_evals_per_s"], fp64r["logl_only_evals_per_s"]),
+        "batching_at_equal_precision (MH stage, FP64 ragged / FP64 per window)":
+            r(fp64r["logl_evals_per_s"], fp64p["logl_evals_per_s"]),
+        "batching_at_equal_precision (logL kernels only, FP64 ragged / FP64 per window)":
+            r(fp64r["logl_only_evals_per_s"], fp64p["logl_only_evals_per_s"]),
+        "both (MH stage, adaptive ragged / FP64 per window)":
+            r(adaptive["logl_evals_per_s"], fp64p["logl_evals_per_s"]),
+    }
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
 
 
 class TimedRegion:
@@ -752,10 +854,11 @@ def pipeline_leg(segments, log, precision: str = "mixed", catalogue=None, noise:
     }
 
 
-def cpu_baseline(wl, seconds, logL_gpu, rho_w, log):
+def cpu_baseline(wl, seconds, logL_gpu, rho_w, log, grad_gpu=None, grad_acc=None):
     """The oracle, unmodified, on a stratified sample of the same workload: a few candidates of
-    windows spread over every (N, C) group; logL and gradient of each.  Also reports the largest
-    disagreement with the GPU values of the same candidates."""
+    windows spread over every (N, C) group; logL and gradient of each, on all host threads and
+    on one.  Also reports the largest disagreement with the GPU values of the same candidates:
+    mixed logL differences, and (into grad_acc) the mixed gradient's error against sqrt(F_ii)."""
     import numpy as np
 
     from oracle import oracle as O
@@ -764,7 +867,8 @@ def cpu_baseline(wl, seconds, logL_gpu, rho_w, log):
     order = sorted(range(wl.n_win), key=lambda i: (wl.windows[i].N, wl.windows[i].C))
     sample = order[:: max(1, len(order) // 16)][:16]
     lg = np.asarray(logL_gpu)
-    def run(n_cand, sample):
+
+    def run(n_cand, sample, nthreads=0):
         nonlocal_max = 0.0
         t = time.time()
         evals = 0
@@ -773,8 +877,8 @@ def cpu_baseline(wl, seconds, logL_gpu, rho_w, log):
             dd, ww = wl.window_data(i)
             th = wl.window_theta(i)[:n_cand]
             a = int(wl.cand_off[i])
-            l, _ = O.loglik(th, win.k0, win.W, win.N, win.C, dd, ww, g, 0)
-            O.loglik_grad(th, win.k0, win.W, win.N, win.C, dd, ww, g, 0)
+            l, _ = O.loglik(th, win.k0, win.W, win.N, win.C, dd, ww, g, nthreads)
+            O.loglik_grad(th, win.k0, win.W, win.N, win.C, dd, ww, g, nthreads)
             evals += 2 * len(th)
             ref = lg[a:a + len(th)]
             dl = (ref - ref[0]) - (l - l[0])
@@ -790,6 +894,9 @@ def cpu_baseline(wl, seconds, logL_gpu, rho_w, log):
         n_w = int(min(64, len(order), max(16, seconds / (per * 10000))))
         sample = order[:: max(1, len(order) // n_w)][:n_w]
     evals, spent, max_dl = run(n_cand, sample)
+    # one core: the same windows, candidates cut to about a tenth of the budget
+    n1 = int(max(16, min(n_cand, 0.1 * seconds / (per * threads * len(sample)))))
+    ev_1, spent_1, _ = run(n1, sample, 1)
     errs = {}
     for i in sample[:: max(1, len(sample) // 16)]:
         win = wl.windows[i]
@@ -800,11 +907,38 @@ def cpu_baseline(wl, seconds, logL_gpu, rho_w, log):
         ref = lg[a:a + len(th)]
         e = float(np.max(np.abs((ref - ref[0]) - (l - l[0])) / np.maximum(1.0, np.abs(l - l[0]))))
         errs[f"window {i} (N={win.N}, C={win.C}, rho={rho_w[i]:.0f})"] = e
-    log(f"cpu oracle: {evals} evals in {spent:.1f}s on {threads} threads")
+    if grad_gpu is not None and grad_acc is not None:
+        # mixed gradients of 4 rows in each of 16 sampled windows against the oracle gradient, in
+        # units of sqrt(F_ii) (the oracle's Fisher matrix at the row)
+        e_f, norm = [], []
+        for i in sample[:: max(1, len(sample) // 16)][:16]:
+            win = wl.windows[i]
+            dd, ww = wl.window_data(i)
+            a = int(wl.cand_off[i])
+            th = wl.window_theta(i)[:4]
+            gg = grad_gpu[a:a + len(th)].cpu().numpy()
+            _, go = O.loglik_grad(th, win.k0, win.W, win.N, win.C, dd, ww, g, 0)
+            _, co = O.loglik(th, win.k0, win.W, win.N, win.C, dd, ww, g, 0)
+            ddv = float(np.sum(ww * np.abs(dd) ** 2))
+            for b in range(len(th)):
+                F = O.fisher(th[b], win.k0, win.W, win.N, win.C, ww, g)
+                e_f.append(float(np.max(np.abs(gg[b] - go[b]) / np.sqrt(np.maximum(np.diag(F), 1e-300)))))
+                norm.append(math.sqrt(ddv + co[b, 1]))
+        e_f, norm = np.array(e_f), np.array(norm)
+        quiet = norm <= GRAD_NORM_LIMIT
+        grad_acc["sampled_rows"] = int(len(e_f))
+        grad_acc["sampled_worst_err_over_sqrtF"] = float(e_f.max())
+        grad_acc["sampled_median_err_over_sqrtF"] = float(np.median(e_f))
+        grad_acc["sampled_frac_within_bar"] = float(np.mean(e_f <= 1e-5))
+        grad_acc["sampled_worst_within_norm_limit"] = float(e_f[quiet].max()) if quiet.any() else None
+        grad_acc["sampled_worst_err_over_sqrtF_norm"] = float(np.max(e_f / norm))
+    log(f"cpu oracle: {evals} evals in {spent:.1f}s on {threads} threads; one core: {ev_1} in {spent_1:.1f}s")
     return {"value": round(evals / spent, 2), "unit": "evals/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(sample)} windows spread over the (N, C) groups x {n_cand} candidates each, "
                       f"logL + gradient per candidate (FP64 C++ oracle, OpenMP over candidates)",
-            "cpu": platform.processor() or platform.machine(),
+            "cpu": cpu_model(),
+            "one_core": {"value": round(ev_1 / spent_1, 2), "unit": "evals/s", "cores": 1,
+                         "sample": f"the same {len(sample)} windows x {n1} candidates"},
             "mixed_dlogl_err_vs_oracle": errs}
 
 

@@ -8,7 +8,7 @@ recomputes sampled rows one by one; chains are compared bit for bit.
   FP64 logL of all rows; the 10,000-step chain at T = 1, bit-exact; also without subtracting
   the other two sources.
 * C3: the benchmark's batch (256 windows x 10,000 proposals): adaptive logL on 2,048 sampled
-  rows and mixed gradients on 256 sampled rows.
+  rows and mixed gradients on 256 sampled rows (error against sqrt(F_ii), see GRAD_BAR).
 * C4: 64 windows x 4,096 candidates uniform over Table I: mixed gradients on 512 sampled rows
   against the oracle gradient, and one candidate per window against central differences of the
   FP64 logL (steps of 1e-6 of the Table I widths).
@@ -93,22 +93,51 @@ def _check_rows(O, wl, l_gpu, rows_per_window, prec_w):
     return worst64, worstmx
 
 
-def _grad_bar(O, wl, i, th, g_gpu):
-    """Mixed-gradient check of one window's rows against the oracle gradient: the difference of
-    each component within 1e-5 of sqrt(F_ii (<d|d> + <h|h>)), the size of that component's
-    natural scale (Cauchy-Schwarz bound of Re<d-h|dh/dtheta_i>)."""
+# Mixed-gradient error model (measured on C3 and C4): |g_gpu - g_oracle|_i is about
+# 2e-7 to 1.1e-6 times sqrt(<d|d> + <h|h>) sqrt(F_ii), largest in the amplitude and inclination
+# components: the FP32 template's relative error (5e-7 typical) times the residual norm.  Bars:
+#  * every row: error <= GRAD_NAT * sqrt(F_ii (<d|d> + <h|h>)), the component's natural scale
+#    (the Cauchy-Schwarz bound of Re<d - h | dh/dtheta_i>);
+#  * rows with sqrt(<d|d> + <h|h>) <= GRAD_NORM_LIMIT: error <= GRAD_BAR * sqrt(F_ii), the
+#    gradient's own noise scale at the truth.
+GRAD_NAT = 2e-6
+GRAD_BAR = 1e-5
+GRAD_NORM_LIMIT = 25.0
+
+
+def _grad_errors(O, wl, i, th, g_gpu):
+    """Per row: the largest |g_gpu - g_oracle| / sqrt(F_ii) over the eight components, and the
+    row's sqrt(<d|d> + <h|h>)."""
     w = wl.windows[i]
     d, ww = wl.window_data(i)
     g = O.Geometry(wl.T)
     _, go = O.loglik_grad(th, w.k0, w.W, w.N, w.C, d, ww, g)
+    _, c = O.loglik(th, w.k0, w.W, w.N, w.C, d, ww, g)
     dd = float(np.sum(ww * np.abs(d) ** 2))
-    worst = 0.0
+    e_f, norm = [], np.sqrt(dd + c[:, 1])
     for b in range(len(th)):
         F = O.fisher(th[b], w.k0, w.W, w.N, w.C, ww, g)
-        _, c = O.loglik(th[b], w.k0, w.W, w.N, w.C, d, ww, g)
-        scale = np.sqrt(np.maximum(np.diag(F), 1e-300) * (dd + c[0, 1]))
-        worst = max(worst, float(np.max(np.abs(g_gpu[b] - go[b]) / scale)))
-    return worst
+        e_f.append(float(np.max(np.abs(g_gpu[b] - go[b]) / np.sqrt(np.maximum(np.diag(F), 1e-300)))))
+    return np.array(e_f), norm
+
+
+def _check_grads(O, wl, rows, win_ids, grad, label):
+    e_f, norm = [], []
+    for i in win_ids:
+        r = rows[i]
+        a, b = _grad_errors(O, wl, i, wl.theta[r], grad[r])
+        e_f.append(a)
+        norm.append(b)
+    e_f, norm = np.concatenate(e_f), np.concatenate(norm)
+    nat = float(np.max(e_f / norm))
+    quiet = norm <= GRAD_NORM_LIMIT
+    banner(f"  {label}: worst error / sqrt(F_ii (dd + hh)) {nat:.2e}; worst error / sqrt(F_ii) {e_f.max():.2e} "
+           f"(rows with sqrt(dd + hh) <= {GRAD_NORM_LIMIT:g}: {int(quiet.sum())} of {len(e_f)}, worst "
+           f"{(e_f[quiet].max() if quiet.any() else 0.0):.2e}); within {GRAD_BAR:g} sqrt(F_ii): "
+           f"{float(np.mean(e_f <= GRAD_BAR)):.0%} of rows")
+    assert nat <= GRAD_NAT, nat
+    assert not quiet.any() or e_f[quiet].max() <= GRAD_BAR, e_f[quiet].max()
+    return quiet
 
 
 def test_c1_full(oracle_lib, tuned):
@@ -180,12 +209,8 @@ def test_c3_full(oracle_lib, tuned):
     gplan.prepare(d, w)
     _, grad = gplan.loglik_grad(th)
     grad = grad.cpu().numpy()
-    worst = 0.0
-    for i in range(0, wl.n_win, 8):                 # 32 windows x 8 rows
-        r = rows[i]
-        worst = max(worst, _grad_bar(O, wl, i, wl.theta[r], grad[r]))
-    banner(f"  mixed gradients: worst error / scale {worst:.2e}")
-    assert worst <= 1e-5
+    quiet = _check_grads(O, wl, rows, range(0, wl.n_win, 8), grad, "mixed gradients (32 windows x 8 rows)")
+    assert quiet.any()                              # the low-SNR windows are checked on sqrt(F_ii)
 
 
 def test_c4_full(oracle_lib, tuned):
@@ -200,9 +225,7 @@ def test_c4_full(oracle_lib, tuned):
     grad = grad.cpu().numpy()
     rng = np.random.default_rng(41)
     rows = _sample_rows(wl, 8, rng)
-    worst = max(_grad_bar(O, wl, i, wl.theta[rows[i]], grad[rows[i]]) for i in range(wl.n_win))
-    banner(f"  mixed gradients vs oracle: worst error / scale {worst:.2e}")
-    assert worst <= 1e-5
+    _check_grads(O, wl, rows, range(wl.n_win), grad, "mixed gradients vs oracle (64 windows x 8 rows)")
     # central differences of the FP64 logL (GPU), one candidate per window, 16 evaluations each
     widths = np.stack([wl.window_box(i).width for i in range(wl.n_win)])
     pick = np.array([r[0] for r in rows])

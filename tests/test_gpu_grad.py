@@ -3,7 +3,9 @@ against central differences of the GPU logL.
 
 Scale of a gradient component: |dlogL/dtheta_i| <= ||d - h|| ||d_i h|| <= sqrt(F_ii (<d|d> + <h|h>))
 up to a factor of order one, so errors are measured against s_i = sqrt(F_ii (<d|d> + <h|h>)).
-Bars: FP64 1e-9 s_i; mixed precision 1e-5 s_i.
+Bars: FP64 1e-9 s_i; mixed precision MIXED_NAT s_i.  The mixed error is the FP32 template's
+relative error (about 5e-7) times the residual norm, so measured against the gradient's own
+noise scale sqrt(F_ii) it grows like sqrt(<d|d> + <h|h>): the full-size tests state it there.
 
 The torch.autograd wrapper (api.loglik) returns the library's gradient through the chain rule.
 
@@ -71,12 +73,14 @@ def _run(wl, prec):
     return l.cpu().numpy(), g.cpu().numpy(), l2.cpu().numpy(), (ctx, plan, d, w, th)
 
 
+MIXED_NAT = 2e-6   # measured worst 1.1e-6 on the full-size workloads (C4), 9e-7 here
+
 FP64_GRAD_OFF = "FP64 gradient switched off: its kernels faulted on the GPU; cause not yet known"
 
 
 @pytest.mark.parametrize("C", [2, 3])
 @pytest.mark.parametrize("prec,bar", [pytest.param(api.GB_FP64, 1e-9, marks=pytest.mark.skip(reason=FP64_GRAD_OFF)),
-                                      (api.GB_MIXED, 1e-5)])
+                                      (api.GB_MIXED, MIXED_NAT)])
 def test_gradient_matches_oracle(oracle_lib, C, prec, bar):
     banner(f"gradient vs oracle C={C} prec={prec}")
     _check_against_oracle(oracle_lib, _workload(oracle_lib, C), prec, bar)
@@ -92,7 +96,7 @@ def test_gradient_high_frequency(oracle_lib):
     f = np.array([w.sources[0, 0] for w in wl.windows])
     f_series = 0.999 / (np.pi * I.ARM_L / I.C_LIGHT)      # below it every link argument is below 2
     assert np.any(f < f_series) and np.any(f > 40e-3), f
-    _check_against_oracle(oracle_lib, wl, api.GB_MIXED, 1e-5)
+    _check_against_oracle(oracle_lib, wl, api.GB_MIXED, MIXED_NAT)
 
 
 def _check_against_oracle(oracle_lib, wl, prec, bar):
@@ -173,7 +177,7 @@ def test_gradient_ragged_mixed(oracle_lib, c3_grad):
         sc = _scales(O, wl, i, th, co[:, 1])
         worst = np.maximum(worst, (np.abs(g[a:a + n] - go) / sc).max(axis=0))
     banner("  worst scaled error per parameter: " + " ".join(f"{x:.1e}" for x in worst))
-    assert worst.max() <= 1e-5
+    assert worst.max() <= MIXED_NAT
 
 
 def test_fp64_gradient_is_refused(c3_grad):
