@@ -56,6 +56,11 @@ typedef struct {
   double orbit_period;   /* period of the guiding centre, s (sidereal year) */
   double arm_length;     /* L, m (half transfer frequency 1/(4 pi L) = 9.55 mHz for 2.5e9 m, Sec. II) */
   double au;             /* radius of the guiding-centre orbit, m */
+  int32_t tdi_generation;/* 1 (or 0): first-generation equal-arm Michelson X, Y, Z, from which
+                            the A, E, T of Sec. II are formed; 2: second generation, which for
+                            equal arms is the first-generation combination minus its copy
+                            delayed by four arm lengths (a factor 1 - D^4, D = e^{-2 pi i f L/c}) */
+  int32_t reserved;      /* must be 0 */
 } gb_config;
 
 /* One frequency window: the padded segment of Sec. III B over which the scalar product is
@@ -75,8 +80,10 @@ typedef struct gb_ctx gb_ctx;     /* device tables for one gb_config (orbit, twi
 typedef struct gb_plan gb_plan;   /* work lists and launch shapes for a set of windows */
 
 /* Create a context on the current HIP device: builds the per-sample orbit tables and the
- * DFT twiddles for N = 64..1024 (device memory owned by the context).  Synchronous.
- * GB_EINVAL for non-positive constants.  *ctx is NULL on failure. */
+ * DFT twiddles for N = 64..1024 (device memory owned by the context).  Every template,
+ * likelihood and gradient of the context uses its TDI generation.  Synchronous.
+ * GB_EINVAL for non-positive constants or a generation other than 0, 1, 2.  *ctx is NULL on
+ * failure. */
 gb_status gb_create(const gb_config* cfg, gb_ctx** ctx);
 void gb_destroy(gb_ctx* ctx);
 

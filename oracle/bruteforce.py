@@ -1,4 +1,5 @@
 """Brute-force time-domain TDI (test infrastructure): the definition the fast/slow model approximates.
+First- and second-generation equal-arm Michelson combinations.
 
 For tiny cases (M <= 2^18 samples) the TDI X, Y, Z are evaluated at every sample time
 directly from the plane-wave field, with every retardation and delay taken exactly, and
@@ -94,18 +95,25 @@ def link(theta, pol, t, r, s, delay, P_orb, L, AU, mode="G1"):
     return (h_emit - h_recv) / (2.0 * (1.0 - kn))
 
 
-def tdi_xyz(theta, t, P_orb, L, AU, mode="G1"):
-    """First-generation equal-arm Michelson X, Y, Z at times t (arrays).
-    X = y13 + y31(t-L) + y12(t-2L) + y21(t-3L) - y12 - y21(t-L) - y13(t-2L) - y31(t-3L),
-    Y, Z by the cyclic relabelling 1 -> 2 -> 3 -> 1."""
+def tdi_xyz(theta, t, P_orb, L, AU, mode="G1", generation=1):
+    """Equal-arm Michelson X, Y, Z at times t (arrays), Y and Z by the cyclic relabelling
+    1 -> 2 -> 3 -> 1.  First generation (eight links):
+      X1 = y13 + y31(t-L) + y12(t-2L) + y21(t-3L) - y12 - y21(t-L) - y13(t-2L) - y31(t-3L).
+    Second generation (sixteen links; every delay operator is one arm length here):
+      X2 = y13 + y31(t-L) + y12(t-2L) + y21(t-3L) + y12(t-4L) + y21(t-5L) + y13(t-6L) + y31(t-7L)
+         - y12 - y21(t-L) - y13(t-2L) - y31(t-3L) - y13(t-4L) - y31(t-5L) - y12(t-6L) - y21(t-7L)."""
     pol = polarisation(theta)
 
     def y(r, s, j):
         return link(theta, pol, t, r - 1, s - 1, j, P_orb, L, AU, mode)
 
     def michelson(a, b, c):
-        return (y(a, c, 0) + y(c, a, 1) + y(a, b, 2) + y(b, a, 3)
-                - y(a, b, 0) - y(b, a, 1) - y(a, c, 2) - y(c, a, 3))
+        x = (y(a, c, 0) + y(c, a, 1) + y(a, b, 2) + y(b, a, 3)
+             - y(a, b, 0) - y(b, a, 1) - y(a, c, 2) - y(c, a, 3))
+        if generation == 2:
+            x = x + (y(a, b, 4) + y(b, a, 5) + y(a, c, 6) + y(c, a, 7)
+                     - y(a, c, 4) - y(c, a, 5) - y(a, b, 6) - y(b, a, 7))
+        return x
 
     X = michelson(1, 2, 3)
     Y = michelson(2, 3, 1)
@@ -113,20 +121,20 @@ def tdi_xyz(theta, t, P_orb, L, AU, mode="G1"):
     return X, Y, Z
 
 
-def tdi_aet(theta, t, P_orb, L, AU, mode="G1"):
-    X, Y, Z = tdi_xyz(theta, t, P_orb, L, AU, mode)
+def tdi_aet(theta, t, P_orb, L, AU, mode="G1", generation=1):
+    X, Y, Z = tdi_xyz(theta, t, P_orb, L, AU, mode, generation)
     A = (Z - X) / math.sqrt(2.0)
     E = (X - 2.0 * Y + Z) / math.sqrt(6.0)
     T = (X + Y + Z) / math.sqrt(3.0)
     return A, E, T
 
 
-def spectrum(theta, M, dt, P_orb, L, AU, mode="G1", chunk=1 << 15):
+def spectrum(theta, M, dt, P_orb, L, AU, mode="G1", chunk=1 << 15, generation=1):
     """Full-length spectra x~_k = dt FFT(x) of A, E, T sampled at t_n = n dt, n < M; [3, M]."""
     series = np.empty((3, M))
     for a in range(0, M, chunk):
         t = dt * np.arange(a, min(M, a + chunk), dtype=np.float64)
-        A, E, T = tdi_aet(theta, t, P_orb, L, AU, mode)
+        A, E, T = tdi_aet(theta, t, P_orb, L, AU, mode, generation)
         series[0, a:a + len(t)] = A
         series[1, a:a + len(t)] = E
         series[2, a:a + len(t)] = T

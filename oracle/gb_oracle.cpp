@@ -14,8 +14,8 @@
 // The paper names the parameters but defers the signal model to the literature, so the
 // model below is this project's reading: a plane wave with + and x polarisations,
 // a rigid equal-arm triangle on the classic first-order heliocentric orbit, the
-// single-link response for light travel L/c, first-generation equal-arm Michelson TDI,
-// and the fast/slow evaluation (slow series on N samples, N-point DFT, heterodyne by the
+// single-link response for light travel L/c, first- or second-generation equal-arm
+// Michelson TDI, and the fast/slow evaluation (slow series on N samples, N-point DFT, heterodyne by the
 // carrier bin q = floor(f0 T)).  Every convention is listed in the design notes.
 //
 // Gradients: every step is written once over a scalar type R; R = double gives values,
@@ -144,6 +144,7 @@ struct Params {
   double P_orb;   // orbital period of the guiding centre, s
   double L;       // arm length, m
   double AU;      // orbital radius, m
+  int tdi;        // TDI generation, 1 or 2
 };
 
 struct V3 {
@@ -271,9 +272,18 @@ void slow_sample(const Source<R>& s, double t, const R& dfreq, const Params& p, 
   const Cx<R> g = one - D * D;
   // X(t) = y13 + y31(t-L) + y12(t-2L) + y21(t-3L) - y12 - y21(t-L) - y13(t-2L) - y31(t-3L);
   // a delay by L multiplies the slowly varying link phasor by D; Y, Z by cyclic relabelling
-  const Cx<R> X = g * ((z13 + D * z31) - (z12 + D * z21));
-  const Cx<R> Y = g * ((z21 + D * z12) - (z23 + D * z32));
-  const Cx<R> Z = g * ((z32 + D * z23) - (z31 + D * z13));
+  Cx<R> X = g * ((z13 + D * z31) - (z12 + D * z21));
+  Cx<R> Y = g * ((z21 + D * z12) - (z23 + D * z32));
+  Cx<R> Z = g * ((z32 + D * z23) - (z31 + D * z13));
+  if (p.tdi == 2) {
+    // second generation: the eight further links of X2 (delays 4L .. 7L) are the four-arm-delayed
+    // copy of X with the opposite sign when the arms are equal, X2(t) = X(t) - X(t - 4L)
+    const Cx<R> D2 = D * D;
+    const Cx<R> g2 = one - D2 * D2;
+    X = g2 * X;
+    Y = g2 * Y;
+    Z = g2 * Z;
+  }
   ch[0] = scaled(Z - X, 1.0 / std::sqrt(2.0));                   // A
   ch[1] = scaled((X - scaled(Y, 2.0)) + Z, 1.0 / std::sqrt(6.0));  // E
   ch[2] = scaled((X + Y) + Z, 1.0 / std::sqrt(3.0));              // T
@@ -355,12 +365,13 @@ R loglik_one(const R th[8], int64_t k0, int W, int N, int C, const double* d, co
   return -0.5 * acc;
 }
 
-Params mkp(double T, double P_orb, double L, double AU) {
+Params mkp(double T, double P_orb, double L, double AU, int tdi) {
   Params p;
   p.T = T;
   p.P_orb = P_orb;
   p.L = L;
   p.AU = AU;
+  p.tdi = tdi;
   return p;
 }
 
@@ -382,7 +393,7 @@ int gbo_max_threads(void) { return threads(0); }
 
 // Spacecraft positions x[3][3] (m) at time t.
 void gbo_spacecraft(double t, double P_orb, double L, double AU, double* x_out) {
-  Params p = mkp(1.0, P_orb, L, AU);
+  Params p = mkp(1.0, P_orb, L, AU, 1);
   V3 x[3];
   spacecraft(t, p, x);
   for (int i = 0; i < 3; ++i) {
@@ -404,8 +415,8 @@ void gbo_dft(double* z, int n) {
 }
 
 // Slow series S_c(t_m) (before the DFT) of one source: out[c][m] complex, c < 3.
-void gbo_slow_series(const double* theta, int N, double T, double P_orb, double L, double AU, double* out) {
-  Params p = mkp(T, P_orb, L, AU);
+void gbo_slow_series(const double* theta, int N, double T, double P_orb, double L, double AU, int tdi, double* out) {
+  Params p = mkp(T, P_orb, L, AU, tdi);
   const Source<double> s = make_source(theta);
   const int64_t q = (int64_t)std::floor(theta[0] * T);
   const double dfreq = theta[0] - (double)q / T;
@@ -421,8 +432,8 @@ void gbo_slow_series(const double* theta, int N, double T, double P_orb, double 
 
 // Templates of B sources: h_out[B][C][N] complex (interleaved), first_bin[B].
 void gbo_waveform(const double* theta, int64_t B, int N, int C, double T, double P_orb, double L,
-                  double AU, double* h_out, int64_t* first_bin, int nthreads) {
-  Params p = mkp(T, P_orb, L, AU);
+                  double AU, int tdi, double* h_out, int64_t* first_bin, int nthreads) {
+  Params p = mkp(T, P_orb, L, AU, tdi);
 #pragma omp parallel for schedule(dynamic, 4) num_threads(threads(nthreads))
   for (int64_t b = 0; b < B; ++b) {
     std::vector<Cx<double>> h[3];
@@ -438,9 +449,9 @@ void gbo_waveform(const double* theta, int64_t B, int N, int C, double T, double
 // logL of B candidates on one window (d: [C][W] complex interleaved, w: [C][W]);
 // comps (may be null): [B][2] = <d|h>, <h|h>.
 void gbo_loglik(const double* theta, int64_t B, int64_t k0, int W, int N, int C, const double* d,
-                const double* w, double T, double P_orb, double L, double AU, double* logL,
+                const double* w, double T, double P_orb, double L, double AU, int tdi, double* logL,
                 double* comps, int nthreads) {
-  Params p = mkp(T, P_orb, L, AU);
+  Params p = mkp(T, P_orb, L, AU, tdi);
 #pragma omp parallel for schedule(dynamic, 4) num_threads(threads(nthreads))
   for (int64_t b = 0; b < B; ++b) {
     double dh = 0.0, hh = 0.0;
@@ -455,9 +466,9 @@ void gbo_loglik(const double* theta, int64_t B, int64_t k0, int W, int N, int C,
 // logL and its gradient [B][8] with respect to (f0, fdot, beta, lambda, A, iota, psi, phi0),
 // by forward-mode dual numbers through every step above (q held fixed).
 void gbo_loglik_grad(const double* theta, int64_t B, int64_t k0, int W, int N, int C, const double* d,
-                     const double* w, double T, double P_orb, double L, double AU, double* logL,
+                     const double* w, double T, double P_orb, double L, double AU, int tdi, double* logL,
                      double* grad, int nthreads) {
-  Params p = mkp(T, P_orb, L, AU);
+  Params p = mkp(T, P_orb, L, AU, tdi);
 #pragma omp parallel for schedule(dynamic, 1) num_threads(threads(nthreads))
   for (int64_t b = 0; b < B; ++b) {
     Dual th[8];
@@ -470,8 +481,8 @@ void gbo_loglik_grad(const double* theta, int64_t B, int64_t k0, int W, int N, i
 
 // Jacobian of the template: jac[8][C][N] complex = d h / d theta_i (same bins as gbo_waveform).
 int64_t gbo_waveform_jacobian(const double* theta, int N, int C, double T, double P_orb, double L,
-                              double AU, double* jac) {
-  Params p = mkp(T, P_orb, L, AU);
+                              double AU, int tdi, double* jac) {
+  Params p = mkp(T, P_orb, L, AU, tdi);
   Dual th[8];
   for (int i = 0; i < 8; ++i) th[i] = seed(theta[i], i);
   std::vector<Cx<Dual>> h[3];
@@ -488,9 +499,9 @@ int64_t gbo_waveform_jacobian(const double* theta, int N, int C, double T, doubl
 // Fisher matrix F_ij = sum_c sum_k w Re(d_i h conj(d_j h)) over window bins k0..k0+W-1
 // (Sec. III G; the garbled "partial p(d|theta)" read as the template derivative).
 void gbo_fisher(const double* theta, int64_t k0, int W, int N, int C, const double* w, double T,
-                double P_orb, double L, double AU, double* F) {
+                double P_orb, double L, double AU, int tdi, double* F) {
   std::vector<double> jac((size_t)16 * C * N);
-  const int64_t fb = gbo_waveform_jacobian(theta, N, C, T, P_orb, L, AU, jac.data());
+  const int64_t fb = gbo_waveform_jacobian(theta, N, C, T, P_orb, L, AU, tdi, jac.data());
   for (int i = 0; i < 8; ++i)
     for (int j = 0; j < 8; ++j) {
       double acc = 0.0;

@@ -40,13 +40,13 @@ def _load():
         lib.gbo_max_threads.restype = i
         lib.gbo_spacecraft.argtypes = [d, d, d, d, _dp]
         lib.gbo_dft.argtypes = [_dp, i]
-        lib.gbo_slow_series.argtypes = [_dp, i, d, d, d, d, _dp]
-        lib.gbo_waveform.argtypes = [_dp, i64, i, i, d, d, d, d, _dp, _i64p, i]
-        lib.gbo_loglik.argtypes = [_dp, i64, i64, i, i, i, _dp, _dp, d, d, d, d, _dp, _dp, i]
-        lib.gbo_loglik_grad.argtypes = [_dp, i64, i64, i, i, i, _dp, _dp, d, d, d, d, _dp, _dp, i]
-        lib.gbo_waveform_jacobian.argtypes = [_dp, i, i, d, d, d, d, _dp]
+        lib.gbo_slow_series.argtypes = [_dp, i, d, d, d, d, i, _dp]
+        lib.gbo_waveform.argtypes = [_dp, i64, i, i, d, d, d, d, i, _dp, _i64p, i]
+        lib.gbo_loglik.argtypes = [_dp, i64, i64, i, i, i, _dp, _dp, d, d, d, d, i, _dp, _dp, i]
+        lib.gbo_loglik_grad.argtypes = [_dp, i64, i64, i, i, i, _dp, _dp, d, d, d, d, i, _dp, _dp, i]
+        lib.gbo_waveform_jacobian.argtypes = [_dp, i, i, d, d, d, d, i, _dp]
         lib.gbo_waveform_jacobian.restype = i64
-        lib.gbo_fisher.argtypes = [_dp, i64, i, i, i, _dp, d, d, d, d, _dp]
+        lib.gbo_fisher.argtypes = [_dp, i64, i, i, i, _dp, d, d, d, d, i, _dp]
         lib.gbo_mh_chain.argtypes = [_dp, _dp, _dp, i64, d, _i32p]
         lib.gbo_mh_chain.restype = i64
         _lib = lib
@@ -62,13 +62,15 @@ def _f64(a):
 
 
 class Geometry:
-    """Observation time and constellation constants of one run."""
+    """Observation time, constellation constants and TDI generation (1 or 2) of one run."""
 
-    def __init__(self, T: float, P_orb: float = I.YEAR, L: float = I.ARM_L, AU: float = I.AU):
-        self.T, self.P_orb, self.L, self.AU = float(T), float(P_orb), float(L), float(AU)
+    def __init__(self, T: float, P_orb: float = I.YEAR, L: float = I.ARM_L, AU: float = I.AU, tdi: int = 1):
+        if tdi not in (1, 2):
+            raise ValueError("tdi must be 1 or 2")
+        self.T, self.P_orb, self.L, self.AU, self.tdi = float(T), float(P_orb), float(L), float(AU), int(tdi)
 
     def args(self):
-        return (self.T, self.P_orb, self.L, self.AU)
+        return (self.T, self.P_orb, self.L, self.AU, self.tdi)
 
 
 def max_threads() -> int:
@@ -103,10 +105,10 @@ def waveform(theta: np.ndarray, N: int, C: int, g: Geometry, nthreads: int = 0):
     return h, fb
 
 
-def template_fn(P_orb: float = I.YEAR):
+def template_fn(P_orb: float = I.YEAR, tdi: int = 1):
     """Adapter for inputs.finalize_data: injections computed by the oracle."""
     def fn(theta, N, C, T):
-        return waveform(theta, N, C, Geometry(T, P_orb))
+        return waveform(theta, N, C, Geometry(T, P_orb, tdi=tdi))
     return fn
 
 
@@ -159,7 +161,7 @@ def mh_chain(logL, log_g, u, temperature: float):
 def loglik_workload(wl: "I.Workload", P_orb: float = I.YEAR, nthreads: int = 0, windows=None,
                     max_cand=None):
     """logL and components of every candidate of every (or the listed) window."""
-    g = Geometry(wl.T, P_orb)
+    g = Geometry(wl.T, P_orb, tdi=wl.tdi)
     outs, comps = [], []
     for i in (range(wl.n_win) if windows is None else windows):
         w = wl.windows[i]

@@ -35,7 +35,8 @@ class GbxError(RuntimeError):
 
 class gb_config(ctypes.Structure):
     _fields_ = [("T", ctypes.c_double), ("orbit_period", ctypes.c_double),
-                ("arm_length", ctypes.c_double), ("au", ctypes.c_double)]
+                ("arm_length", ctypes.c_double), ("au", ctypes.c_double),
+                ("tdi_generation", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class gb_window(ctypes.Structure):
@@ -129,8 +130,8 @@ def _real_view(t: torch.Tensor) -> torch.Tensor:
 
 
 # ------------------------------------------------------------------------------------------
-def gb_create(T: float, orbit_period: float, arm_length: float, au: float) -> int:
-    cfg = gb_config(T, orbit_period, arm_length, au)
+def gb_create(T: float, orbit_period: float, arm_length: float, au: float, tdi: int = 1) -> int:
+    cfg = gb_config(T, orbit_period, arm_length, au, int(tdi), 0)
     out = _vp()
     _check(lib().gb_create(ctypes.byref(cfg), ctypes.byref(out)), "gb_create")
     return out.value
@@ -413,11 +414,12 @@ def apply_tuning(ctx: int, report: str) -> int:
 
 # ------------------------------------------------------------------------------------------
 class Context:
-    """Owns a gb_ctx for one (T, orbit, arm length) setting on the current device."""
+    """Owns a gb_ctx for one (T, orbit, arm length, TDI generation) setting on the current device."""
 
-    def __init__(self, T: float, orbit_period: float, arm_length: float, au: float):
+    def __init__(self, T: float, orbit_period: float, arm_length: float, au: float, tdi: int = 1):
         self.T = float(T)
-        self.handle = gb_create(T, orbit_period, arm_length, au)
+        self.tdi = int(tdi)
+        self.handle = gb_create(T, orbit_period, arm_length, au, tdi)
 
     def waveform(self, theta: torch.Tensor, N: int, C: int, precision: int = GB_FP64, stream=None):
         return gb_waveform(self.handle, theta, N, C, precision, stream)
@@ -506,10 +508,10 @@ def loglik(plan: "Plan", theta: torch.Tensor) -> torch.Tensor:
     return LogLikelihood.apply(theta, plan)
 
 
-def context_for(T: float):
-    """Context with the synthetic setting's constellation constants."""
+def context_for(T: float, tdi: int = 1):
+    """Context with the synthetic setting's constellation constants (TDI generation 1 or 2)."""
     from . import inputs as I
-    return Context(T, I.YEAR, I.ARM_L, I.AU)
+    return Context(T, I.YEAR, I.ARM_L, I.AU, tdi)
 
 
 def template_fn(ctx: Context, precision: int = GB_FP64, device="cuda"):

@@ -177,8 +177,11 @@ extern "C" gb_status gb_create(const gb_config* cfg, gb_ctx** out) {
   if (!(cfg->T > 0) || !(cfg->orbit_period > 0) || !(cfg->arm_length > 0) || !(cfg->au > 0) ||
       !std::isfinite(cfg->T) || !std::isfinite(cfg->arm_length) || !std::isfinite(cfg->au))
     return fail(GB_EINVAL, "gb_create: T, orbit_period, arm_length and au must be positive and finite");
+  if (cfg->tdi_generation < 0 || cfg->tdi_generation > 2 || cfg->reserved != 0)
+    return fail(GB_EINVAL, "gb_create: tdi_generation must be 1 or 2 (0 means 1) and reserved 0");
   gb_ctx* c = new gb_ctx();
   c->cfg = *cfg;
+  if (c->cfg.tdi_generation == 0) c->cfg.tdi_generation = 1;
   hipError_t e = hipGetDevice(&c->device);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device);
   for (int i = 0; i < 5 && e == hipSuccess; ++i) {
@@ -223,6 +226,7 @@ static BatchArgs base_args(const gb_ctx* c, int N, int prec) {
   a.tw = prec == GB_FP64 ? (const void*)t.tw64 : (const void*)t.tw32;
   a.T = c->cfg.T;
   a.Lc = c->cfg.arm_length / kC;
+  a.tdi2 = c->cfg.tdi_generation == 2;
   return a;
 }
 

@@ -5,7 +5,9 @@
 //   plane wave H = Re[(A+ e+ - i Ax ex) e^{i Phi(t - k.x/c)}], Phi = 2 pi f0 t + pi fdot t^2 + phi0,
 //   single link (light s -> r over L):  z_rs = -i (pi f L/c) sinc(u_rs) (n.H.n)
 //                                          e^{i[Phi - 2 pi f (L/2 + k.(x_r + x_s)/2)/c]},
-//   first-generation TDI  X = (1 - D^2)[(z13 + D z31) - (z12 + D z21)], D = e^{-2 pi i f L/c},
+//   first-generation TDI  X = (1 - D^2)[(z13 + D z31) - (z12 + D z21)], D = e^{-2 pi i f L/c};
+//   second generation (equal arms): X2 = (1 - D^4) X, the eight further links being the copy of
+//   X delayed by four arm lengths with the opposite sign,
 //   A = (Z - X)/sqrt2, E = (X - 2Y + Z)/sqrt6, T = (X + Y + Z)/sqrt3  (Sec. II),
 //   slow series S(t_m) = response with the carrier e^{2 pi i q t/T} removed, q = floor(f0 T),
 //   template h(q + j) = T/(2N) DFT_N[S](j mod N), j in [-N/2, N/2).
@@ -207,7 +209,7 @@ __device__ __forceinline__ Cand<R> make_cand(const double* th, double T) {
 template <class R, int C>
 __device__ __forceinline__ void slow_sample(const Cand<R>& s, const double* __restrict__ ob64,
                                             const R* __restrict__ obR, int N, int m, double t,
-                                            double Lc, cplx<R> out[C]) {
+                                            double Lc, bool tdi2, cplx<R> out[C]) {
   // common phase in cycles (FP64), reduced to [-1/2, 1/2]
   const double f = s.f0 + s.fd * t;
   const double kR = s.kxd * ob64[OB_RX * N + m] + s.kyd * ob64[OB_RY * N + m];
@@ -276,7 +278,10 @@ __device__ __forceinline__ void slow_sample(const Cand<R>& s, const double* __re
   // K = (1 - D^2) (-i x) e^{2 pi i p}, with 1 - D^2 = -2i sin(-2 pi f L/c) D (no cancellation
   // at low frequency)
   const cplx<R> omd = mk<R>((R)2 * sD * sD, -((R)2 * cD * sD));
-  const cplx<R> K = scal(mul_mi(omd * mk<R>(cp, sp)), x);
+  cplx<R> K = scal(mul_mi(omd * mk<R>(cp, sp)), x);
+  // second generation: 1 - D^4 = 2i sin(4 pi f L/c) D^2 = -4i sD cD D^2 (no cancellation at low
+  // frequency either)
+  if (tdi2) K = K * mul_mi(scal(mk<R>(cD * cD - sD * sD, (R)2 * cD * sD), (R)4 * sD * cD));
   // the channels without their normalisations (chan_norm)
   out[0] = K * (Z - X);
   out[1] = K * (X - scal(Y, (R)2) + Z);
@@ -502,8 +507,8 @@ namespace gbx {
 template <class R, int C>
 __device__ __forceinline__ void grad_sample_rev(const Cand<R>& s, const CandG<R>& sg,
                                                 const double* __restrict__ ob64, const R* __restrict__ obR,
-                                                int N, int m, double t, double Lc, const cplx<R> sbar[C],
-                                                GradAcc& acc) {
+                                                int N, int m, double t, double Lc, bool tdi2,
+                                                const cplx<R> sbar[C], GradAcc& acc) {
   const R twopi = (R)(2.0 * kPi), pi = (R)kPi;
   const double f = s.f0 + s.fd * t;
   const double Rx = ob64[OB_RX * N + m], Ry = ob64[OB_RY * N + m];
@@ -517,8 +522,21 @@ __device__ __forceinline__ void grad_sample_rev(const Cand<R>& s, const CandG<R>
   const cplx<R> D = mk<R>(cDm, sDm);
   const R phiD = fr * (R)(2.0 * kPi * Lc);
   const R x = fr * (R)(kPi * Lc);
-  const R kappa = -(R)2 * x * sDm;                     // = phi_D sin(phi_D)
-  const cplx<R> Ep = D * mk<R>(cp, sp);                 // e^{i psi}
+  R kappa = -(R)2 * x * sDm;                           // = phi_D sin(phi_D)
+  cplx<R> Ep = D * mk<R>(cp, sp);                       // e^{i psi}
+  // amplitude and phase of K along f (below): d kappa/df and d psi/df
+  R dkappa_f = twopi * Lr * (-sDm + phiD * cDm);        // d(phi_D sin phi_D)/df
+  R dpsi_f = -twopi * ((R)1.5 * Lr + (R)kR);
+  if (tdi2) {
+    // second generation: K2 = K (1 - D^4) = K 2 sin(2 phi_D) i D^2, so kappa gains the factor
+    // g = 2 sin(2 phi_D) = -4 sDm cDm and psi the phase pi/2 - 2 phi_D
+    const R g = -(R)4 * sDm * cDm;
+    const R dg = (R)4 * (cDm * cDm - sDm * sDm) * twopi * Lr;   // 4 cos(2 phi_D) d phi_D/df
+    dkappa_f = dkappa_f * g + kappa * dg;
+    kappa = kappa * g;
+    Ep = mul_i(Ep * (D * D));
+    dpsi_f = dpsi_f - (R)2 * twopi * Lr;
+  }
   const cplx<R> K = scal(Ep, kappa);
   const R uR = s.u[0] * (R)Rx + s.u[1] * (R)Ry;
   const R vR = s.v[0] * (R)Rx + s.v[1] * (R)Ry;
@@ -604,9 +622,7 @@ __device__ __forceinline__ void grad_sample_rev(const Cand<R>& s, const CandG<R>
   const cplx<R> GU = K * QU, GV = K * QV;
 
   // amplitude and phase of K
-  const R dkappa_f = twopi * Lr * (-sDm + phiD * cDm);  // d(phi_D sin phi_D)/df
   const R EQre = (Ep * Q).x;
-  const R dpsi_f = -twopi * ((R)1.5 * Lr + (R)kR);
   const R dpsi_b = -twopi * fr * uR;
   const R dpsi_l = -twopi * fr * sg.cb * vR;
   R gf = EQre * dkappa_f - J.y * dpsi_f;

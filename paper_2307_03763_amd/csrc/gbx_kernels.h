@@ -40,6 +40,7 @@ struct BatchArgs {
   const void* tw;         // twiddles in the compute precision
   double T;
   double Lc;              // L / c
+  int tdi2;               // second-generation TDI
   int64_t B;              // MODE_WAVEFORM: number of templates
   double* h_out;          // MODE_WAVEFORM: complex128 [B][C][N]
   int64_t* first_bin;     // MODE_WAVEFORM: [B]
@@ -83,7 +84,7 @@ __device__ __forceinline__ void template_to_lds(const Cand<R>& s, const BatchArg
     const int m = lane + LPC * e;
     const double t = a.T * (double)m / (double)N;
     cplx<R> o[C];
-    slow_sample<R, C>(s, a.ob64, obR, N, m, t, a.Lc, o);
+    slow_sample<R, C>(s, a.ob64, obR, N, m, t, a.Lc, a.tdi2 != 0, o);
 #pragma unroll
     for (int c = 0; c < C; ++c) buf[c * N + m] = o[c];
   }
@@ -190,7 +191,7 @@ __device__ __forceinline__ void process_grad(const BatchArgs& a, const DevWin& w
     cplx<R> sbar[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) sbar[c] = buf[c * N + m];
-    grad_sample_rev<R, C>(s, sg, a.ob64, obR, N, m, t, a.Lc, sbar, ga);
+    grad_sample_rev<R, C>(s, sg, a.ob64, obR, N, m, t, a.Lc, a.tdi2 != 0, sbar, ga);
   };
 #pragma unroll 1
   for (int e = 0; e < E; ++e) sample(e);

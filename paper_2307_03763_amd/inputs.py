@@ -63,13 +63,16 @@ def psd_single_link(f):
     return s_acc_ff, s_oms_ff
 
 
-def psd_aet(f, arm_length: float = ARM_L):
-    """One-sided noise PSDs (S_A = S_E, S_T) of the first-generation equal-arm A, E, T.
+def psd_aet(f, arm_length: float = ARM_L, tdi: int = 1):
+    """One-sided noise PSDs (S_A = S_E, S_T) of the equal-arm A, E, T of TDI generation 1 or 2.
 
     Link noises are independent; the A/E/T combinations of Sec. II diagonalise their
-    covariance.  With x = 2 pi f L / c:
+    covariance.  With x = 2 pi f L / c, first generation:
       S_A = 8 sin^2 x [(2 + cos x) S_oms + 2 (3 + 2 cos x + cos 2x) S_acc]
       S_T = 32 sin^2 x sin^2(x/2) [S_oms + 4 sin^2(x/2) S_acc]
+    The second-generation combinations with equal arms are the first-generation ones minus
+    their copy delayed by four arm lengths, which multiplies both PSDs by |1 - e^{-4ix}|^2
+    = 4 sin^2(2x).
     """
     f = np.asarray(f, dtype=np.float64)
     s_acc, s_oms = psd_single_link(f)
@@ -78,13 +81,16 @@ def psd_aet(f, arm_length: float = ARM_L):
     s_a = 8.0 * sx2 * ((2.0 + np.cos(x)) * s_oms + 2.0 * (3.0 + 2.0 * np.cos(x) + np.cos(2 * x)) * s_acc)
     sh2 = np.sin(x / 2.0) ** 2
     s_t = 32.0 * sx2 * sh2 * (s_oms + 4.0 * sh2 * s_acc)
+    if tdi == 2:
+        g2 = 4.0 * np.sin(2.0 * x) ** 2
+        s_a, s_t = s_a * g2, s_t * g2
     return s_a, s_t
 
 
-def channel_psd(k0: int, W: int, C: int, T: float, arm_length: float = ARM_L) -> np.ndarray:
+def channel_psd(k0: int, W: int, C: int, T: float, arm_length: float = ARM_L, tdi: int = 1) -> np.ndarray:
     """PSD per channel and window bin, shape [C, W]; bins k0..k0+W-1 at f = k / T."""
     f = (k0 + np.arange(W, dtype=np.float64)) / T
-    s_a, s_t = psd_aet(f, arm_length)
+    s_a, s_t = psd_aet(f, arm_length, tdi)
     rows = [s_a, s_a] + ([s_t] if C == 3 else [])
     return np.stack(rows[:C])
 
@@ -278,6 +284,7 @@ class Workload:
     weights: Optional[np.ndarray] = None   # float64, same layout
     data_off: Optional[np.ndarray] = None  # [n_win] offsets (in elements) into data/weights
     psd: Optional[np.ndarray] = None
+    tdi: int = 1                           # TDI generation of the data (noise PSD and injections)
 
     @property
     def n_win(self) -> int:
@@ -328,7 +335,7 @@ def finalize_data(wl: Workload, template_fn: Optional[TemplateFn], rng_noise, no
     blocks_d, blocks_w, blocks_s = [], [], []
     o = 0
     for w in wl.windows:
-        psd = channel_psd(w.k0, w.W, w.C, wl.T)
+        psd = channel_psd(w.k0, w.W, w.C, wl.T, tdi=wl.tdi)
         d = np.zeros((w.C, w.W), dtype=np.complex128)
         if template_fn is not None and len(w.sources):
             srcs = w.sources

@@ -40,6 +40,9 @@ def test_argument_validation_without_device():
     assert b"config" in L.gb_last_error()
     bad = api.gb_config(-1.0, 1.0, 1.0, 1.0)
     assert L.gb_create(ctypes.byref(bad), ctypes.byref(out)) == api.GB_EINVAL and out.value is None
+    bad = api.gb_config(1.0, 1.0, 1.0, 1.0, 3, 0)
+    assert L.gb_create(ctypes.byref(bad), ctypes.byref(out)) == api.GB_EINVAL and out.value is None
+    assert b"tdi_generation" in L.gb_last_error()
     assert L.gb_plan_create(None, None, 0, 0, ctypes.byref(out)) == api.GB_EINVAL
     assert L.gb_waveform(None, None, 1, 128, 2, 0, None, None, None) == api.GB_EINVAL
     assert L.gb_loglik(None, None, None, None, None, None, None) == api.GB_EINVAL
@@ -51,7 +54,7 @@ def test_argument_validation_without_device():
 
 def test_struct_layouts_match_header():
     from paper_2307_03763_amd import api
-    assert ctypes.sizeof(api.gb_config) == 32
+    assert ctypes.sizeof(api.gb_config) == 40 and api.gb_config.tdi_generation.offset == 32
     assert ctypes.sizeof(api.gb_window) == 48
     assert api.gb_window.data_off.offset == 24 and api.gb_window.n_cand.offset == 40
 

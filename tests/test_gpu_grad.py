@@ -52,7 +52,7 @@ def _workload(oracle_lib, C, f_lo=12e-3, f_span=4e-3):
 def _scales(O, wl, i, th, comps_hh):
     w = wl.windows[i]
     _, ww = wl.window_data(i)
-    g = O.Geometry(wl.T)
+    g = O.Geometry(wl.T, tdi=wl.tdi)
     dd = float(np.sum(ww * np.abs(wl.window_data(i)[0]) ** 2))
     out = []
     for b in range(len(th)):
