@@ -413,6 +413,47 @@ def apply_tuning(ctx: int, report: str) -> int:
 
 
 # ------------------------------------------------------------------------------------------
+# Destruction during a HIP-graph capture.  gb_destroy and gb_plan_destroy free device memory,
+# and a free while a stream is being captured invalidates the capture.  A capture may see such a
+# destruction without asking for it: the cyclic garbage collector can collect an unreferenced
+# Plan or Context at any allocation, including one inside the captured body.  So while a
+# capture is open (capturing()), the destructors queue their frees; the outermost capture runs
+# them when it closes.
+_capture_depth = 0
+_deferred = []
+
+
+class capturing:
+    """Context manager around a HIP-graph capture: Plan and Context destruction inside it is
+    deferred to its end (nested captures count, the outermost one runs the queue)."""
+
+    def __enter__(self):
+        global _capture_depth
+        _capture_depth += 1
+        return self
+
+    def __exit__(self, *exc):
+        global _capture_depth
+        _capture_depth -= 1
+        if _capture_depth == 0:
+            release_deferred()
+        return False
+
+
+def release_deferred():
+    """Run the frees queued during captures (a no-op while a capture is still open)."""
+    while _deferred and _capture_depth == 0:
+        fn, handle = _deferred.pop(0)
+        fn(handle)
+
+
+def _release(fn, handle):
+    if _capture_depth > 0:
+        _deferred.append((fn, handle))
+    else:
+        fn(handle)
+
+
 class Context:
     """Owns a gb_ctx for one (T, orbit, arm length, TDI generation) setting on the current device."""
 
@@ -426,7 +467,7 @@ class Context:
 
     def close(self):
         if self.handle:
-            gb_destroy(self.handle)
+            _release(gb_destroy, self.handle)
             self.handle = 0
 
     def __del__(self):
@@ -475,7 +516,7 @@ class Plan:
 
     def close(self):
         if self.handle:
-            gb_plan_destroy(self.handle)
+            _release(gb_plan_destroy, self.handle)
             self.handle = 0
 
     def __del__(self):

@@ -227,23 +227,19 @@ def _de_converged(s, tol: float) -> np.ndarray:
     return np.isfinite(m) & (s.std(axis=1) <= tol * np.abs(m))
 
 
-def _capture_graph(torch, gr, stream, body):
-    """Record body() into the HIP graph gr on stream.
+# Capture mode of every graph the drivers record: "global", so that a call from any thread that
+# is unsafe during a capture (an allocation, a free, a synchronisation) is reported at once.
+CAPTURE_MODE = "global"
 
-    The capture runs in relaxed mode, so no call outside the captured stream can invalidate it.
-    The cyclic garbage collector is held off while it runs: torch.cuda.graph collects garbage
-    just before the capture starts, and a later collection could otherwise destroy an
-    unreferenced plan or context inside the capture, whose device frees would interfere with
-    it."""
-    import gc
-    enabled = gc.isenabled()
-    gc.disable()
-    try:
-        with torch.cuda.graph(gr, stream=stream, capture_error_mode="relaxed"):
+
+def _capture_graph(torch, gr, stream, body):
+    """Record body() into the HIP graph gr on stream, in CAPTURE_MODE.  Plans and contexts
+    destroyed while it runs (by the cyclic garbage collector, for instance) free their device
+    memory after the capture (api.capturing), not inside it."""
+    from . import api
+    with api.capturing():
+        with torch.cuda.graph(gr, stream=stream, capture_error_mode=CAPTURE_MODE):
             body()
-    finally:
-        if enabled:
-            gc.enable()
 
 
 # Share of the device DE batch that must have converged before the converged windows leave it:

@@ -161,3 +161,51 @@ def test_de_convergence_stop(c1):
     assert hist.shape == (401, 1) and np.all(np.diff(hist[:, 0]) >= 0)
     assert hist[-1, 0] == hist[-150, 0]            # stopped well before the last generation
     assert abs(th[0, 0, 0] - src[0]) * wl.T < 1.0
+
+
+def test_destruction_inside_a_capture_is_deferred(monkeypatch):
+    """Plans and contexts destroyed while a graph capture is open (as the cyclic collector may do
+    at any allocation inside the captured body) queue their device frees until the outermost
+    capture closes; outside a capture they free at once.  Checked with a stand-in library that
+    records the calls."""
+    import ctypes
+    import gc
+
+    from paper_2307_03763_amd import api
+
+    calls = []
+
+    class Stub:
+        def gb_create(self, cfg, out):
+            out._obj.value = 0x1000
+            return 0
+
+        def gb_plan_create(self, ctx, wins, n, prec, out):
+            out._obj.value = 0x2000 + len(calls)
+            return 0
+
+        def gb_plan_destroy(self, h):
+            calls.append(("plan", h))
+
+        def gb_destroy(self, h):
+            calls.append(("ctx", h))
+
+    monkeypatch.setattr(api, "lib", lambda: Stub())
+    table = [[1000, 64, 64, 2, 0, 0, 0, 4]]
+    ctx = api.Context(1.0, 1.0, 1.0, 1.0)
+    p0 = api.Plan(ctx, table, api.GB_MIXED)
+    del p0
+    gc.collect()
+    assert calls == [("plan", 0x2000)]                 # no capture: freed at once
+    p1 = api.Plan(ctx, table, api.GB_MIXED)
+    with api.capturing():
+        with api.capturing():                          # nested captures
+            p2 = api.Plan(ctx, table, api.GB_MIXED)
+            del p1, p2
+            gc.collect()
+            ctx.close()
+        assert calls == [("plan", 0x2000)]             # still inside the outer capture
+    assert sorted(c[0] for c in calls[1:]) == ["ctx", "plan", "plan"]
+    assert api._deferred == [] and api._capture_depth == 0
+    from paper_2307_03763_amd import drivers as D
+    assert D.CAPTURE_MODE == "global"

@@ -146,8 +146,11 @@ def test_device_de_graph_matches_eager(oracle_lib):
     """The device DE replayed from captured HIP graphs against the same DE launched eagerly. Both
     consume the same draws, so populations, scores and the whole history must agree bit for bit,
     over many chunk replays with eager host work (the convergence checks) between them,
-    compactions with re-captures, and a partial last chunk run eagerly."""
+    compactions with re-captures, and a partial last chunk run eagerly.  The chunks are captured
+    in global mode, where any unsafe call during the capture fails it."""
     banner("device DE: HIP-graph chunks vs eager launches")
+    from paper_2307_03763_amd import drivers as D
+    assert D.CAPTURE_MODE == "global"
     from tests.test_search_cpu import segments_workload
     wl, seg = segments_workload(oracle_lib)
     ctx = api.context_for(wl.T)

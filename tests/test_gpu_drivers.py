@@ -100,8 +100,11 @@ def test_polish_gpu_mixed_gradient(env):
 
 @pytest.mark.parametrize("graph", [False, True])
 def test_posterior_stage(env, graph):
+    """One MH stage (draw, gb_mh_step, chain) eager and captured in a HIP graph in global capture
+    mode, where any unsafe call during the capture fails it."""
     banner(f"drivers: posterior stage on C1, graph={graph}")
     api, D, I, O, wl = env["api"], env["D"], env["I"], env["O"], env["c1"]
+    assert D.CAPTURE_MODE == "global"
     n = 4096
     _, ctx, d_t, w_t, tab = _gpu_backend(api, D, wl, [0], api.GB_FP64)
     row = tab[0].copy()
