@@ -210,6 +210,48 @@ gb_status gb_add_templates(gb_ctx* ctx, const gb_window* windows, int n_win, con
 gb_status gb_noise_estimate(const gb_window* windows, int n_win, const double* d, double T, double* w, double* S,
                             void* stream);
 
+/* Settings of the global noise estimate (host memory); the values of Sec. III F in brackets. */
+typedef struct {
+  double dt;             /* sampling interval of the data's time series, s; M = T / dt samples,
+                            a power of two in [2^20, 2^22] [15 s] */
+  double f_switch;       /* Savitzky-Golay switch frequency, Hz [0.8e-3] */
+  int32_t nperseg;       /* Welch segment length L: 8192 or 16384 [16384: 2 M / L - 1 = 511
+                            segments at M = 2^22, the paper's 500 windows] */
+  int32_t clip_width;    /* median-clip window, Welch bins, at most 64 [30] */
+  int32_t clip_stride;   /* its shift [15] */
+  int32_t sg_short;      /* Savitzky-Golay window length below f_switch [10] */
+  int32_t sg_long;       /* and above [70; 50 for T = 0.5 yr] */
+  int32_t reserved;      /* must be 0 */
+} gb_noise_global_config;
+
+/* Global noise estimate of Sec. III F from a residual d (the data minus the recovered signals;
+ * with d - s_partial sum s, Sec. III G, the partial-residual estimate), for every window and
+ * channel at once:
+ *  1. per channel, the one-sided spectrum of the band assembled from the segments seg (host
+ *     int64 [n_win][2], absolute bins [lo, hi) inside the window and inside [1, M/2); the
+ *     segments of a channel must not overlap; zero where none is), transformed to the time
+ *     series x_n = (1/T) sum_k d_k e^{2 pi i k n / M} (inverse of the convention of the
+ *     templates) by a four-step inverse DFT;
+ *  2. Welch's method: periodic Hann windows of L = nperseg samples at 50% overlap (2M/L - 1
+ *     segments), one-sided density P_j = 2 dt / sum w^2 * mean |DFT(w x)_j|^2 (DC and Nyquist not
+ *     doubled) at f_j = j / (L dt);
+ *  3. over the channel's band (the Welch bins inside its segments), the median clip: windows of
+ *     clip_width bins shifted by clip_stride, in order, values above twice the window's median set
+ *     to twice the median;
+ *  4. Savitzky-Golay of order 1: window sg_short below f_switch and sg_long above (interior: the
+ *     window mean; the first and last length/2 points from the line fitted to the end windows);
+ *  5. the natural cubic spline through the smoothed band, evaluated at every bin of every window
+ *     (held at its end values outside the band), S, and the weights w = 4 / (T S).
+ * windows: host [n_win] (k0, W, C, data_off used; at most 65535); d: device complex128; w: device
+ * float64 (d's layout, every window's C x W block written); S: device, same layout, or NULL;
+ * welch, smooth: device [3][L/2 + 1] or NULL (step 2 and step 4 of each channel; smooth is zero
+ * outside the band; rows of absent channels zero).  All FP64.  Synchronous; allocates about
+ * 40 M bytes of temporaries.  GB_EINVAL on a bad setting, window, segment or a band narrower than
+ * the filter windows. */
+gb_status gb_noise_global(const gb_window* windows, const int64_t* seg, int n_win, const double* d, double T,
+                          const gb_noise_global_config* cfg, double* w, double* S, double* welch, double* smooth,
+                          void* stream);
+
 /* gb_noise_estimate without any device allocation, for callers that cannot allocate device
  * memory (tight search loops that re-estimate the noise after every found signal, code that
  * must not call hipMalloc).  Same arguments, results and synchronous behaviour as

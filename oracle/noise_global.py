@@ -45,9 +45,7 @@ def assemble(d: np.ndarray, seg, windows, data_off, M: int, c: int) -> np.ndarra
             continue
         lo, hi = int(seg[i][0]), int(seg[i][1])
         block = d[int(data_off[i]) + c * W: int(data_off[i]) + (c + 1) * W]
-        for k in range(lo, hi):
-            if 0 <= k <= M // 2:
-                X[k] = block[k - k0]
+        X[lo:hi] = block[lo - k0:hi - k0]
     return X
 
 

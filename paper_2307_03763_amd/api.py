@@ -24,7 +24,7 @@ PRECISION = {"fp64": GB_FP64, "mixed": GB_MIXED, "per_window": GB_PER_WINDOW}
 EXPORTS = ("gb_create", "gb_destroy", "gb_last_error", "gb_waveform", "gb_plan_create",
            "gb_plan_destroy", "gb_plan_info", "gb_window_prepare", "gb_loglik", "gb_loglik_grad", "gb_mh_step",
            "gb_autotune", "gb_select_variant", "gb_fisher", "gb_kde_logpdf", "gb_add_templates",
-           "gb_noise_estimate", "gb_noise_estimate_noalloc", "gb_de_trial", "gb_de_select")
+           "gb_noise_estimate", "gb_noise_estimate_noalloc", "gb_noise_global", "gb_de_trial", "gb_de_select")
 
 
 class GbxError(RuntimeError):
@@ -37,6 +37,12 @@ class gb_config(ctypes.Structure):
     _fields_ = [("T", ctypes.c_double), ("orbit_period", ctypes.c_double),
                 ("arm_length", ctypes.c_double), ("au", ctypes.c_double),
                 ("tdi_generation", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class gb_noise_global_config(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("f_switch", ctypes.c_double), ("nperseg", ctypes.c_int32),
+                ("clip_width", ctypes.c_int32), ("clip_stride", ctypes.c_int32), ("sg_short", ctypes.c_int32),
+                ("sg_long", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class gb_window(ctypes.Structure):
@@ -93,6 +99,9 @@ def lib():
         L.gb_noise_estimate.restype = st
         L.gb_noise_estimate_noalloc.argtypes = [ctypes.POINTER(gb_window), i, _vp, d, _vp, _vp, _vp]
         L.gb_noise_estimate_noalloc.restype = st
+        L.gb_noise_global.argtypes = [ctypes.POINTER(gb_window), ctypes.POINTER(ctypes.c_int64), i, _vp, d,
+                                      ctypes.POINTER(gb_noise_global_config), _vp, _vp, _vp, _vp, _vp]
+        L.gb_noise_global.restype = st
         L.gb_de_trial.argtypes = [i, i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, d, d, _vp, _vp, _vp]
         L.gb_de_trial.restype = st
         L.gb_de_select.argtypes = [i, i, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
@@ -328,6 +337,35 @@ def gb_noise_estimate_noalloc(table, d: torch.Tensor, T: float, w: torch.Tensor,
                                            _dev(w, torch.float64, "w"),
                                            None if S is None else _dev(S, torch.float64, "S"), _stream(stream)),
            "gb_noise_estimate_noalloc")
+
+
+def gb_noise_global(table, seg, d: torch.Tensor, T: float, dt: float = 15.0, nperseg: int = 16384,
+                    clip_width: int = 30, clip_stride: int = 15, sg_short: int = 10, sg_long: int = 70,
+                    f_switch: float = 0.8e-3, w: Optional[torch.Tensor] = None, S: bool = True,
+                    stages: bool = False, stream=None):
+    """Global noise estimate of the residual d (window layout of ``table``) over the segments
+    ``seg`` ([n_win, 2] absolute bins [lo, hi) per window).  Returns (w, S or None, welch or None,
+    smooth or None): the weights 4 / (T S) and the estimate S in d's layout, and with
+    ``stages`` the Welch and smoothed curves [3, nperseg/2 + 1]."""
+    wins = windows_array(table)
+    sg = np.ascontiguousarray(np.asarray(seg, dtype=np.int64).reshape(len(wins), 2))
+    n = _data_len(wins)
+    _check_len(d, n, "d")
+    if w is None:
+        w = torch.zeros(d.shape, dtype=torch.float64, device=d.device)
+    _check_len(w, n, "w")
+    s_t = torch.zeros(d.shape, dtype=torch.float64, device=d.device) if S else None
+    nb = nperseg // 2 + 1
+    wl = torch.zeros((3, nb), dtype=torch.float64, device=d.device) if stages else None
+    sm = torch.zeros((3, nb), dtype=torch.float64, device=d.device) if stages else None
+    cfg = gb_noise_global_config(float(dt), float(f_switch), int(nperseg), int(clip_width), int(clip_stride),
+                                 int(sg_short), int(sg_long), 0)
+    opt = lambda t, name: None if t is None else _dev(t, torch.float64, name)
+    _check(lib().gb_noise_global(wins, sg.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(wins),
+                                 _dev(d, torch.complex128, "d"), float(T), ctypes.byref(cfg),
+                                 _dev(w, torch.float64, "w"), opt(s_t, "S"), opt(wl, "welch"), opt(sm, "smooth"),
+                                 _stream(stream)), "gb_noise_global")
+    return w, s_t, wl, sm
 
 
 def gb_de_trial(lo: torch.Tensor, hi: torch.Tensor, x: torch.Tensor, u_idx: torch.Tensor, u_cross: torch.Tensor,

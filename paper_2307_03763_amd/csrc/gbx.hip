@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -16,6 +17,7 @@
 #include "gbx_chain.h"
 #include "gbx_post.h"
 #include "gbx_noise.h"
+#include "gbx_noise_global.h"
 #include "gbx_de.h"
 #include "gbx_variants.h"
 
@@ -705,6 +707,153 @@ extern "C" gb_status gb_noise_estimate(const gb_window* windows, int n_win, cons
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   (void)hipFree(d_nw);
   if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? GB_ENOMEM : GB_EHIP, "gb_noise_estimate: %s", hipGetErrorString(e));
+  return GB_OK;
+}
+
+// ------------------------------------------------------------------------------- global noise estimate
+namespace {
+
+template <int NF>
+void launch_ifft_a(const double* Y, double* Z, const double* tw, int64_t M1, hipStream_t st) {
+  hipLaunchKernelGGL(k_ifft_a<NF>, dim3((unsigned)M1), dim3(NF / 8), 0, st, Y, Z, tw, M1);
+}
+
+constexpr int kIfftM1 = 2048;  // pass-B length of the four-step inverse DFT
+
+}  // namespace
+
+extern "C" gb_status gb_noise_global(const gb_window* windows, const int64_t* seg, int n_win, const double* d,
+                                     double T, const gb_noise_global_config* cfg, double* w, double* S,
+                                     double* welch, double* smooth, void* stream) {
+  if (!cfg || !windows || !seg || !d || !w || n_win < 1 || n_win > 65535)
+    return fail(GB_EINVAL, "gb_noise_global: null arguments or n_win outside 1..65535");
+  const double dt = cfg->dt;
+  if (!(T > 0.0) || !std::isfinite(T) || !(dt > 0.0) || !std::isfinite(dt))
+    return fail(GB_EINVAL, "gb_noise_global: T and dt must be positive and finite");
+  const int64_t M = (int64_t)std::llround(T / dt);
+  if (M < (1 << 20) || M > (1 << 22) || (M & (M - 1)) || std::fabs((double)M * dt - T) > 1e-9 * T)
+    return fail(GB_EINVAL, "gb_noise_global: T / dt must be a power of two in [2^20, 2^22]");
+  const int L = cfg->nperseg;
+  if (L != 8192 && L != 16384) return fail(GB_EINVAL, "gb_noise_global: nperseg must be 8192 or 16384");
+  if (cfg->clip_width < 1 || cfg->clip_width > 64 || cfg->clip_stride < 1 || cfg->sg_short < 1 ||
+      cfg->sg_long < 1 || !(cfg->f_switch >= 0.0) || cfg->reserved != 0)
+    return fail(GB_EINVAL, "gb_noise_global: clip width 1..64, stride >= 1, filter lengths >= 1, f_switch >= 0");
+  const int NF = L / 2;
+  const int64_t M2 = M / kIfftM1;
+  const int K = (int)(2 * M / L - 1);
+  const int64_t pitch = NF + 1;
+  // windows, segments, bands
+  std::vector<SegWin> sw(n_win);
+  int64_t band_lo[3] = {INT64_MAX, INT64_MAX, INT64_MAX}, band_hi[3] = {0, 0, 0};
+  int64_t max_cw = 0;
+  for (int i = 0; i < n_win; ++i) {
+    const gb_window& g = windows[i];
+    const int64_t lo = seg[2 * i], hi = seg[2 * i + 1];
+    if ((g.C != 2 && g.C != 3) || g.W < 1 || g.data_off < 0 || g.k0 < 0)
+      return fail(GB_EINVAL, "gb_noise_global: window %d: C must be 2 or 3, W >= 1, offsets >= 0", i);
+    if (!(lo < hi) || lo < g.k0 || hi > g.k0 + g.W || lo < 1 || hi > M / 2)
+      return fail(GB_EINVAL, "gb_noise_global: window %d: segment [%lld, %lld) must lie inside the window and "
+                  "inside [1, M/2)", i, (long long)lo, (long long)hi);
+    sw[i] = SegWin{g.k0, g.data_off, lo, hi, g.W, g.C};
+    max_cw = std::max(max_cw, (int64_t)g.C * g.W);
+    for (int c = 0; c < g.C; ++c) {
+      band_lo[c] = std::min(band_lo[c], lo);
+      band_hi[c] = std::max(band_hi[c], hi);
+    }
+  }
+  // the segments of one channel must not overlap (each bin has one owner)
+  for (int c = 0; c < 3; ++c) {
+    std::vector<std::pair<int64_t, int64_t>> r;
+    for (const SegWin& x : sw)
+      if (c < x.C) r.emplace_back(x.lo, x.hi);
+    std::sort(r.begin(), r.end());
+    for (size_t k = 1; k < r.size(); ++k)
+      if (r[k].first < r[k - 1].second) return fail(GB_EINVAL, "gb_noise_global: overlapping segments in channel %d", c);
+  }
+  int h_lo[3] = {0, 0, 0}, h_n[3] = {0, 0, 0};
+  const int wl_max = std::max(std::max(cfg->sg_short, cfg->sg_long), 3);
+  for (int c = 0; c < 3; ++c) {
+    if (band_hi[c] == 0) continue;
+    const int64_t j_lo = (band_lo[c] * L + M - 1) / M, j_hi = ((band_hi[c] - 1) * L) / M;
+    h_lo[c] = (int)j_lo;
+    h_n[c] = (int)(j_hi - j_lo + 1);
+    if (h_n[c] < wl_max) return fail(GB_EINVAL, "gb_noise_global: channel %d: the band holds %d Welch bins, fewer "
+                                     "than the filter window %d", c, h_n[c], wl_max);
+  }
+  // Hann window and its sum of squares (periodic: w_n = 1/2 - 1/2 cos(2 pi n / L))
+  std::vector<double> hann(L);
+  double ssq = 0.0;
+  for (int n = 0; n < L; ++n) {
+    hann[n] = 0.5 - 0.5 * std::cos(2.0 * kPi * (double)n / (double)L);
+    ssq += hann[n] * hann[n];
+  }
+  hipStream_t st = (hipStream_t)stream;
+  double *Y = nullptr, *Z = nullptr, *x = nullptr, *Pseg = nullptr, *P = nullptr, *Pc = nullptr, *Sm = nullptr,
+         *mm = nullptr, *dg = nullptr, *twA = nullptr, *twB = nullptr, *twW = nullptr, *d_hann = nullptr;
+  SegWin* d_sw = nullptr;
+  int *d_lo = nullptr, *d_n = nullptr;
+  hipError_t e = hipSuccess;
+  auto mal = [&](void** p, size_t bytes) {
+    if (e == hipSuccess) e = hipMalloc(p, bytes);
+  };
+  mal((void**)&Y, sizeof(double) * 2 * M);
+  mal((void**)&Z, sizeof(double) * 2 * M);
+  mal((void**)&x, sizeof(double) * M);
+  mal((void**)&Pseg, sizeof(double) * (size_t)K * pitch);
+  for (double** q : {&P, &Pc, &Sm, &mm, &dg}) mal((void**)q, sizeof(double) * 3 * pitch);
+  mal((void**)&twA, sizeof(double) * 2 * M2);
+  mal((void**)&twB, sizeof(double) * 2 * kIfftM1);
+  mal((void**)&twW, sizeof(double) * 2 * NF);
+  mal((void**)&d_hann, sizeof(double) * L);
+  mal((void**)&d_sw, sizeof(SegWin) * n_win);
+  mal((void**)&d_lo, sizeof(int) * 3);
+  mal((void**)&d_n, sizeof(int) * 3);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_hann, hann.data(), sizeof(double) * L, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_sw, sw.data(), sizeof(SegWin) * n_win, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_lo, h_lo, sizeof(h_lo), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_n, h_n, sizeof(h_n), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_twiddle64, dim3((unsigned)((M2 + 255) / 256)), dim3(256), 0, st, twA, (int)M2);
+    hipLaunchKernelGGL(k_twiddle64, dim3(kIfftM1 / 256), dim3(256), 0, st, twB, kIfftM1);
+    hipLaunchKernelGGL(k_twiddle64, dim3((unsigned)(NF / 256)), dim3(256), 0, st, twW, NF);
+    for (double* q : {P, Sm})
+      hipLaunchKernelGGL(k_fill_zero, dim3(64), dim3(256), 0, st, q, (int64_t)3 * pitch);
+    e = hipGetLastError();
+  }
+  for (int c = 0; c < 3 && e == hipSuccess; ++c) {
+    if (h_n[c] == 0) continue;
+    hipLaunchKernelGGL(k_fill_zero, dim3(1024), dim3(256), 0, st, Y, 2 * M);
+    hipLaunchKernelGGL(k_assemble, dim3((unsigned)n_win), dim3(256), 0, st, d_sw, d, c, M, Y);
+    if (M2 == 512) launch_ifft_a<512>(Y, Z, twA, kIfftM1, st);
+    else if (M2 == 1024) launch_ifft_a<1024>(Y, Z, twA, kIfftM1, st);
+    else launch_ifft_a<2048>(Y, Z, twA, kIfftM1, st);
+    hipLaunchKernelGGL(k_ifft_b<kIfftM1>, dim3((unsigned)M2), dim3(kIfftM1 / 8), 0, st, Z, x, twB, M2, 1.0 / T);
+    if (NF == 8192)
+      hipLaunchKernelGGL(k_welch_seg<8192>, dim3((unsigned)K), dim3(1024), 0, st, x, d_hann, twW, Pseg);
+    else
+      hipLaunchKernelGGL(k_welch_seg<4096>, dim3((unsigned)K), dim3(512), 0, st, x, d_hann, twW, Pseg);
+    hipLaunchKernelGGL(k_welch_mean, dim3((unsigned)((pitch + 255) / 256)), dim3(256), 0, st, Pseg, K, (int)pitch,
+                       2.0 * dt / ssq, P + c * pitch);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    const int nmax = std::max(h_n[0], std::max(h_n[1], h_n[2]));
+    hipLaunchKernelGGL(k_median_clip, dim3(3), dim3(64), 0, st, P, Pc, pitch, d_lo, d_n, cfg->clip_width,
+                       cfg->clip_stride);
+    hipLaunchKernelGGL(k_savgol, dim3((unsigned)((nmax + 255) / 256), 3), dim3(256), 0, st, Pc, Sm, pitch, d_lo, d_n,
+                       L, dt, cfg->f_switch, cfg->sg_short, cfg->sg_long);
+    hipLaunchKernelGGL(k_spline_m, dim3(3), dim3(64), 0, st, Sm, mm, dg, pitch, d_lo, d_n);
+    hipLaunchKernelGGL(k_spline_eval, dim3((unsigned)((max_cw + 255) / 256), (unsigned)n_win), dim3(256), 0, st, d_sw,
+                       Sm, mm, pitch, d_lo, d_n, (int64_t)(M / L), T, w, S);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess && welch) e = hipMemcpyAsync(welch, P, sizeof(double) * 3 * pitch, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess && smooth) e = hipMemcpyAsync(smooth, Sm, sizeof(double) * 3 * pitch, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  for (void* q : {(void*)Y, (void*)Z, (void*)x, (void*)Pseg, (void*)P, (void*)Pc, (void*)Sm, (void*)mm, (void*)dg,
+                  (void*)twA, (void*)twB, (void*)twW, (void*)d_hann, (void*)d_sw, (void*)d_lo, (void*)d_n})
+    (void)hipFree(q);
+  if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? GB_ENOMEM : GB_EHIP, "gb_noise_global: %s", hipGetErrorString(e));
   return GB_OK;
 }
 
