@@ -71,6 +71,7 @@ def parse():
     ap.add_argument("--rho-mixed", type=float, default=8.0)
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-posterior", action="store_true")
+    ap.add_argument("--no-configs", action="store_true", help="skip the throughput of C1, C2, C4 and C5")
     ap.add_argument("--posterior-sources", type=int, default=3)
     ap.add_argument("--no-pipeline", action="store_true")
     ap.add_argument("--pipeline-segments", type=int, nargs=2, default=(2000, 3000), metavar=("FIRST", "END"),
@@ -351,6 +352,10 @@ def main():
         for p in win_plans:
             p.close()
 
+    cfgs = None
+    if not args.no_configs:
+        cfgs = configs_leg(log)
+
     post = None
     if not args.no_posterior:
         post = posterior_leg(args.posterior_sources, log)
@@ -409,6 +414,7 @@ def main():
                          "and batching together; 'speedups' separates them",
         "speedups": speedups(adaptive, mixed, fp64r, fp64),
         "roofline": roofline,
+        "configs": cfgs,
         "posterior": post,
         "pipeline": pipe,
         "timed_region_ns": region.t,
@@ -744,6 +750,91 @@ def posterior_leg(n_sources, log):
             "context": "paper: 1.8 s per signal for the same six stages on a Quadro RTX 4000 Mobile"}
 
 
+def configs_leg(log, reps: int = 5):
+    """Throughput of the other workloads, each at its full size on the device (inputs resident,
+    autotuned launch shapes, HIP events around the call, mean of `reps` after one untimed call):
+    C1 (1,000 candidates, one window), C2 (10,000 candidates in the reduced box of three
+    overlapping GBs, then the 10,000-step chain: the MH stage), C4 (64 windows x 4,096 gradients)
+    and C5 (4,000 full-band windows x 512 DE candidates, logL as the search scores them).  Per
+    call: evaluations per second and the algorithmic FLOP rate of the flop model against the
+    78.6 TFLOP/s vector peak (whole call, all its launches)."""
+    import numpy as np
+    import torch
+
+    from paper_2307_03763_amd import api
+    from paper_2307_03763_amd import inputs as I
+    E = lambda: torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+    ctxs = {}
+
+    def ctx_for(T):
+        if T not in ctxs:
+            ctxs[T] = api.context_for(T)
+            api.gb_autotune(ctxs[T].handle, 2)
+        return ctxs[T]
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = E(), E()
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    def flops(wl, grad):
+        return sum(float(wl.n_cand[i]) * flops_per_eval(w.N, w.C, min(w.W, w.N), grad) for i, w in enumerate(wl.windows))
+
+    def entry(wl, ms, grad, extra=None):
+        rows = int(sum(wl.n_cand))
+        tf = flops(wl, grad) / (ms * 1e-3) / 1e12
+        out = {"evals_per_s": round(rows / (ms * 1e-3), 1), "ms_per_call": round(ms, 4), "evals_per_call": rows,
+               "tflops": round(tf, 3), "frac_of_78.6": round(tf / PEAK_VALU_TFLOPS, 4)}
+        out.update(extra or {})
+        return out
+
+    res = {}
+    for name in ("C1", "C2", "C4", "C5"):
+        t0 = time.time()
+        T = I.T2 if name in ("C2", "C5") else I.T1
+        ctx = ctx_for(T)
+        tf = api.template_fn(ctx, api.GB_FP64)
+        wl = {"C1": lambda: I.workload_c1(tf, n_cand=1000), "C2": lambda: I.workload_c2(tf, n_cand=10000),
+              "C4": lambda: I.workload_c4(tf, n_win=64, n_cand=4096), "C5": lambda: I.workload_c5(tf)}[name]()
+        d = torch.as_tensor(wl.data, device="cuda")
+        w = torch.as_tensor(wl.weights, device="cuda")
+        th = torch.as_tensor(wl.theta, device="cuda")
+        rows = len(wl.theta)
+        logL = torch.empty(rows, dtype=torch.float64, device="cuda")
+        r = {"workload": wl.name}
+        for pname, prec in (("fp64", api.GB_FP64), ("mixed", api.GB_MIXED)):
+            p = api.Plan(ctx, wl.window_table(), prec)
+            p.prepare(d, w)
+            if name == "C2":
+                rng = np.random.default_rng(5)
+                log_g = torch.zeros(rows, dtype=torch.float64, device="cuda")
+                u = torch.as_tensor(rng.random(rows), device="cuda")
+                chain = torch.empty(rows, dtype=torch.int32, device="cuda")
+                nacc = torch.empty(wl.n_win, dtype=torch.int64, device="cuda")
+                ms = timed(lambda: api.gb_mh_step(p.handle, d, w, th, log_g, u, 1.0, logL, chain, nacc, stream))
+                r[f"{pname}_mh_stage"] = entry(wl, ms, False, {"note": "logL of every proposal, then the chain"})
+            ms = timed(lambda: api.gb_loglik(p.handle, d, w, th, logL, None, stream))
+            r[f"{pname}_logl"] = entry(wl, ms, False)
+            if name == "C4" and prec == api.GB_MIXED:
+                grad = torch.empty((rows, 8), dtype=torch.float64, device="cuda")
+                ms = timed(lambda: api.gb_loglik_grad(p.handle, d, w, th, logL, grad, stream))
+                r["mixed_grad"] = entry(wl, ms, True)
+            p.close()
+        res[name] = r
+        log(f"configs: {name} in {time.time() - t0:.1f} s: " +
+            ", ".join(f"{k} {v['evals_per_s']:.3e}/s" for k, v in r.items() if isinstance(v, dict)))
+    for c in ctxs.values():
+        c.close()
+    return res
+
+
 S_PARTIAL = 0.7   # share of the recovered signals subtracted for the posterior's noise (Sec. III G)
 
 
@@ -825,8 +916,17 @@ def pipeline_leg(segments, log, precision: str = "mixed", catalogue=None, noise:
     noise_fit = {}
     w_post = w
     t_noise = time.time()
-    for kind, dd in (("residual", d_res),
-                     ("partial", api.gb_add_templates(ctx.handle, table, th_si, wi, -S_PARTIAL, d) if len(si) else d)):
+    L_welch, M_ser = 16384, int(round(T / I.DT))
+    j_lo = -((-int(seg_bins[:, 0].min()) * L_welch) // M_ser)           # ceil(lo L / M)
+    j_hi = ((int(seg_bins[:, 1].max()) - 1) * L_welch) // M_ser
+    n_welch = j_hi - j_lo + 1
+    if n_welch < 70:
+        noise_fit = {"skipped": f"the block's band holds {n_welch} Welch bins of {L_welch} samples, fewer than the "
+                                f"70-bin Savitzky-Golay window: the posterior uses the PSD"}
+        posterior_noise = "psd"
+    for kind, dd in (() if n_welch < 70 else
+                     (("residual", d_res),
+                      ("partial", api.gb_add_templates(ctx.handle, table, th_si, wi, -S_PARTIAL, d) if len(si) else d))):
         w_k, S_k, _, _ = api.gb_noise_global(table, seg_bins, dd, T, I.DT)
         ratio = S_k.cpu().numpy() / wl.psd
         noise_fit[kind] = {"median_S_over_psd": round(float(np.median(ratio)), 4),

@@ -206,10 +206,10 @@ __device__ __forceinline__ Cand<R> make_cand(const double* th, double T) {
 // One sample of the slow series of channels A, E[, T] (without their normalisations) for unit
 // amplitude at t = tab time m.
 // ob64: FP64 orbit table [OB_FIELDS][N]; obR: the same in precision R (fields >= OB_N12).
-template <class R, int C>
+template <class R, int C, bool TDI2>
 __device__ __forceinline__ void slow_sample(const Cand<R>& s, const double* __restrict__ ob64,
                                             const R* __restrict__ obR, int N, int m, double t,
-                                            double Lc, bool tdi2, cplx<R> out[C]) {
+                                            double Lc, cplx<R> out[C]) {
   // common phase in cycles (FP64), reduced to [-1/2, 1/2]
   const double f = s.f0 + s.fd * t;
   const double kR = s.kxd * ob64[OB_RX * N + m] + s.kyd * ob64[OB_RY * N + m];
@@ -281,7 +281,7 @@ __device__ __forceinline__ void slow_sample(const Cand<R>& s, const double* __re
   cplx<R> K = scal(mul_mi(omd * mk<R>(cp, sp)), x);
   // second generation: 1 - D^4 = 2i sin(4 pi f L/c) D^2 = -4i sD cD D^2 (no cancellation at low
   // frequency either)
-  if (tdi2) K = K * mul_mi(scal(mk<R>(cD * cD - sD * sD, (R)2 * cD * sD), (R)4 * sD * cD));
+  if (TDI2) K = K * mul_mi(scal(mk<R>(cD * cD - sD * sD, (R)2 * cD * sD), (R)4 * sD * cD));
   // the channels without their normalisations (chan_norm)
   out[0] = K * (Z - X);
   out[1] = K * (X - scal(Y, (R)2) + Z);
@@ -504,11 +504,11 @@ namespace gbx {
 // Its derivative along f (local frequency), beta, lambda collects: the amplitude kappa and
 // the phase psi of K, the arm phases chi_a, the projections F+_a, Fx_a, the six link sincs
 // through u = x (1 -+ k.n_a), and the delay D inside Lam_a.
-template <class R, int C>
+template <class R, int C, bool TDI2>
 __device__ __forceinline__ void grad_sample_rev(const Cand<R>& s, const CandG<R>& sg,
                                                 const double* __restrict__ ob64, const R* __restrict__ obR,
-                                                int N, int m, double t, double Lc, bool tdi2,
-                                                const cplx<R> sbar[C], GradAcc& acc) {
+                                                int N, int m, double t, double Lc, const cplx<R> sbar[C],
+                                                GradAcc& acc) {
   const R twopi = (R)(2.0 * kPi), pi = (R)kPi;
   const double f = s.f0 + s.fd * t;
   const double Rx = ob64[OB_RX * N + m], Ry = ob64[OB_RY * N + m];
@@ -527,7 +527,7 @@ __device__ __forceinline__ void grad_sample_rev(const Cand<R>& s, const CandG<R>
   // amplitude and phase of K along f (below): d kappa/df and d psi/df
   R dkappa_f = twopi * Lr * (-sDm + phiD * cDm);        // d(phi_D sin phi_D)/df
   R dpsi_f = -twopi * ((R)1.5 * Lr + (R)kR);
-  if (tdi2) {
+  if (TDI2) {
     // second generation: K2 = K (1 - D^4) = K 2 sin(2 phi_D) i D^2, so kappa gains the factor
     // g = 2 sin(2 phi_D) = -4 sDm cDm and psi the phase pi/2 - 2 phi_D
     const R g = -(R)4 * sDm * cDm;

@@ -1,6 +1,8 @@
 // Kernels of the Galactic-binary likelihood path (gfx950).
 #pragma once
 
+#include <type_traits>
+
 #include "gbx_device.h"
 
 namespace gbx {
@@ -73,21 +75,31 @@ __device__ __forceinline__ void slot_reduce(double v[NV], double (*s_red)[16]) {
   }
 }
 
-// Slow series of one template into LDS (all its lanes), then the forward DFT.
-template <class R, int N, int LPC, int C>
-__device__ __forceinline__ void template_to_lds(const Cand<R>& s, const BatchArgs& a, int lane, cplx<R>* buf) {
+// The slow-series samples of one lane, one at a time (keeps the live state of a single sample
+// in registers); TDI2 selects the TDI generation at compile time, so that the branch on it is
+// taken once per template, outside the loop.
+template <class R, int N, int LPC, int C, bool TDI2>
+__device__ __forceinline__ void series_samples(const Cand<R>& s, const BatchArgs& a, int lane, cplx<R>* buf) {
   constexpr int E = N / LPC;
   const R* obR = (const R*)a.obR;
-  // one sample at a time: keeps the live state of a single sample in registers
 #pragma unroll 1
   for (int e = 0; e < E; ++e) {
     const int m = lane + LPC * e;
     const double t = a.T * (double)m / (double)N;
     cplx<R> o[C];
-    slow_sample<R, C>(s, a.ob64, obR, N, m, t, a.Lc, a.tdi2 != 0, o);
+    slow_sample<R, C, TDI2>(s, a.ob64, obR, N, m, t, a.Lc, o);
 #pragma unroll
     for (int c = 0; c < C; ++c) buf[c * N + m] = o[c];
   }
+}
+
+// Slow series of one template into LDS (all its lanes), then the forward DFT.
+template <class R, int N, int LPC, int C>
+__device__ __forceinline__ void template_to_lds(const Cand<R>& s, const BatchArgs& a, int lane, cplx<R>* buf) {
+  if (a.tdi2)
+    series_samples<R, N, LPC, C, true>(s, a, lane, buf);
+  else
+    series_samples<R, N, LPC, C, false>(s, a, lane, buf);
   slot_sync<LPC>();
   fft_lds<R, N, LPC, C, -1>(buf, lane, (const cplx<R>*)a.tw);
 }
@@ -185,16 +197,23 @@ __device__ __forceinline__ void process_grad(const BatchArgs& a, const DevWin& w
   fft_lds<R, N, LPC, C, +1>(buf, lane, (const cplx<R>*)a.tw);
   GradAcc& ga = *reinterpret_cast<GradAcc*>(&v[3]);  // v[3..12]: per-sample accumulators
   const R* obR = (const R*)a.obR;
-  auto sample = [&](int e) {
-    const int m = lane + LPC * e;
-    const double t = a.T * (double)m / (double)N;
-    cplx<R> sbar[C];
-#pragma unroll
-    for (int c = 0; c < C; ++c) sbar[c] = buf[c * N + m];
-    grad_sample_rev<R, C>(s, sg, a.ob64, obR, N, m, t, a.Lc, a.tdi2 != 0, sbar, ga);
-  };
+  auto samples = [&](auto tdi2) {
+    constexpr bool TDI2 = decltype(tdi2)::value;
 #pragma unroll 1
-  for (int e = 0; e < E; ++e) sample(e);
+    for (int e = 0; e < E; ++e) {
+      const int m = lane + LPC * e;
+      const double t = a.T * (double)m / (double)N;
+      cplx<R> sbar[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) sbar[c] = buf[c * N + m];
+      grad_sample_rev<R, C, TDI2>(s, sg, a.ob64, obR, N, m, t, a.Lc, sbar, ga);
+    }
+  };
+  // the TDI generation is uniform over the launch: one branch per template, outside the loop
+  if (a.tdi2)
+    samples(std::true_type{});
+  else
+    samples(std::false_type{});
   slot_reduce<LPC, WPB, 13>(v, s_red);
   if (lane == 0 && active) {
     const double nan = __builtin_nan("");
