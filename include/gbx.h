@@ -69,7 +69,8 @@ typedef struct {
   int64_t k0;            /* absolute index of the first bin */
   int32_t W;             /* number of bins, >= 1 */
   int32_t N;             /* slow-series samples per template: power of two in [64, 1024] */
-  int32_t C;             /* channels, 2 (A, E) or 3 (A, E, T) */
+  int32_t C;             /* channels, 2 (A, E) or 3 (A, E, T); 0 in gb_plan_create: the rule of
+                            Sec. II, resolved from the window's centre (see gb_channels) */
   int32_t precision;     /* gb_precision of this window when the plan is GB_PER_WINDOW */
   int64_t data_off;      /* element offset of the window's [C][W] block in d and in w */
   int64_t cand_off;      /* first candidate row of this window in theta and the outputs */
@@ -97,6 +98,13 @@ const char* gb_last_error(void);
  * GB_EINVAL: B < 0, N not a power of two in [64, 1024], C not 2 or 3, null pointers. */
 gb_status gb_waveform(gb_ctx* ctx, const double* theta, int64_t B, int N, int C,
                       gb_precision precision, double* h_out, int64_t* first_bin, void* stream);
+
+/* The channel count the rule of Sec. II gives a window: the T channel is used at and above half
+ * the transfer frequency, f >= f* / 2 = c / (4 pi L) (9.55 mHz for L = 2.5e9 m, the context's arm
+ * length), judged at the window's centre f = (k0 + W/2) / T; *C = 3 there and 2 below.  Callers
+ * that pass C = 0 to gb_plan_create lay out their data with this count.  GB_EINVAL: null
+ * pointers, W < 1. */
+gb_status gb_channels(const gb_ctx* ctx, int64_t k0, int32_t W, int32_t* C);
 
 /* Build a plan for `n_win` windows (host array, copied): validates every window, groups the
  * windows by (N, C, precision), splits their candidates into tiles ordered by cost and

@@ -73,6 +73,12 @@ class Geometry:
         return (self.T, self.P_orb, self.L, self.AU, self.tdi)
 
 
+def channels(f: float, L: float = I.ARM_L) -> int:
+    """The channel rule of Sec. II: A and E below half the transfer frequency f*/2 = c / (4 pi L),
+    A, E and T at and above it."""
+    return 3 if f >= 299792458.0 / (4.0 * 3.141592653589793 * L) else 2
+
+
 def max_threads() -> int:
     return int(_load().gbo_max_threads())
 

@@ -21,7 +21,7 @@ GB_OK, GB_EINVAL, GB_EHIP, GB_ENOMEM, GB_EUNSUPPORTED = 0, -1, -2, -3, -4
 GB_FP64, GB_MIXED, GB_PER_WINDOW = 0, 1, 2
 PRECISION = {"fp64": GB_FP64, "mixed": GB_MIXED, "per_window": GB_PER_WINDOW}
 
-EXPORTS = ("gb_create", "gb_destroy", "gb_last_error", "gb_waveform", "gb_plan_create",
+EXPORTS = ("gb_create", "gb_destroy", "gb_last_error", "gb_waveform", "gb_channels", "gb_plan_create",
            "gb_plan_destroy", "gb_plan_info", "gb_window_prepare", "gb_loglik", "gb_loglik_grad", "gb_mh_step",
            "gb_autotune", "gb_select_variant", "gb_fisher", "gb_kde_logpdf", "gb_add_templates",
            "gb_noise_estimate", "gb_noise_estimate_noalloc", "gb_noise_global", "gb_de_trial", "gb_de_select")
@@ -72,6 +72,8 @@ def lib():
         L.gb_last_error.restype = ctypes.c_char_p
         L.gb_waveform.argtypes = [_vp, _vp, i64, i, i, i, _vp, _vp, _vp]
         L.gb_waveform.restype = st
+        L.gb_channels.argtypes = [_vp, i64, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+        L.gb_channels.restype = st
         L.gb_plan_create.argtypes = [_vp, ctypes.POINTER(gb_window), i, i, ctypes.POINTER(_vp)]
         L.gb_plan_create.restype = st
         L.gb_plan_destroy.argtypes = [_vp]
@@ -170,6 +172,13 @@ def windows_array(table) -> ctypes.Array:
         prec = int(r[8]) if len(r) > 8 else GB_FP64
         arr[i] = gb_window(int(r[0]), int(r[1]), int(r[2]), int(r[3]), prec, int(r[4]), int(r[6]), int(r[7]))
     return arr
+
+
+def gb_channels(ctx: int, k0: int, W: int) -> int:
+    """Channel count of the rule of Sec. II for a window (what C = 0 resolves to in a plan)."""
+    C = ctypes.c_int32()
+    _check(lib().gb_channels(ctx, int(k0), int(W), ctypes.byref(C)), "gb_channels")
+    return C.value
 
 
 def gb_plan_create(ctx: int, table, precision: int) -> int:

@@ -260,6 +260,20 @@ extern "C" gb_status gb_waveform(gb_ctx* c, const double* theta, int64_t B, int 
   return launch(v, dim3((unsigned)blocks), a, (hipStream_t)stream);
 }
 
+// ------------------------------------------------------------------------------- channels
+// The rule of Sec. II: A, E below f*/2 = c / (4 pi L), A, E, T at and above, at the window centre.
+static int paper_channels(const gb_ctx* c, int64_t k0, int32_t W) {
+  const double f = ((double)k0 + 0.5 * (double)W) / c->cfg.T;
+  return f >= kC / (4.0 * kPi * c->cfg.arm_length) ? 3 : 2;
+}
+
+extern "C" gb_status gb_channels(const gb_ctx* c, int64_t k0, int32_t W, int32_t* C) {
+  if (!c || !C) return fail(GB_EINVAL, "gb_channels: null argument");
+  if (W < 1) return fail(GB_EINVAL, "gb_channels: W = %d < 1", W);
+  *C = paper_channels(c, k0, W);
+  return GB_OK;
+}
+
 // ------------------------------------------------------------------------------- plans
 namespace {
 struct Bucket {
@@ -310,12 +324,14 @@ extern "C" gb_status gb_plan_create(gb_ctx* c, const gb_window* windows, int n_w
     return fail(GB_EINVAL, "gb_plan_create: bad precision %d", (int)prec);
   std::vector<DevWin> dw(n_win);
   int64_t rows = 0;
+  std::vector<gb_window> resolved(windows, windows + n_win);
   for (int i = 0; i < n_win; ++i) {
-    const gb_window& w = windows[i];
+    gb_window& w = resolved[i];
     const int wp = prec == GB_PER_WINDOW ? w.precision : (int)prec;
     if (!pow2_in_range(w.N)) return fail(GB_EINVAL, "window %d: N = %d is not a power of two in [64, 1024]", i, w.N);
-    if (w.C != 2 && w.C != 3) return fail(GB_EINVAL, "window %d: C = %d (must be 2 or 3)", i, w.C);
     if (w.W < 1) return fail(GB_EINVAL, "window %d: W = %d < 1", i, w.W);
+    if (w.C == 0) w.C = paper_channels(c, w.k0, w.W);
+    if (w.C != 2 && w.C != 3) return fail(GB_EINVAL, "window %d: C = %d (must be 2, 3, or 0 for the rule)", i, w.C);
     if (w.k0 < 0) return fail(GB_EINVAL, "window %d: k0 < 0", i);
     if (w.data_off < 0 || w.cand_off < 0 || w.n_cand < 0)
       return fail(GB_EINVAL, "window %d: negative offset or count", i);
@@ -334,7 +350,7 @@ extern "C" gb_status gb_plan_create(gb_ctx* c, const gb_window* windows, int n_w
   }
   gb_plan* p = new gb_plan();
   p->ctx = c;
-  p->wins.assign(windows, windows + n_win);
+  p->wins = resolved;
   p->rows = rows;
   // group by (N, C, precision); larger N first (longest work first)
   std::vector<int> order(n_win);

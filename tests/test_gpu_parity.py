@@ -299,3 +299,49 @@ def test_rejects_unprepared_data(c3_small):
         api.Plan(ctx, bad, api.GB_FP64)
     with pytest.raises(api.GbxError):
         ctx.waveform(th[:2], 96, 2)
+
+
+def test_channel_rule_in_plan(oracle_lib):
+    """Windows with C = 0 take the channel count of the rule of Sec. II in gb_plan_create
+    (gb_channels reports it, for the data layout); it agrees with the oracle's own rule on both
+    sides of 9.55 mHz, and the likelihood of such a plan matches the oracle at the resolved count."""
+    from tests.gpu_common import loglik_tolerance
+    banner("channel rule: C = 0 windows resolved by the plan")
+    O = oracle_lib
+    T = I.T1
+    ctx = api.context_for(T)
+    rng = np.random.default_rng(61)
+    rows, blocks, wins, thetas, off, coff = [], [], [], [], 0, 0
+    for f in (9.40e-3, 9.545e-3, 9.56e-3, 9.70e-3, 3e-3, 15e-3):
+        W, N = 256, 256
+        q = int(f * T)
+        k0 = q - W // 2
+        C = api.gb_channels(ctx.handle, k0, W)
+        assert C == O.channels((k0 + W / 2) / T), f
+        src = I.make_theta([(q + 0.4) / T], I.fdot_gr(f, 0.5), 1e-21, I.random_angles(rng, 1))
+        h, fb = O.waveform(src, N, C, O.Geometry(T))
+        d = I.draw_noise(rng, I.channel_psd(k0, W, C, T), T)
+        I.add_templates(d, k0, h, fb)
+        ww = I.inner_product_weights(I.channel_psd(k0, W, C, T), T)
+        th = I.draw_gaussian_around(rng, src[0], I.table1_box(k0 / T, (k0 + W) / T, T), 1e-4, 5)
+        rows.append([k0, W, N, 0, off, 0, coff, len(th)])
+        blocks.append((d, ww))
+        wins.append((k0, W, N, C))
+        thetas.append(th)
+        off += C * W
+        coff += len(th)
+    dd = np.concatenate([b[0].ravel() for b in blocks])
+    ww = np.concatenate([b[1].ravel() for b in blocks])
+    th = np.concatenate(thetas)
+    plan = api.Plan(ctx, np.array(rows), api.GB_FP64)
+    assert api.gb_plan_info(plan.handle)[2] == off
+    plan.prepare(dev(dd, torch.complex128), dev(ww))
+    l = plan.loglik(dev(th)).cpu().numpy()
+    for i, (k0, W, N, C) in enumerate(wins):
+        d, w = blocks[i]
+        lo, co = O.loglik(thetas[i], k0, W, N, C, d, w, O.Geometry(T))
+        a = rows[i][6]
+        dd_i = float(np.sum(w * np.abs(d) ** 2))
+        assert np.all(np.abs(l[a:a + len(lo)] - lo) <= loglik_tolerance(dd_i, co[:, 0], co[:, 1])), i
+    plan.close()
+    ctx.close()

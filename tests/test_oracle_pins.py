@@ -462,3 +462,14 @@ def test_paper_schedule_and_boxes():
     lo, hi = I.reduced_box(th, box, 1e-6 * box.width)
     assert hi[6] - lo[6] == pytest.approx(2 * gv["reduced_box_psi_halfwidth"]["value"], rel=1e-12)
     assert hi[7] - lo[7] == pytest.approx(2 * gv["reduced_box_phi0_halfwidth"]["value"], rel=1e-12)
+
+
+def test_channel_rule(oracle_lib):
+    """The oracle's channel rule switches at the paper's printed half transfer frequency, 9.55 mHz
+    (Sec. II), for the arm length of the synthetic setting."""
+    O = oracle_lib
+    gv = json.load(open(GOLDEN))["half_transfer_frequency_hz"]
+    f = gv["value"]
+    assert O.channels(f * (1 - 2 * gv["rel_tol"])) == 2
+    assert O.channels(f * (1 + 2 * gv["rel_tol"])) == 3
+    assert O.channels(1e-3) == 2 and O.channels(20e-3) == 3
