@@ -29,6 +29,9 @@ COPY_N = 1 << 28            # copy calibration: 256 M doubles = 2 GiB read + 2 G
 N_SIMD = 256 * 4            # MI355X: 256 compute units of 4 SIMDs
 SQ_COUNTERS = ("SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_WAIT_ANY", "SQ_WAIT_INST_ANY",
                "SQ_ACTIVE_INST_ANY", "SQ_ACTIVE_INST_VALU", "SQ_INSTS_VALU")
+# a second pass (eight SQ counters per rocprofv3 --pmc run): LDS instructions and their stalls
+LDS_COUNTERS = ("SQ_WAVES", "SQ_INSTS_LDS", "SQ_ACTIVE_INST_LDS", "SQ_LDS_IDX_ACTIVE", "SQ_LDS_BANK_CONFLICT",
+                "SQ_LDS_ADDR_CONFLICT", "SQ_LDS_UNALIGNED_STALL", "SQ_WAIT_INST_LDS")
 
 
 # ------------------------------------------------------------------------------------------
@@ -90,7 +93,8 @@ def parse():
                     help="print the timed-region kernel summary of a rocprofv3 --kernel-trace and exit")
     ap.add_argument("--counter-summary", nargs=2, metavar=("BENCH_JSON", "PMC_DIR"),
                     help="print per-kernel issue statistics of the timed region from a rocprofv3 --pmc run of "
-                         "the SQ counters " + " ".join(SQ_COUNTERS) + " and exit")
+                         "the SQ counters " + " ".join(SQ_COUNTERS) + " (or LDS statistics from a run of " +
+                         " ".join(LDS_COUNTERS) + ") and exit")
     return ap.parse_args()
 
 
@@ -578,18 +582,13 @@ def trace_summary(bench_json: str, trace_dir: str) -> str:
     return "\n".join(lines)
 
 
-def counter_summary(bench_json: str, pmc_dir: str) -> str:
-    """Per-kernel issue statistics from one rocprofv3 --pmc run of SQ_COUNTERS over the bench
-    (its output line in bench_json), summed over the dispatches of each k_batch kernel inside
-    the timed region.  Per wave: the share of its cycles spent issuing VALU
-    instructions (SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES) and waiting (SQ_WAIT_ANY /
-    SQ_WAVE_CYCLES).  The persistent kernels launch exactly the waves that stay resident, so
-    waves per SIMD = waves per dispatch / N_SIMD, and that times the per-wave VALU share is the
-    share of the SIMD's cycles with a VALU instruction in flight."""
+def _counter_sums(bench_json: str, pmc_dir: str, counters) -> dict:
+    """Per k_batch kernel: the counters summed over its dispatches inside the timed region (each
+    counter's per-shader-engine values summed per dispatch), and the set of those dispatches."""
     b = _last_json(bench_json)
     per = {}
-    for ctr in SQ_COUNTERS:
-        tot = {}   # the counter has one value per shader engine: sum them per dispatch
+    for ctr in counters:
+        tot = {}
         for k, t0, t1, v in _dispatches(pmc_dir, ctr):
             tot[(k, t0, t1)] = tot.get((k, t0, t1), 0.0) + v
         for k, t0, t1, v in _in_region([key + (v,) for key, v in tot.items()], b):
@@ -598,6 +597,38 @@ def counter_summary(bench_json: str, pmc_dir: str) -> str:
             d = per.setdefault(k, {"disp": set()})
             d["disp"].add((t0, t1))
             d[ctr] = d.get(ctr, 0.0) + v
+    return per
+
+
+def lds_summary(bench_json: str, pmc_dir: str) -> str:
+    """Per-kernel LDS statistics from a rocprofv3 --pmc run of LDS_COUNTERS over the bench: LDS
+    instructions per wave, and the shares of the cycles in which the LDS was busy with a
+    wave's request (SQ_LDS_IDX_ACTIVE) that went to bank conflicts and to address conflicts."""
+    per = _counter_sums(bench_json, pmc_dir, LDS_COUNTERS)
+    lines = [f"{'kernel':<34} {'disp':>5} {'avg ms':>8} {'LDS inst/wave':>13} {'bank-conflict':>13} "
+             f"{'addr-conflict':>13} {'unaligned':>9}",
+             f"{'':<34} {'':>5} {'':>8} {'':>13} {'/ LDS active':>13} {'/ LDS active':>13} {'/ active':>9}"]
+    for k, d in sorted(per.items(), key=lambda kv: -sum(t1 - t0 for t0, t1 in kv[1]["disp"])):
+        n = len(d["disp"])
+        ms = sum(t1 - t0 for t0, t1 in d["disp"]) * 1e-6 / n
+        act = max(d["SQ_LDS_IDX_ACTIVE"], 1.0)
+        lines.append(f"{k:<34} {n:>5} {ms:>8.3f} {d['SQ_INSTS_LDS'] / d['SQ_WAVES']:>13.1f} "
+                     f"{d['SQ_LDS_BANK_CONFLICT'] / act:>13.4f} {d['SQ_LDS_ADDR_CONFLICT'] / act:>13.4f} "
+                     f"{d['SQ_LDS_UNALIGNED_STALL'] / act:>9.4f}")
+    return "\n".join(lines)
+
+
+def counter_summary(bench_json: str, pmc_dir: str) -> str:
+    """Per-kernel issue statistics from one rocprofv3 --pmc run of SQ_COUNTERS over the bench
+    (its output line in bench_json), summed over the dispatches of each k_batch kernel inside
+    the timed region.  Per wave: the share of its cycles spent issuing VALU
+    instructions (SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES) and waiting (SQ_WAIT_ANY /
+    SQ_WAVE_CYCLES).  The persistent kernels launch exactly the waves that stay resident, so
+    waves per SIMD = waves per dispatch / N_SIMD, and that times the per-wave VALU share is the
+    share of the SIMD's cycles with a VALU instruction in flight."""
+    if not _dispatches(pmc_dir, "SQ_WAVE_CYCLES") and _dispatches(pmc_dir, "SQ_LDS_BANK_CONFLICT"):
+        return lds_summary(bench_json, pmc_dir)
+    per = _counter_sums(bench_json, pmc_dir, SQ_COUNTERS)
     lines = [f"{'kernel':<34} {'disp':>5} {'avg ms':>8} {'waves/SIMD':>10} {'VALU/wave':>9} {'wait/wave':>9} "
              f"{'SIMD VALU busy':>14} {'VALU cyc/inst':>13}"]
     for k, d in sorted(per.items(), key=lambda kv: -sum(t1 - t0 for t0, t1 in kv[1]["disp"])):

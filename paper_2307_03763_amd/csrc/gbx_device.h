@@ -149,6 +149,39 @@ __device__ __forceinline__ float sinc_r(float u) {
   return __builtin_amdgcn_sinf(u * (float)(0.5 / kPi)) / u;
 }
 
+// The short series: for link arguments |u| <= sinc_short_max<R>(), FP64 ten terms (the next,
+// u^20/21!, is below 7e-17 at 1.5) and FP32 five terms (u^10/11! below 3e-8 at 1.0).  A template
+// takes it when every lane of its wave has all six link arguments in that range (frequencies up
+// to about 28 and 19 mHz), so no quotient is needed there.
+template <class R>
+__device__ __forceinline__ constexpr double sinc_short_max() { return sizeof(R) == 8 ? 1.5 : 1.0; }
+__device__ __forceinline__ double sinc_short(double u) {
+  const double u2 = u * u;
+  double p = -1.0 / 121645100408832000.0;  // -1/19!
+  p = p * u2 + 1.0 / 355687428096000.0;     // 1/17!
+  p = p * u2 - 1.0 / 1307674368000.0;       // -1/15!
+  p = p * u2 + 1.0 / 6227020800.0;          // 1/13!
+  p = p * u2 - 1.0 / 39916800.0;            // -1/11!
+  p = p * u2 + 1.0 / 362880.0;              // 1/9!
+  p = p * u2 - 1.0 / 5040.0;                // -1/7!
+  p = p * u2 + 1.0 / 120.0;                 // 1/5!
+  p = p * u2 - 1.0 / 6.0;                   // -1/3!
+  return p * u2 + 1.0;
+}
+__device__ __forceinline__ float sinc_short(float u) {
+  const float u2 = u * u;
+  float p = 1.0f / 362880.0f;               // 1/9!
+  p = p * u2 - 1.0f / 5040.0f;              // -1/7!
+  p = p * u2 + 1.0f / 120.0f;               // 1/5!
+  p = p * u2 - 1.0f / 6.0f;                 // -1/3!
+  return p * u2 + 1.0f;
+}
+template <class R, bool SHORT>
+__device__ __forceinline__ R sinc_sel(R u) {
+  if (SHORT) return sinc_short(u);
+  return sinc_r(u);
+}
+
 // Per-candidate constants (computed once per template, replicated over its lanes).
 template <class R>
 struct Cand {
@@ -206,7 +239,7 @@ __device__ __forceinline__ Cand<R> make_cand(const double* th, double T) {
 // One sample of the slow series of channels A, E[, T] (without their normalisations) for unit
 // amplitude at t = tab time m.
 // ob64: FP64 orbit table [OB_FIELDS][N]; obR: the same in precision R (fields >= OB_N12).
-template <class R, int C, bool TDI2>
+template <class R, int C, bool TDI2, bool SHORT>
 __device__ __forceinline__ void slow_sample(const Cand<R>& s, const double* __restrict__ ob64,
                                             const R* __restrict__ obR, int N, int m, double t,
                                             double Lc, cplx<R> out[C]) {
@@ -267,9 +300,9 @@ __device__ __forceinline__ void slow_sample(const Cand<R>& s, const double* __re
     P[a] = b * ph[opp[a]];
   }
   // link sincs: n12 = +arm 12 for link 12, -arm 12 for link 21 (and cyclically)
-  const R s12 = sinc_r(x * ((R)1 - kn[0])), s21 = sinc_r(x * ((R)1 + kn[0]));
-  const R s23 = sinc_r(x * ((R)1 - kn[1])), s32 = sinc_r(x * ((R)1 + kn[1]));
-  const R s31 = sinc_r(x * ((R)1 - kn[2])), s13 = sinc_r(x * ((R)1 + kn[2]));
+  const R s12 = sinc_sel<R, SHORT>(x * ((R)1 - kn[0])), s21 = sinc_sel<R, SHORT>(x * ((R)1 + kn[0]));
+  const R s23 = sinc_sel<R, SHORT>(x * ((R)1 - kn[1])), s32 = sinc_sel<R, SHORT>(x * ((R)1 + kn[1]));
+  const R s31 = sinc_sel<R, SHORT>(x * ((R)1 - kn[2])), s13 = sinc_sel<R, SHORT>(x * ((R)1 + kn[2]));
   // G(a, b) = a + D b for real a, b
   auto G = [&](R a, R b) { return mk<R>(a + cD * b, sD * b); };
   const cplx<R> X = P[2] * G(s13, s31) - P[0] * G(s12, s21);
@@ -464,6 +497,41 @@ __device__ __forceinline__ void sinc_d(float u, float* s, float* ds) {
     *ds = (cs - *s) / u;
   }
 }
+// sinc and its derivative by the short series (see sinc_short)
+__device__ __forceinline__ void sinc_d_short(double u, double* s, double* ds) {
+  const double u2 = u * u;
+  const double c[10] = {1.0, -1.0 / 6.0, 1.0 / 120.0, -1.0 / 5040.0, 1.0 / 362880.0, -1.0 / 39916800.0,
+                        1.0 / 6227020800.0, -1.0 / 1307674368000.0, 1.0 / 355687428096000.0,
+                        -1.0 / 121645100408832000.0};
+  double p = c[9], q = 18.0 * c[9];
+#pragma unroll
+  for (int k = 8; k >= 1; --k) {
+    p = p * u2 + c[k];
+    q = q * u2 + 2.0 * k * c[k];
+  }
+  *s = p * u2 + c[0];
+  *ds = q * u;
+}
+__device__ __forceinline__ void sinc_d_short(float u, float* s, float* ds) {
+  const float u2 = u * u;
+  const float c[5] = {1.0f, -1.0f / 6.0f, 1.0f / 120.0f, -1.0f / 5040.0f, 1.0f / 362880.0f};
+  float p = c[4], q = 8.0f * c[4];
+#pragma unroll
+  for (int k = 3; k >= 1; --k) {
+    p = p * u2 + c[k];
+    q = q * u2 + 2.0f * k * c[k];
+  }
+  *s = p * u2 + c[0];
+  *ds = q * u;
+}
+template <class R, bool SHORT>
+__device__ __forceinline__ void sinc_d_sel(R u, R* s, R* ds) {
+  if (SHORT)
+    sinc_d_short(u, s, ds);
+  else
+    sinc_d(u, s, ds);
+}
+
 // Extra per-candidate constants of the gradient.
 template <class R>
 struct CandG {
@@ -504,7 +572,7 @@ namespace gbx {
 // Its derivative along f (local frequency), beta, lambda collects: the amplitude kappa and
 // the phase psi of K, the arm phases chi_a, the projections F+_a, Fx_a, the six link sincs
 // through u = x (1 -+ k.n_a), and the delay D inside Lam_a.
-template <class R, int C, bool TDI2>
+template <class R, int C, bool TDI2, bool SHORT>
 __device__ __forceinline__ void grad_sample_rev(const Cand<R>& s, const CandG<R>& sg,
                                                 const double* __restrict__ ob64, const R* __restrict__ obR,
                                                 int N, int m, double t, double Lc, const cplx<R> sbar[C],
@@ -592,8 +660,8 @@ __device__ __forceinline__ void grad_sample_rev(const Cand<R>& s, const CandG<R>
   R sv[6], sd[6];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    sinc_d(x * ((R)1 - kn[a]), &sv[2 * a], &sd[2 * a]);
-    sinc_d(x * ((R)1 + kn[a]), &sv[2 * a + 1], &sd[2 * a + 1]);
+    sinc_d_sel<R, SHORT>(x * ((R)1 - kn[a]), &sv[2 * a], &sd[2 * a]);
+    sinc_d_sel<R, SHORT>(x * ((R)1 + kn[a]), &sv[2 * a + 1], &sd[2 * a + 1]);
   }
   const R s12 = sv[0], s21 = sv[1], s23 = sv[2], s32 = sv[3], s31 = sv[4], s13 = sv[5];
   // channel cotangents (of the series without their normalisations) folded onto X, Y, Z

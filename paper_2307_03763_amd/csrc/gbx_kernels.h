@@ -75,10 +75,32 @@ __device__ __forceinline__ void slot_reduce(double v[NV], double (*s_red)[16]) {
   }
 }
 
+// Whether the short sinc series covers every link argument of every template in this wave:
+// |u| = x |1 -+ k.n| <= 2 pi f L / c with f the largest local frequency f0 + max(0, fdot T).
+// The vote makes the choice uniform over the wave, so the sample loop does not diverge.
+template <class R>
+__device__ __forceinline__ bool wave_sinc_short(const Cand<R>& s, const BatchArgs& a) {
+  const double fhi = s.f0 + fmax(0.0, s.fd * a.T);
+  return __all(2.0 * kPi * fhi * a.Lc <= sinc_short_max<R>());
+}
+
+// Calls body(tdi2, short) with the two compile-time choices of a template's sample loops: the TDI
+// generation (uniform over the launch) and the short sinc series (uniform over the wave).
+template <class F>
+__device__ __forceinline__ void with_loop_flags(bool tdi2, bool shrt, F&& body) {
+  if (tdi2) {
+    if (shrt) body(std::true_type{}, std::true_type{});
+    else body(std::true_type{}, std::false_type{});
+  } else {
+    if (shrt) body(std::false_type{}, std::true_type{});
+    else body(std::false_type{}, std::false_type{});
+  }
+}
+
 // The slow-series samples of one lane, one at a time (keeps the live state of a single sample
-// in registers); TDI2 selects the TDI generation at compile time, so that the branch on it is
-// taken once per template, outside the loop.
-template <class R, int N, int LPC, int C, bool TDI2>
+// in registers); TDI2 and SHORT are compile-time choices (with_loop_flags), so that the
+// branches on them are taken once per template, outside the loop.
+template <class R, int N, int LPC, int C, bool TDI2, bool SHORT>
 __device__ __forceinline__ void series_samples(const Cand<R>& s, const BatchArgs& a, int lane, cplx<R>* buf) {
   constexpr int E = N / LPC;
   const R* obR = (const R*)a.obR;
@@ -87,7 +109,7 @@ __device__ __forceinline__ void series_samples(const Cand<R>& s, const BatchArgs
     const int m = lane + LPC * e;
     const double t = a.T * (double)m / (double)N;
     cplx<R> o[C];
-    slow_sample<R, C, TDI2>(s, a.ob64, obR, N, m, t, a.Lc, o);
+    slow_sample<R, C, TDI2, SHORT>(s, a.ob64, obR, N, m, t, a.Lc, o);
 #pragma unroll
     for (int c = 0; c < C; ++c) buf[c * N + m] = o[c];
   }
@@ -96,10 +118,9 @@ __device__ __forceinline__ void series_samples(const Cand<R>& s, const BatchArgs
 // Slow series of one template into LDS (all its lanes), then the forward DFT.
 template <class R, int N, int LPC, int C>
 __device__ __forceinline__ void template_to_lds(const Cand<R>& s, const BatchArgs& a, int lane, cplx<R>* buf) {
-  if (a.tdi2)
-    series_samples<R, N, LPC, C, true>(s, a, lane, buf);
-  else
-    series_samples<R, N, LPC, C, false>(s, a, lane, buf);
+  with_loop_flags(a.tdi2 != 0, wave_sinc_short<R>(s, a), [&](auto tdi2, auto shrt) {
+    series_samples<R, N, LPC, C, decltype(tdi2)::value, decltype(shrt)::value>(s, a, lane, buf);
+  });
   slot_sync<LPC>();
   fft_lds<R, N, LPC, C, -1>(buf, lane, (const cplx<R>*)a.tw);
 }
@@ -197,8 +218,8 @@ __device__ __forceinline__ void process_grad(const BatchArgs& a, const DevWin& w
   fft_lds<R, N, LPC, C, +1>(buf, lane, (const cplx<R>*)a.tw);
   GradAcc& ga = *reinterpret_cast<GradAcc*>(&v[3]);  // v[3..12]: per-sample accumulators
   const R* obR = (const R*)a.obR;
-  auto samples = [&](auto tdi2) {
-    constexpr bool TDI2 = decltype(tdi2)::value;
+  auto samples = [&](auto tdi2, auto shrt) {
+    constexpr bool TDI2 = decltype(tdi2)::value, SHORT = decltype(shrt)::value;
 #pragma unroll 1
     for (int e = 0; e < E; ++e) {
       const int m = lane + LPC * e;
@@ -206,14 +227,11 @@ __device__ __forceinline__ void process_grad(const BatchArgs& a, const DevWin& w
       cplx<R> sbar[C];
 #pragma unroll
       for (int c = 0; c < C; ++c) sbar[c] = buf[c * N + m];
-      grad_sample_rev<R, C, TDI2>(s, sg, a.ob64, obR, N, m, t, a.Lc, sbar, ga);
+      grad_sample_rev<R, C, TDI2, SHORT>(s, sg, a.ob64, obR, N, m, t, a.Lc, sbar, ga);
     }
   };
-  // the TDI generation is uniform over the launch: one branch per template, outside the loop
-  if (a.tdi2)
-    samples(std::true_type{});
-  else
-    samples(std::false_type{});
+  // one branch per template, outside the loop
+  with_loop_flags(a.tdi2 != 0, wave_sinc_short<R>(s, a), samples);
   slot_reduce<LPC, WPB, 13>(v, s_red);
   if (lane == 0 && active) {
     const double nan = __builtin_nan("");
