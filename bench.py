@@ -156,7 +156,10 @@ def main():
         tune = "\n".join(_last_json(args.tune_from)["autotune"])
         log(f"launch shapes of {args.tune_from}: {api.apply_tuning(ctx.handle, tune)} set")
     else:
-        tune = api.gb_autotune(ctx.handle, 3)
+        # every family on synthetic candidates, then the families of this workload on its own
+        # windows, data and candidates (the choice that its plans use)
+        tune = api.merge_tuning(api.gb_autotune(ctx.handle, 3),
+                                api.gb_autotune_windows(ctx.handle, table, d, w, th, 3))
     log(f"autotune {time.time() - t0:.1f}s:\n{tune}")
 
     # ---------------------------------------------------------------- precision policy
@@ -263,9 +266,6 @@ def main():
     mixed = summary(step_mx, ms_mx, per_mx)
     log(f"mixed ragged: {ms_mx:.2f} ms/step {mixed}")
     logl_mixed = logL.cpu().numpy().copy()
-    # logL kernels alone (no chain) of the adaptive step: the MH groups timed through gb_loglik
-    ms_ad_logl = float(sum(t for key, _, t in kern if key[0] == "mh"))
-    adaptive["logl_only_evals_per_s"] = round(rows / (ms_ad_logl * 1e-3), 1)
 
     def time_calls(fn, reps):
         """Mean time of one call of fn (a sequence of launches on `stream`), HIP events."""
@@ -278,6 +278,13 @@ def main():
             b.record(stream)
         torch.cuda.synchronize()
         return float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+    # logL kernels alone (no chain) of the adaptive step: its MH plan (every window, one
+    # persistent launch per (N, C, precision) bucket) through gb_loglik, the batching of the FP64
+    # ragged figure below
+    p_mh = step_ad[0][2]
+    ms_ad_logl = time_calls(lambda: api.gb_loglik(p_mh.handle, d, w, th, logL, None, stream), args.steps)
+    adaptive["logl_only_evals_per_s"] = round(rows / (ms_ad_logl * 1e-3), 1)
 
     # FP64 ragged: the headline's plan structure (one MH call over all windows: one persistent
     # logL launch per (N, C) bucket, one chain launch) with every window in FP64, so that mixed
@@ -765,6 +772,7 @@ def posterior_leg(n_sources, log):
                                torch.as_tensor(wl.weights, device="cuda"))
     src = wl.windows[0].sources[0]
     box = wl.window_box(0)
+    D.tune_on_windows(ctx, row[None, :], be.d, be.w, [box], per_window=10000)
     D.annealed_posterior(be, src, box, np.random.default_rng(0), n=10000)   # warm-up (plans, code)
     times, acc = [], []
     for k in range(n_sources):
@@ -783,7 +791,7 @@ def posterior_leg(n_sources, log):
 
 def configs_leg(log, reps: int = 5):
     """Throughput of the other workloads, each at its full size on the device (inputs resident,
-    autotuned launch shapes, HIP events around the call, mean of `reps` after one untimed call):
+    launch shapes tuned on the workload's own windows, HIP events around the call, mean of `reps` after one untimed call):
     C1 (1,000 candidates, one window), C2 (10,000 candidates in the reduced box of three
     overlapping GBs, then the 10,000-step chain: the MH stage), C4 (64 windows x 4,096 gradients)
     and C5 (4,000 full-band windows x 512 DE candidates, logL as the search scores them).  Per
@@ -839,6 +847,7 @@ def configs_leg(log, reps: int = 5):
         th = torch.as_tensor(wl.theta, device="cuda")
         rows = len(wl.theta)
         logL = torch.empty(rows, dtype=torch.float64, device="cuda")
+        api.gb_autotune_windows(ctx.handle, wl.window_table(), d, w, th, 2)
         r = {"workload": wl.name}
         for pname, prec in (("fp64", api.GB_FP64), ("mixed", api.GB_MIXED)):
             p = api.Plan(ctx, wl.window_table(), prec)
@@ -915,8 +924,11 @@ def pipeline_leg(segments, log, precision: str = "mixed", catalogue=None, noise:
     _, comps = p.loglik(torch.as_tensor(inj, device="cuda"), comps=True)
     rho_opt = np.sqrt(comps[:, 1].cpu().numpy())
     p.close()
+    t_tune = time.time()
+    D.tune_on_windows(ctx, table, d, w, boxes, per_window=512)
     log(f"pipeline: {wl.n_win} segments {segs[0, 0] * 1e3:.3f}-{segs[-1, 1] * 1e3:.3f} mHz, {len(inj)} injected "
-        f"({int((rho_opt > 9).sum())} with optimal SNR > 9), setup {time.time() - t_setup:.1f} s")
+        f"({int((rho_opt > 9).sum())} with optimal SNR > 9), setup {time.time() - t_setup:.1f} s "
+        f"(launch shapes tuned on the segments in {time.time() - t_tune:.1f} s)")
 
     prec = {"mixed": api.GB_MIXED, "fp64": api.GB_FP64}[precision]
 

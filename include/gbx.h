@@ -169,6 +169,20 @@ gb_status gb_mh_step(gb_plan* plan, const double* d, const double* w, const doub
  * `report` (host, may be NULL) receives a text summary of at most report_len bytes. */
 gb_status gb_autotune(gb_ctx* ctx, int reps, char* report, size_t report_len);
 
+/* As gb_autotune, but timed on real work: the windows' (N, C) groups, in both precisions, with
+ * the data d, weights w and candidates theta laid out as for gb_loglik (d, w, theta: device,
+ * covering every window's data_off + C W bins and cand_off + n_cand rows; windows: host [n_win],
+ * their precision field ignored, C = 0 resolved by the rule of Sec. II).  Each group is timed
+ * over its windows' candidates in window order, up to 2^19 of them.  Families that no window
+ * exercises keep their previous choice.  The choice is kept in the context and used by plans
+ * created afterwards (existing plans keep theirs).  Synchronous on the null stream; allocates;
+ * the outputs of the timed launches go to scratch of its own.  `report` as in gb_autotune (the
+ * count after "ms /" is the candidates timed).  GB_EINVAL: bad window (as gb_plan_create) or
+ * null array. */
+gb_status gb_autotune_windows(gb_ctx* ctx, const gb_window* windows, int n_win, const double* d,
+                              const double* w, const double* theta, int reps, char* report,
+                              size_t report_len);
+
 /* Set the launch shape of one (precision, mode, N, C) group by hand, as gb_autotune would:
  * for repeating a tuned configuration exactly (for example in a profiling run).  mode:
  * 1 = likelihood, 2 = gradient.  The shape must be one of the compiled variants (the

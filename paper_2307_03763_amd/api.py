@@ -23,7 +23,7 @@ PRECISION = {"fp64": GB_FP64, "mixed": GB_MIXED, "per_window": GB_PER_WINDOW}
 
 EXPORTS = ("gb_create", "gb_destroy", "gb_last_error", "gb_waveform", "gb_channels", "gb_plan_create",
            "gb_plan_destroy", "gb_plan_info", "gb_window_prepare", "gb_loglik", "gb_loglik_grad", "gb_mh_step",
-           "gb_autotune", "gb_select_variant", "gb_fisher", "gb_kde_logpdf", "gb_add_templates",
+           "gb_autotune", "gb_autotune_windows", "gb_select_variant", "gb_fisher", "gb_kde_logpdf", "gb_add_templates",
            "gb_noise_estimate", "gb_noise_estimate_noalloc", "gb_noise_global", "gb_de_trial", "gb_de_select")
 
 
@@ -91,6 +91,8 @@ def lib():
         L.gb_mh_step.restype = st
         L.gb_autotune.argtypes = [_vp, i, ctypes.c_char_p, ctypes.c_size_t]
         L.gb_autotune.restype = st
+        L.gb_autotune_windows.argtypes = [_vp, _vp, i, _vp, _vp, _vp, i, ctypes.c_char_p, ctypes.c_size_t]
+        L.gb_autotune_windows.restype = st
         L.gb_select_variant.argtypes = [_vp, i, i, i, i, i, i, i]
         L.gb_select_variant.restype = st
         L.gb_fisher.argtypes = [_vp, _vp, _vp, i, ctypes.POINTER(gb_window), _vp, _vp, _vp]
@@ -274,6 +276,32 @@ def gb_autotune(ctx: int, reps: int = 5) -> str:
     buf = ctypes.create_string_buffer(16384)
     _check(lib().gb_autotune(ctx, reps, buf, len(buf)), "gb_autotune")
     return buf.value.decode()
+
+
+def gb_autotune_windows(ctx: int, table, d: torch.Tensor, w: torch.Tensor, theta: torch.Tensor, reps: int = 3) -> str:
+    """Launch shapes timed on the windows of `table` with their own data d, weights w and
+    candidates theta [rows, 8]; returns the report of the families it tuned."""
+    arr = windows_array(table)
+    plan = gb_plan_create(ctx, table, GB_FP64)   # the sizes the windows need (C = 0 resolved)
+    try:
+        _check_data(plan, d, w)
+        _check_cand(plan, theta, [])
+    finally:
+        gb_plan_destroy(plan)
+    buf = ctypes.create_string_buffer(16384)
+    _check(lib().gb_autotune_windows(ctx, arr, len(arr), _dev(_real_view(d), torch.float64, "d"),
+                                     _dev(w, torch.float64, "w"), _dev(theta, torch.float64, "theta"), reps,
+                                     buf, len(buf)), "gb_autotune_windows")
+    return buf.value.decode()
+
+
+def merge_tuning(base: str, override: str) -> str:
+    """A tuning report with the lines of `override` in place of `base`'s lines for the same
+    (precision, mode, N, C) family."""
+    head = lambda line: line.split(":", 1)[0]
+    over = {head(l): l for l in override.splitlines() if l.strip()}
+    out = [over.pop(head(l), l) for l in base.splitlines() if l.strip()]
+    return "\n".join(out + list(over.values())) + "\n"
 
 
 def gb_select_variant(ctx: int, precision: int, mode: int, N: int, C: int, lanes_per_template: int,

@@ -377,7 +377,11 @@ extern "C" gb_status gb_plan_create(gb_ctx* c, const gb_window* windows, int n_w
       gb_plan_destroy(p);
       return fail(GB_EUNSUPPORTED, "no kernel variant for N=%d C=%d", b.N, b.C);
     }
-    const int cpb = b.v[MODE_LOGLIK]->WPB * 64 / b.v[MODE_LOGLIK]->LPC;
+    // tiles hold a whole number of workgroup passes of every mode's kernel (the counts are powers
+    // of two, so the largest is a multiple of the others)
+    int cpb = 0;
+    for (int m = 1; m < 3; ++m)
+      if (b.v[m]) cpb = std::max(cpb, b.v[m]->WPB * 64 / b.v[m]->LPC);
     const int tsz = cpb * kTileIters;
     std::vector<Tile> tiles;
     for (size_t k = s; k < t; ++k) {
@@ -998,6 +1002,37 @@ extern "C" gb_status gb_select_variant(gb_ctx* c, gb_precision prec, int mode, i
               prec == GB_FP64 ? "double" : "float", N, lpc, C, wpb, mode, occ);
 }
 
+// Mean time of `reps` launches of variant v over a.tiles (after one warm-up launch) on the null
+// stream, with the persistent grid a plan would give it.
+static hipError_t time_variant(const gb_ctx* c, const Variant& v, BatchArgs& a, int reps, hipEvent_t e0,
+                               hipEvent_t e1, float* ms) {
+  int nb = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, v.fn, v.WPB * 64, lds_bytes(v));
+  if (e != hipSuccess) return e;
+  const dim3 grid((unsigned)std::max(1, std::min(a.n_tiles, std::max(1, nb) * c->n_cu)));
+  if (launch(&v, grid, a, 0) != GB_OK) return hipErrorLaunchFailure;  // warm-up
+  e = hipEventRecord(e0, 0);
+  for (int r = 0; r < reps && e == hipSuccess; ++r)
+    if (launch(&v, grid, a, 0) != GB_OK) e = hipErrorLaunchFailure;
+  if (e == hipSuccess) e = hipEventRecord(e1, 0);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  *ms = 0.0f;
+  if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+  *ms /= (float)reps;
+  return e;
+}
+
+// One line of a tuning report.
+static std::string tune_line(int prec, int mode, int N, int C, const Variant& v, float ms, int64_t n, int tried) {
+  char line[256];
+  std::snprintf(line, sizeof line,
+                "%s %s N=%d C=%d: lanes/template=%d min waves/SIMD=%d %.4f ms / %lld (%d variants) "
+                "kernel=k_batch<%s,%d,%d,%d,%d,%d,%d>\n",
+                prec == GB_FP64 ? "fp64 " : "mixed", mode == MODE_GRAD ? "grad  " : "loglik", N, C, v.LPC, v.occ,
+                ms, (long long)n, tried, prec == GB_FP64 ? "double" : "float", N, v.LPC, C, v.WPB, mode, v.occ);
+  return line;
+}
+
 // Time every compiled variant of each (precision, N, C, mode) family on synthetic candidates
 // (one window of W = N bins at 8 mHz, 16384 candidates) and keep the fastest in the context.
 extern "C" gb_status gb_autotune(gb_ctx* c, int reps, char* report, size_t report_len) {
@@ -1071,9 +1106,6 @@ extern "C" gb_status gb_autotune(gb_ctx* c, int reps, char* report, size_t repor
             std::vector<Tile> tiles;
             for (int c0 = 0; c0 < B; c0 += tsz) tiles.push_back(Tile{0, std::min(tsz, B - c0), c0});
             e = hipMemcpy(d_tiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice);
-            int nb = 0;
-            if (e == hipSuccess)
-              e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, v.fn, v.WPB * 64, lds_bytes(v));
             if (e != hipSuccess) break;
             BatchArgs a = base_args(c, N, prec);
             a.wins = d_win;
@@ -1085,20 +1117,9 @@ extern "C" gb_status gb_autotune(gb_ctx* c, int reps, char* report, size_t repor
             a.theta = d_th;
             a.logL = d_l;
             a.grad = d_g;
-            const dim3 grid((unsigned)std::max(1, std::min((int)tiles.size(), std::max(1, nb) * c->n_cu)));
-            gb_status s = launch(&v, grid, a, 0);  // warm-up
-            if (s != GB_OK) {
-              e = hipErrorLaunchFailure;
-              break;
-            }
-            e = hipEventRecord(e0, 0);
-            for (int r = 0; r < reps && e == hipSuccess; ++r)
-              if (launch(&v, grid, a, 0) != GB_OK) e = hipErrorLaunchFailure;
-            if (e == hipSuccess) e = hipEventRecord(e1, 0);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
             float ms = 0.0f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            ms /= (float)reps;
+            e = time_variant(c, v, a, reps, e0, e1, &ms);
+            if (e != hipSuccess) break;
             ++tried;
             if (!best || ms < best_ms) {
               best = &v;
@@ -1107,14 +1128,7 @@ extern "C" gb_status gb_autotune(gb_ctx* c, int reps, char* report, size_t repor
           }
           if (best) {
             c->choice[prec][ni][C - 2][mode] = best;
-            char line[256];
-            std::snprintf(line, sizeof line,
-                          "%s %s N=%d C=%d: lanes/template=%d min waves/SIMD=%d %.4f ms / %d (%d variants) "
-                          "kernel=k_batch<%s,%d,%d,%d,%d,%d,%d>\n",
-                          prec == GB_FP64 ? "fp64 " : "mixed", mode == MODE_GRAD ? "grad  " : "loglik", N, C,
-                          best->LPC, best->occ, best_ms, B, tried, prec == GB_FP64 ? "double" : "float", N,
-                          best->LPC, C, best->WPB, mode, best->occ);
-            rep += line;
+            rep += tune_line(prec, mode, N, C, *best, best_ms, B, tried);
           }
         }
   if (e0) (void)hipEventDestroy(e0);
@@ -1122,6 +1136,111 @@ extern "C" gb_status gb_autotune(gb_ctx* c, int reps, char* report, size_t repor
   for (void* p : {(void*)d_th, (void*)d_d, (void*)d_w, (void*)d_l, (void*)d_g, (void*)d_win, (void*)d_tiles, (void*)d_ctr})
     (void)hipFree(p);
   if (e != hipSuccess) return fail(GB_EHIP, "gb_autotune: %s", hipGetErrorString(e));
+  if (report && report_len) std::snprintf(report, report_len, "%s", rep.c_str());
+  return GB_OK;
+}
+
+static const int64_t kTuneMaxCand = 1 << 19;  // candidates timed per (N, C) group of gb_autotune_windows
+
+// Time every compiled variant on the (N, C) groups of the given windows, in both precisions, with
+// their own data, weights and candidates; keep the fastest of each (precision, N, C, mode) family
+// in the context.  Each group is timed over its windows' candidates, in window order, up to
+// kTuneMaxCand of them (whole tiles).
+extern "C" gb_status gb_autotune_windows(gb_ctx* c, const gb_window* windows, int n_win, const double* d,
+                                         const double* w, const double* theta, int reps, char* report,
+                                         size_t report_len) {
+  if (!c) return fail(GB_EINVAL, "gb_autotune_windows: null context");
+  if (n_win < 0 || (n_win > 0 && !windows)) return fail(GB_EINVAL, "gb_autotune_windows: bad window array");
+  if (n_win > 0 && (!d || !w || !theta)) return fail(GB_EINVAL, "gb_autotune_windows: null array");
+  if (reps < 1) reps = 1;
+  std::string rep;
+  const VariantList& all = all_variants();
+  double *d_l = nullptr, *d_g = nullptr;
+  Tile* d_tiles = nullptr;
+  size_t tile_cap = 0;
+  unsigned* d_ctr = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipMalloc(&d_ctr, 2 * sizeof(unsigned));
+  if (e == hipSuccess) e = hipMemset(d_ctr, 0, 2 * sizeof(unsigned));
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  gb_status st = GB_OK;
+  for (int prec = GB_FP64; prec <= GB_MIXED && e == hipSuccess && st == GB_OK && n_win > 0; ++prec) {
+    gb_plan* p = nullptr;
+    st = gb_plan_create(c, windows, n_win, (gb_precision)prec, &p);
+    if (st != GB_OK) break;
+    if (!d_l && p->rows > 0) {
+      e = hipMalloc(&d_l, sizeof(double) * p->rows);
+      if (e == hipSuccess) e = hipMalloc(&d_g, sizeof(double) * 8 * p->rows);
+    }
+    // (N, C) groups of the windows that hold candidates, in window order
+    std::vector<std::vector<int>> groups(5 * 2);
+    for (int i = 0; i < n_win; ++i)
+      if (p->wins[i].n_cand > 0) groups[n_index(p->wins[i].N) * 2 + p->wins[i].C - 2].push_back(i);
+    for (int gi = 0; gi < 10 && e == hipSuccess; ++gi) {
+      if (groups[gi].empty()) continue;
+      const int N = 64 << (gi / 2), C = 2 + gi % 2;
+      for (int mode = MODE_LOGLIK; mode <= MODE_GRAD && e == hipSuccess; ++mode) {
+        const Variant* best = nullptr;
+        float best_ms = 0.0f;
+        int64_t best_n = 0;
+        int tried = 0;
+        for (int i = 0; i < all.n && e == hipSuccess; ++i) {
+          const Variant& v = all.v[i];
+          if (v.prec != prec || v.N != N || v.C != C || v.mode != mode) continue;
+          const int tsz = v.WPB * 64 / v.LPC * kTileIters;
+          std::vector<Tile> tiles;
+          int64_t n = 0;
+          for (int wi : groups[gi]) {
+            for (int64_t c0 = 0; c0 < p->wins[wi].n_cand && n < kTuneMaxCand; c0 += tsz) {
+              const int32_t k = (int32_t)std::min<int64_t>(tsz, p->wins[wi].n_cand - c0);
+              tiles.push_back(Tile{wi, k, c0});
+              n += k;
+            }
+            if (n >= kTuneMaxCand) break;
+          }
+          if (tiles.size() > tile_cap) {
+            (void)hipFree(d_tiles);
+            d_tiles = nullptr;
+            tile_cap = tiles.size();
+            e = hipMalloc(&d_tiles, sizeof(Tile) * tile_cap);
+          }
+          if (e == hipSuccess)
+            e = hipMemcpy(d_tiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice);
+          if (e != hipSuccess) break;
+          BatchArgs a = base_args(c, N, prec);
+          a.wins = p->d_wins;
+          a.tiles = d_tiles;
+          a.n_tiles = (int)tiles.size();
+          a.ctr = d_ctr;
+          a.d = d;
+          a.w = w;
+          a.theta = theta;
+          a.logL = d_l;
+          a.grad = d_g;
+          float ms = 0.0f;
+          e = time_variant(c, v, a, reps, e0, e1, &ms);
+          if (e != hipSuccess) break;
+          ++tried;
+          if (!best || ms < best_ms) {
+            best = &v;
+            best_ms = ms;
+            best_n = n;
+          }
+        }
+        if (best && e == hipSuccess) {
+          c->choice[prec][gi / 2][C - 2][mode] = best;
+          rep += tune_line(prec, mode, N, C, *best, best_ms, best_n, tried);
+        }
+      }
+    }
+    gb_plan_destroy(p);
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  for (void* q : {(void*)d_l, (void*)d_g, (void*)d_tiles, (void*)d_ctr}) (void)hipFree(q);
+  if (st != GB_OK) return st;
+  if (e != hipSuccess) return fail(GB_EHIP, "gb_autotune_windows: %s", hipGetErrorString(e));
   if (report && report_len) std::snprintf(report, report_len, "%s", rep.c_str());
   return GB_OK;
 }

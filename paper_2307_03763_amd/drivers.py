@@ -151,6 +151,26 @@ def _to_theta(x: np.ndarray) -> np.ndarray:
     return I.from_table1(u)
 
 
+def tune_on_windows(ctx, table, d, w, boxes, per_window: int = 512, rng: Optional[np.random.Generator] = None,
+                    reps: int = 2) -> str:
+    """Launch shapes of ``ctx`` chosen on the work a search or a posterior gives it: the windows of
+    ``table`` on the data d and weights w, with ``per_window`` candidates each drawn uniformly in
+    the window's Table I box (as a DE population starts; amplitude at the reference value), timed
+    by gb_autotune_windows.  Plans created afterwards use the choice; returns its report."""
+    import torch
+    from . import api
+    rng = np.random.default_rng(0) if rng is None else rng
+    lo, hi = _box_arrays(boxes)
+    lo, hi = lo[:, list(SEARCH_DIMS)], hi[:, list(SEARCH_DIMS)]
+    t = np.asarray(table, dtype=np.int64).reshape(len(table), -1).copy()
+    n = len(t)
+    x = lo[:, None, :] + rng.random((n, per_window, lo.shape[1])) * (hi - lo)[:, None, :]
+    th = torch.as_tensor(_to_theta(x).reshape(-1, 8), dtype=torch.float64, device="cuda")
+    t[:, 6] = np.arange(n) * per_window
+    t[:, 7] = per_window
+    return api.gb_autotune_windows(ctx.handle, t, d, w, th, reps)
+
+
 def de_search(backend, boxes, rng: np.random.Generator, pop: int = 512, generations: int = 50,
               cr: float = 0.7, f_lo: float = 0.5, f_hi: float = 1.0, init: Optional[np.ndarray] = None,
               keep: int = 1, on_device: Optional[bool] = None, strategy: str = "best1", tol: float = 0.0,

@@ -50,6 +50,23 @@ def test_argument_validation_without_device():
     assert L.gb_mh_step(None, None, None, None, None, None, 1.0, None, None, None, None) == api.GB_EINVAL
     assert L.gb_window_prepare(None, None, None, None) == api.GB_EINVAL
     assert L.gb_plan_info(None, None, None, None) == api.GB_EINVAL
+    assert L.gb_autotune_windows(None, None, 0, None, None, None, 1, None, 0) == api.GB_EINVAL
+
+
+def test_merge_tuning_reports():
+    """A window-tuned line replaces the generic line of its (precision, mode, N, C) family; other
+    lines stay, families only the override holds are appended."""
+    from paper_2307_03763_amd import api
+    base = ("fp64  loglik N=512 C=3: lanes/template=128 min waves/SIMD=3 0.25 ms / 16384 (9 variants) "
+            "kernel=k_batch<double,512,128,3,4,1,3>\n"
+            "mixed grad   N=512 C=3: lanes/template=64 min waves/SIMD=2 0.31 ms / 16384 (6 variants) "
+            "kernel=k_batch<float,512,64,3,4,2,2>\n")
+    over = ("fp64  loglik N=512 C=3: lanes/template=128 min waves/SIMD=3 4.9 ms / 400000 (9 variants) "
+            "kernel=k_batch<double,512,128,3,2,1,3>\n"
+            "mixed loglik N=64 C=2: lanes/template=8 min waves/SIMD=2 0.26 ms / 450000 (4 variants) "
+            "kernel=k_batch<float,64,8,2,4,1,2>\n")
+    out = api.merge_tuning(base, over).splitlines()
+    assert out == [over.splitlines()[0], base.splitlines()[1], over.splitlines()[1]]
 
 
 def test_struct_layouts_match_header():

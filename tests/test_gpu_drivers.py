@@ -144,3 +144,28 @@ def test_posterior_stage(env, graph):
             assert not np.array_equal(prev, th), "each replay draws new proposals"
         prev = th
     plan.close()
+
+
+def test_tune_on_windows_then_search(env):
+    """tune_on_windows tunes the families of the windows it is given (two C4 windows: one (N, C)),
+    on per_window candidates each; a DE search on the tuned context still takes the oracle-driven
+    run's decisions."""
+    banner("drivers: launch shapes tuned on two C4 windows, then the DE search of the first test")
+    api, D, O, wl = env["api"], env["D"], env["O"], env["c4"]
+    be, ctx, d_t, w_t, tab = _gpu_backend(api, D, wl, [0, 1], api.GB_FP64)
+    boxes = [wl.window_box(0), wl.window_box(1)]
+    be.close()
+    rep = D.tune_on_windows(ctx, tab, d_t, w_t, boxes, per_window=300, rng=np.random.default_rng(1))
+    fam = {(int(tab[i, 2]), int(tab[i, 3])) for i in range(2)}
+    heads = sorted(l.split(":", 1)[0] for l in rep.splitlines() if l.strip())
+    want = sorted(f"{p} N={N} C={C}" for N, C in fam for p in ("fp64  loglik", "mixed loglik", "mixed grad  "))
+    assert heads == want, (heads, want)
+    assert all("/ 600 (" in l for l in rep.splitlines() if l.strip()), rep
+    be = D.GpuBackend(ctx, tab, d_t, w_t, api.GB_FP64)
+    th_g, rho_g, hist_g = D.de_search(be, boxes, np.random.default_rng(7), pop=256, generations=40, keep=4,
+                                      on_device=False)
+    th_o, rho_o, hist_o = D.de_search(OracleBackend(O, wl, [0, 1]), boxes, np.random.default_rng(7),
+                                      pop=256, generations=40, keep=4)
+    np.testing.assert_allclose(hist_g, hist_o, rtol=1e-10)
+    np.testing.assert_allclose(th_g, th_o, rtol=1e-9)
+    be.close()

@@ -121,3 +121,62 @@ def test_every_launch_shape(oracle_lib, N, C):
     assert all(ran.get(k, 0) >= 2 for k in ((api.GB_FP64, MODE_LOGLIK), (api.GB_MIXED, MODE_LOGLIK),
                                              (api.GB_MIXED, MODE_GRAD))), ran
     ctx.close()
+
+
+def test_autotune_on_windows(oracle_lib):
+    """gb_autotune_windows tunes exactly the families its windows hold (logL in both precisions,
+    the gradient in mixed), on all of their candidates (37 here), names compiled kernels of those
+    families, and plans created afterwards meet the oracle bars.  Arrays too small for the
+    windows, and null arrays, are refused on the host."""
+    banner("autotune on windows, N=256 C=3")
+    O = oracle_lib
+    wl = _group(O, 256, 3, seed=4242)
+    ref = _reference(O, wl, grad=True)
+    dd = window_dd(wl)
+    ctx = api.context_for(wl.T)
+    d, w, th = dev(wl.data, torch.complex128), dev(wl.weights), dev(wl.theta)
+    table = wl.window_table()
+    rep = api.gb_autotune_windows(ctx.handle, table, d, w, th, 2)
+    banner("  " + rep.replace("\n", "\n[gpu-test]   "))
+    lines = [l for l in rep.splitlines() if l.strip()]
+    heads = sorted(l.split(":", 1)[0] for l in lines)
+    assert heads == ["fp64  loglik N=256 C=3", "mixed grad   N=256 C=3", "mixed loglik N=256 C=3"], heads
+    for l in lines:
+        assert f"/ {int(wl.n_cand.sum())} (" in l, l
+        kern = l.split("kernel=", 1)[1]
+        r, N, lpc, C, wpb, mode, occ = kern[len("k_batch<"):-1].split(",")
+        assert (N, C) == ("256", "3")
+        assert r == ("double" if l.startswith("fp64") else "float")
+        assert mode == ("2" if "grad" in l else "1")
+        api.gb_select_variant(ctx.handle, api.GB_FP64 if r == "double" else api.GB_MIXED, int(mode), 256, 3,
+                              int(lpc), int(wpb), int(occ))      # a compiled variant
+    # re-apply the report (gb_select_variant above leaves the same choice) and check the plans
+    assert api.apply_tuning(ctx.handle, rep) == 3
+    for prec in (api.GB_FP64, api.GB_MIXED):
+        plan = api.Plan(ctx, table, prec)
+        plan.prepare(d, w)
+        l = plan.loglik(th)
+        if prec == api.GB_MIXED:
+            l2, g = plan.loglik_grad(th)
+            g = g.cpu().numpy()
+        torch.cuda.synchronize()
+        l = l.cpu().numpy()
+        for i in range(wl.n_win):
+            a, n = int(wl.cand_off[i]), int(wl.n_cand[i])
+            r = ref[i]
+            if prec == api.GB_FP64:
+                tol = loglik_tolerance(dd[i], r["co"][:, 0], r["co"][:, 1])
+                assert np.all(np.abs(l[a:a + n] - r["lo"]) <= tol), i
+            else:
+                e = delta_logl_error(l[a:a + n], r["lo"], l[a], r["lo"][0]).max()
+                assert e <= max(1e-5, MIXED_SLOPE * r["rho"]), (i, e)
+                err = np.abs(g[a:a + n] - r["go"]) / r["sc"]
+                assert err.max() <= MIXED_NAT, (i, err.max(axis=0))
+        plan.close()
+    with pytest.raises(ValueError):
+        api.gb_autotune_windows(ctx.handle, table, d, w, th[:-1], 1)
+    with pytest.raises(ValueError):
+        api.gb_autotune_windows(ctx.handle, table, d[:-1], w, th, 1)
+    arr = api.windows_array(table)
+    assert api.lib().gb_autotune_windows(ctx.handle, arr, len(arr), None, None, None, 1, None, 0) == api.GB_EINVAL
+    ctx.close()
