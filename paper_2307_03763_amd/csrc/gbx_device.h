@@ -105,6 +105,18 @@ __device__ __forceinline__ void sincos_rev(double x, double* s, double* c) {
   *s = (q & 2) ? -a : a;
   *c = (q == 1 || q == 2) ? -b : b;
 }
+// sin and cos of an angle x in radians: x = n 2 pi + r by a two-part 2 pi (Cody-Waite:
+// the head is 2 pi rounded to double, the tail the next 53 bits; each product is removed with
+// one rounding), then sincos_rev of r / 2 pi.  Absolute error about 5e-16 for |x| up to 1e6.
+// Used for the per-candidate angles, in place of the general library routine (whose
+// large-argument machinery every lane of a template would run).
+__device__ __forceinline__ void sincos_rad(double x, double* s, double* c) {
+  const double n = rint(x * (0.5 / kPi));
+  double r = fma(-n, 6.283185307179586, x);  // 2 pi, head
+  r = fma(-n, 2.4492935982947064e-16, r);    // 2 pi, tail
+  sincos_rev(r * (0.5 / kPi), s, c);
+}
+
 // FP32: the hardware transcendentals, which take their argument in revolutions (|x| <= 1 on
 // every call here).
 __device__ __forceinline__ void sincos_rev(float x, float* s, float* c) {
@@ -212,11 +224,12 @@ __device__ __forceinline__ Cand<R> make_cand(const double* th, double T) {
   s.q = (int64_t)floor(f0 * T);
   s.df = f0 - (double)s.q / T;
   s.phi0c = ph * (0.5 / kPi);
-  double sb, cb, sl, cl, s2, c2;
-  sincos(be, &sb, &cb);
-  sincos(la, &sl, &cl);
-  sincos(2.0 * ps, &s2, &c2);
-  const double ci = cos(io);
+  double sb, cb, sl, cl, s2, c2, si, ci;
+  sincos_rad(be, &sb, &cb);
+  sincos_rad(la, &sl, &cl);
+  sincos_rad(2.0 * ps, &s2, &c2);
+  sincos_rad(io, &si, &ci);
+  (void)si;
   s.kxd = -cb * cl;
   s.kyd = -cb * sl;
   s.k[0] = (R)(-cb * cl);
@@ -542,8 +555,8 @@ template <class R>
 __device__ __forceinline__ CandG<R> make_cand_grad(const double* th, bool ok) {
   CandG<R> g;
   double sb, cb, sl, cl;
-  sincos(ok ? th[2] : 0.0, &sb, &cb);
-  sincos(ok ? th[3] : 0.0, &sl, &cl);
+  sincos_rad(ok ? th[2] : 0.0, &sb, &cb);
+  sincos_rad(ok ? th[3] : 0.0, &sl, &cl);
   g.sb = (R)sb;
   g.cb = (R)cb;
   g.wl[0] = (R)cl;

@@ -242,8 +242,8 @@ __device__ __forceinline__ void process_grad(const BatchArgs& a, const DevWin& w
     } else {
       a.logL[row] = -0.5 * ((w.dd - v[1]) + v[0]);
       double si, ci, s2, c2;
-      sincos(th[5], &si, &ci);
-      sincos(2.0 * th[6], &s2, &c2);
+      sincos_rad(th[5], &si, &ci);
+      sincos_rad(2.0 * th[6], &s2, &c2);
       const double Ap = 1.0 + ci * ci, Ac = -2.0 * ci;
       const double apx = Ap * c2, apy = Ac * s2, axx = Ap * s2, axy = -Ac * c2;
       const double gur = v[7], gui = v[8], gvr = v[9], gvi = v[10];
