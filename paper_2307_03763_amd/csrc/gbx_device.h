@@ -105,6 +105,35 @@ __device__ __forceinline__ void sincos_rev(double x, double* s, double* c) {
   *s = (q & 2) ? -a : a;
   *c = (q == 1 || q == 2) ? -b : b;
 }
+// sin and cos of 2 pi x for |x| <= 0.07 revolution (|theta| <= 0.44), by the Taylor series at
+// theta = 2 pi x with no reduction: sin to theta^13 and cos to theta^14 (first omitted terms
+// below 4e-18 and 1e-19).  The spacecraft phase factors take it where the short sinc series
+// applies: 2 pi f L/c <= 1.5 bounds their argument f k.p/(2c), |p| = L/sqrt3, by 0.069.
+// FP32 keeps the hardware unit.
+__device__ __forceinline__ void sincos_rev_small(double x, double* s, double* c) {
+  const double th = x * (2.0 * kPi);
+  const double t2 = th * th;
+  double ps = 1.0 / 6227020800.0;          // 1/13!
+  ps = fma(ps, t2, -1.0 / 39916800.0);     // -1/11!
+  ps = fma(ps, t2, 1.0 / 362880.0);        // 1/9!
+  ps = fma(ps, t2, -1.0 / 5040.0);         // -1/7!
+  ps = fma(ps, t2, 1.0 / 120.0);           // 1/5!
+  ps = fma(ps, t2, -1.0 / 6.0);            // -1/3!
+  *s = fma(ps * t2, th, th);
+  double pc = 1.0 / 87178291200.0;         // 1/14!
+  pc = fma(pc, t2, -1.0 / 479001600.0);    // -1/12!
+  pc = fma(pc, t2, 1.0 / 3628800.0);       // 1/10!
+  pc = fma(pc, t2, -1.0 / 40320.0);        // -1/8!
+  pc = fma(pc, t2, 1.0 / 720.0);           // 1/6!
+  pc = fma(pc, t2, -1.0 / 24.0);           // -1/4!
+  pc = fma(pc, t2, 0.5);                   // 1/2!
+  *c = fma(-pc, t2, 1.0);
+}
+__device__ __forceinline__ void sincos_rev_small(float x, float* s, float* c) {
+  *s = __builtin_amdgcn_sinf(x);
+  *c = __builtin_amdgcn_cosf(x);
+}
+
 // sin and cos of an angle x in radians: x = n 2 pi + r by a two-part 2 pi (Cody-Waite:
 // the head is 2 pi rounded to double, the tail the next 53 bits; each product is removed with
 // one rounding), then sincos_rev of r / 2 pi.  Absolute error about 5e-16 for |x| up to 1e6.
@@ -249,6 +278,33 @@ __device__ __forceinline__ Cand<R> make_cand(const double* th, double T) {
   return s;
 }
 
+// Element m of field f of an orbit table [OB_FIELDS][N].  BUF (the FP64 kernels) reads through a
+// buffer resource over the whole table: the per-lane byte offset of sample m (one VGPR, shared
+// by the fourteen reads of a sample) plus the field's row offset as a scalar, so no per-lane
+// 64-bit address arithmetic is formed; the resource's word 3 is the gfx9-family raw-buffer
+// setting, and a read past the table's bytes would return zero (m never leaves [0, N)).
+// Measured: the FP64 short sample loop loses 30 of its 457 instructions; the single-precision
+// kernels, whose scalar registers are scarcer, ran slower with it and index plainly.
+template <bool BUF, class T>
+__device__ __forceinline__ T ob_at(const T* __restrict__ tab, int f, int N, int m) {
+  if constexpr (BUF) {
+    const __amdgpu_buffer_rsrc_t r =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(tab), (short)0, OB_FIELDS * N * (int)sizeof(T), 0x00020000);
+    const int boff = m * (int)sizeof(T), soff = f * N * (int)sizeof(T);
+    T x;
+    if constexpr (sizeof(T) == 8) {
+      const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, boff, soff, 0);
+      __builtin_memcpy(&x, &v, 8);
+    } else {
+      const auto v = __builtin_amdgcn_raw_buffer_load_b32(r, boff, soff, 0);
+      __builtin_memcpy(&x, &v, 4);
+    }
+    return x;
+  } else {
+    return tab[f * N + m];
+  }
+}
+
 // One sample of the slow series of channels A, E[, T] (without their normalisations) for unit
 // amplitude at t = tab time m.
 // ob64: FP64 orbit table [OB_FIELDS][N]; obR: the same in precision R (fields >= OB_N12).
@@ -256,9 +312,10 @@ template <class R, int C, bool TDI2, bool SHORT>
 __device__ __forceinline__ void slow_sample(const Cand<R>& s, const double* __restrict__ ob64,
                                             const R* __restrict__ obR, int N, int m, double t,
                                             double Lc, cplx<R> out[C]) {
+  constexpr bool BUF = sizeof(R) == 8;  // orbit reads through a buffer resource (ob_at)
   // common phase in cycles (FP64), reduced to [-1/2, 1/2]
   const double f = s.f0 + s.fd * t;
-  const double kR = s.kxd * ob64[OB_RX * N + m] + s.kyd * ob64[OB_RY * N + m];
+  const double kR = s.kxd * ob_at<BUF>(ob64, OB_RX, N, m) + s.kyd * ob_at<BUF>(ob64, OB_RY, N, m);
   double p = s.df * t + 0.5 * s.fd * t * t + s.phi0c - f * (0.5 * Lc + kR);
   p -= rint(p);
   R sp, cp;
@@ -274,7 +331,7 @@ __device__ __forceinline__ void slow_sample(const Cand<R>& s, const double* __re
 #pragma unroll
   for (int a = 0; a < 2; ++a) {
     const int o = OB_N12 + 3 * a;
-    const R n0 = obR[(o + 0) * N + m], n1 = obR[(o + 1) * N + m], n2 = obR[(o + 2) * N + m];
+    const R n0 = ob_at<BUF>(obR, o + 0, N, m), n1 = ob_at<BUF>(obR, o + 1, N, m), n2 = ob_at<BUF>(obR, o + 2, N, m);
     kn[a] = s.k[0] * n0 + s.k[1] * n1 + s.k[2] * n2;
     un[a] = s.u[0] * n0 + s.u[1] * n1 + s.u[2] * n2;
     vn[a] = s.v[0] * n0 + s.v[1] * n1;
@@ -292,7 +349,8 @@ __device__ __forceinline__ void slow_sample(const Cand<R>& s, const double* __re
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     const int o = OB_P1 + 3 * i;
-    kp[i] = s.k[0] * obR[(o + 0) * N + m] + s.k[1] * obR[(o + 1) * N + m] + s.k[2] * obR[(o + 2) * N + m];
+    kp[i] = s.k[0] * ob_at<BUF>(obR, o + 0, N, m) + s.k[1] * ob_at<BUF>(obR, o + 1, N, m) +
+            s.k[2] * ob_at<BUF>(obR, o + 2, N, m);
   }
   // e^{i pi f k.dx_i / c} per spacecraft; the offsets from the guiding centre sum to zero, so
   // the third factor is the conjugate of the product of the other two
@@ -300,7 +358,10 @@ __device__ __forceinline__ void slow_sample(const Cand<R>& s, const double* __re
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
     R sc, cc;
-    sincos_rev((R)0.5 * fr * kp[i], &sc, &cc);
+    if (SHORT)
+      sincos_rev_small((R)0.5 * fr * kp[i], &sc, &cc);
+    else
+      sincos_rev((R)0.5 * fr * kp[i], &sc, &cc);
     ph[i] = mk<R>(cc, sc);
   }
   ph[2] = conjg(ph[0] * ph[1]);
@@ -591,8 +652,9 @@ __device__ __forceinline__ void grad_sample_rev(const Cand<R>& s, const CandG<R>
                                                 int N, int m, double t, double Lc, const cplx<R> sbar[C],
                                                 GradAcc& acc) {
   const R twopi = (R)(2.0 * kPi), pi = (R)kPi;
+  constexpr bool BUF = sizeof(R) == 8;  // orbit reads through a buffer resource (ob_at)
   const double f = s.f0 + s.fd * t;
-  const double Rx = ob64[OB_RX * N + m], Ry = ob64[OB_RY * N + m];
+  const double Rx = ob_at<BUF>(ob64, OB_RX, N, m), Ry = ob_at<BUF>(ob64, OB_RY, N, m);
   const double kR = s.kxd * Rx + s.kyd * Ry;
   double p = s.df * t + 0.5 * s.fd * t * t + s.phi0c - f * (0.5 * Lc + kR);
   p -= rint(p);
@@ -629,7 +691,7 @@ __device__ __forceinline__ void grad_sample_rev(const Cand<R>& s, const CandG<R>
 #pragma unroll
   for (int a = 0; a < 2; ++a) {
     const int o = OB_N12 + 3 * a;
-    const R n0 = obR[(o + 0) * N + m], n1 = obR[(o + 1) * N + m], n2 = obR[(o + 2) * N + m];
+    const R n0 = ob_at<BUF>(obR, o + 0, N, m), n1 = ob_at<BUF>(obR, o + 1, N, m), n2 = ob_at<BUF>(obR, o + 2, N, m);
     kn[a] = s.k[0] * n0 + s.k[1] * n1 + s.k[2] * n2;
     un[a] = s.u[0] * n0 + s.u[1] * n1 + s.u[2] * n2;
     vn[a] = s.v[0] * n0 + s.v[1] * n1;
@@ -646,7 +708,7 @@ __device__ __forceinline__ void grad_sample_rev(const Cand<R>& s, const CandG<R>
     Fx[a] = (R)2 * un[a] * vn[a];
     if (a == 0) continue;  // spacecraft 3 (arm 12) below
     const int q = OB_P1 + 3 * opp[a];
-    const R p0 = obR[(q + 0) * N + m], p1 = obR[(q + 1) * N + m], p2 = obR[(q + 2) * N + m];
+    const R p0 = ob_at<BUF>(obR, q + 0, N, m), p1 = ob_at<BUF>(obR, q + 1, N, m), p2 = ob_at<BUF>(obR, q + 2, N, m);
     kp[a] = s.k[0] * p0 + s.k[1] * p1 + s.k[2] * p2;
     up[a] = s.u[0] * p0 + s.u[1] * p1 + s.u[2] * p2;
     vp[a] = s.v[0] * p0 + s.v[1] * p1;
