@@ -703,22 +703,15 @@ def committed_traffic(kernel: str, evals: int):
         return None
     h = kernel_source_hash()
     want = kernel.replace(" ", "")
-    family = want.rsplit(",", 1)[0]
-    exact = same_code = None
     for line in open(path):
         if line.lstrip().startswith("#"):
             continue
         f = dict(x.split("=", 1) for x in line.split() if "=" in x)
-        if f.get("kernel_src") != h or "kernel" not in f:
-            continue
-        b = round(float(f["bytes"]) * evals / float(f["evals"]), 1)
-        if f["kernel"] == want:
-            exact = b
-        elif f["kernel"].rsplit(",", 1)[0] == family:
-            # the last template argument only sets the persistent grid (workgroups per CU);
-            # the variants of one family compile to the same machine code
-            same_code = b
-    return exact if exact is not None else same_code
+        # only the same instantiation: the last template argument is the occupancy bound of
+        # __launch_bounds__, which changes the register allocation and so the machine code
+        if f.get("kernel_src") == h and f.get("kernel") == want:
+            return round(float(f["bytes"]) * evals / float(f["evals"]), 1)
+    return None
 
 
 def copy_calibration():
