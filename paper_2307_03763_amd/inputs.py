@@ -522,20 +522,44 @@ def workload_c4(template_fn: Optional[TemplateFn], n_win: int = 64, n_cand: int 
     return finalize_data(wl, template_fn, r_noise, noise)
 
 
+W_MAX = 4096  # the widest padded window (the per-segment median sorts a window's channel in LDS)
+
+
+def split_wide(segs, T: float, w_max: int = W_MAX) -> List[tuple]:
+    """Segments whose padded window (1.5 times the segment) would exceed ``w_max`` bins, cut into
+    the fewest equal parts whose windows fit; the others unchanged."""
+    out = []
+    for fa, fb in segs:
+        n = max(1, math.ceil(1.5 * (fb - fa) * T / w_max))
+        step = (fb - fa) / n
+        out += [(fa + i * step, fa + (i + 1) * step if i + 1 < n else fb) for i in range(n)]
+    return out
+
+
 def workload_c5_windows(n_target: int = 4000, T: float = T2, f_min: float = 0.3e-3,
                         f_max: float = 30e-3) -> tuple:
-    """Full-band windows: Algorithm 1 with B_max scaled by kappa (bisection) so that
-    ``n_target`` segments result; padded W = 3 kappa B_max T clamped to [64, 4096]."""
+    """Full-band windows: Algorithm 1 with B_max scaled by kappa, its segments wider than a
+    4096-bin padded window allows split into equal parts (split_wide: above about 18 mHz
+    Algorithm 1's segments outgrow the window, which would leave their outer bins outside every
+    window), kappa chosen by bisection so that ``n_target`` segments result in all; padded
+    W = 1.5 x segment, in [64, 4096]."""
     lo_k, hi_k = 0.05, 20.0
     for _ in range(60):
         mid = math.sqrt(lo_k * hi_k)
-        n = len(segmenting(f_min, f_max, T, mid))
+        n = len(split_wide(segmenting(f_min, f_max, T, mid), T))
         if n > n_target:
             lo_k = mid
         else:
             hi_k = mid
     kappa = hi_k
-    segs = segmenting(f_min, f_max, T, kappa)
+    # the split makes the count step unevenly with kappa: take the nearest kappa (steps of 1e-4
+    # relative) that gives exactly n_target segments, if one is close
+    for j in sorted(range(-300, 301), key=abs):
+        k = hi_k * (1.0 + 1e-4 * j)
+        if len(split_wide(segmenting(f_min, f_max, T, k), T)) == n_target:
+            kappa = k
+            break
+    segs = split_wide(segmenting(f_min, f_max, T, kappa), T)
     return kappa, segs
 
 
@@ -546,8 +570,8 @@ def nextpow2(x: int) -> int:
 def workload_c5(template_fn: Optional[TemplateFn], n_target: int = 4000, n_gb: int = 20000, pop: int = 512,
                 noise: bool = True, T: float = T2, segments: Optional[tuple] = None) -> Workload:
     """Full band: the windows of Algorithm 1 over 0.3-30 mHz with B_max scaled so that
-    ``n_target`` segments result (workload_c5_windows); each padded by a quarter of its width on
-    both sides (W = 3 kappa B_max T bins, clamped to [64, 4096]).  ``n_gb`` GBs: f0 log-uniform
+    ``n_target`` segments result, the widest split to fit (workload_c5_windows); each padded by
+    a quarter of its width on both sides (W = 1.5 x segment bins, in [64, 4096]).  ``n_gb`` GBs: f0 log-uniform
     0.3-30 mHz, A log-uniform 1e-23..1e-21, fdot from chirp masses 0.1-1 Msun, sources wider than
     1024 - 16 bins rejected (as C3).  Every GB is injected into every window its band overlaps;
     N = nextpow2(widest overlapping band + 16) clamped to [64, 1024]; C by the paper rule at the

@@ -13,7 +13,8 @@ recomputes sampled rows one by one; chains are compared bit for bit.
   against the oracle gradient, and one candidate per window against central differences of the
   FP64 logL (steps of 1e-6 of the Table I widths).
 * C5: 4,000 full-band windows x 512 DE candidates (2.05 M rows): adaptive logL on 2 sampled rows
-  per window.
+  per window; a pair whose candidate template is louder than the policy's SNR 8 (the candidates
+  span the whole prior box) is held to the mixed error model, 2e-6 times that SNR.
 """
 
 import math
@@ -25,6 +26,7 @@ import torch
 from paper_2307_03763_amd import api
 from paper_2307_03763_amd import inputs as I
 from tests.gpu_common import banner, dev, loglik_tolerance
+from tests.test_gpu_parity import MIXED_SLOPE
 
 pytestmark = pytest.mark.gpu
 
@@ -73,7 +75,13 @@ def _sample_rows(wl, per_window, rng):
 
 def _check_rows(O, wl, l_gpu, rows_per_window, prec_w):
     """FP64 windows: |l - l_oracle| within the FP64 bound; mixed windows: logL differences
-    against the window's first sampled row within BAR_MIXED."""
+    against the window's first sampled row within BAR_MIXED (relative to max(1, |difference|)).
+    The precision policy bounds the SNR of the window's sources (<= RHO_MIXED), not that of the
+    candidates: a candidate drawn over the whole prior box (C5) can carry a template far louder.
+    The mixed error grows like the loudest SNR involved (the FP32 template's relative error times
+    its norm), so a pair whose louder template exceeds RHO_MIXED is held to the error model
+    MIXED_SLOPE * rho_template instead, when that is the larger bound.  Returns the worst FP64
+    error over its bound and the worst mixed error over its bound (both pass at <= 1)."""
     g = O.Geometry(wl.T)
     worst64, worstmx = 0.0, 0.0
     for i, r in enumerate(rows_per_window):
@@ -88,8 +96,11 @@ def _check_rows(O, wl, l_gpu, rows_per_window, prec_w):
             tol = loglik_tolerance(dd, co[:, 0], co[:, 1])
             worst64 = max(worst64, float(np.max(np.abs(lg - lo) / tol)))
         elif len(r) > 1:
-            e = np.abs((lg - lg[0]) - (lo - lo[0])) / np.maximum(1.0, np.abs(lo - lo[0]))
-            worstmx = max(worstmx, float(e.max()))
+            err = np.abs((lg - lg[0]) - (lo - lo[0]))
+            bound = BAR_MIXED * np.maximum(1.0, np.abs(lo - lo[0]))
+            rho_t = np.sqrt(np.maximum(co[:, 1], co[0, 1]))
+            bound = np.where(rho_t > RHO_MIXED, np.maximum(bound, MIXED_SLOPE * rho_t), bound)
+            worstmx = max(worstmx, float((err / bound).max()))
     return worst64, worstmx
 
 
@@ -203,8 +214,8 @@ def test_c3_full(oracle_lib, tuned):
     rng = np.random.default_rng(31)
     rows = _sample_rows(wl, 8, rng)
     w64, wmx = _check_rows(O, wl, l, rows, prec_w)
-    banner(f"  FP64 windows: worst |dlogL| / bound {w64:.2f}; mixed windows: worst error {wmx:.2e}")
-    assert w64 <= 1.0 and wmx <= BAR_MIXED
+    banner(f"  FP64 windows: worst |dlogL| / bound {w64:.2f}; mixed windows: worst error / bound {wmx:.2f}")
+    assert w64 <= 1.0 and wmx <= 1.0
     gplan = api.Plan(ctx, wl.window_table(), api.GB_MIXED)
     gplan.prepare(d, w)
     _, grad = gplan.loglik_grad(th)
@@ -270,5 +281,5 @@ def test_c5_full(oracle_lib, tuned):
     rows = _sample_rows(wl, 2, np.random.default_rng(51))
     w64, wmx = _check_rows(O, wl, l, rows, prec_w)
     banner(f"  {int((prec_w == api.GB_MIXED).sum())} mixed windows; FP64 worst |dlogL| / bound {w64:.2f}; "
-           f"mixed worst error {wmx:.2e}")
-    assert w64 <= 1.0 and wmx <= BAR_MIXED
+           f"mixed worst error / bound {wmx:.2f}")
+    assert w64 <= 1.0 and wmx <= 1.0

@@ -431,6 +431,34 @@ def test_paper_numbers():
     assert len(segs) == 4930
 
 
+def test_full_band_windows_cover_their_segments():
+    """The full-band workload: 4000 contiguous segments over 0.3-30 mHz (Algorithm 1 with B_max
+    scaled, the widest split), each inside its padded window of at most 4096 bins, so every bin of
+    the band belongs to some window (the global noise estimate and the search see all of it).
+    Without the split, the windows of Algorithm 1's segments above about 18.5 mHz would hold only
+    21-77% of their segment."""
+    T = I.T2
+    kappa, segs = I.workload_c5_windows(4000, T)
+    segs = np.asarray(segs)
+    assert len(segs) == 4000 and 1.0 < kappa < 2.0
+    # the band is covered: the last Algorithm 1 segment straddles 30 mHz, and its parts divide it
+    assert segs[0, 0] == 0.3e-3 and segs[-1, 1] >= 30e-3
+    assert np.allclose(segs[1:, 0], segs[:-1, 1], rtol=0, atol=1e-15)
+    fa, fb = segs[:, 0], segs[:, 1]
+    W = np.clip(np.round(1.5 * (fb - fa) * T), 64, I.W_MAX).astype(np.int64)
+    k0 = np.floor(0.5 * (fa + fb) * T).astype(np.int64) - W // 2
+    assert np.all(k0 <= np.ceil(fa * T)) and np.all(k0 + W >= np.ceil(fb * T)), "a segment outside its window"
+    # the unsplit Algorithm 1 segmentation at the same kappa does outgrow the window
+    raw = np.asarray(I.segmenting(0.3e-3, 30e-3, T, kappa))
+    assert np.any(1.5 * (raw[:, 1] - raw[:, 0]) * T > I.W_MAX)
+    # split parts are equal and as few as fit
+    for a, b in raw[::25]:
+        parts = I.split_wide([(a, b)], T)
+        n = len(parts)
+        assert n == max(1, int(np.ceil(1.5 * (b - a) * T / I.W_MAX)))
+        assert all(abs((q - p) - (b - a) / n) < 1e-12 * b for p, q in parts)
+
+
 def test_paper_schedule_and_boxes():
     """The constants the drivers and the input generator take from the paper, against its printed
     values: the six-temperature schedule and n_samples of Algorithm 4 (Sec. III G), the psi and
