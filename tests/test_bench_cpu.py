@@ -71,8 +71,8 @@ def test_committed_traffic_lookup(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: h)
     # exact kernel, scaled to the evaluations of a launch
     assert bench.committed_traffic("k_batch<float,512,64,3,4,2,1>", 200000) == 40000000.0
-    # the other persistent-grid variant of the family (same machine code)
-    assert bench.committed_traffic("k_batch<float,512,64,3,4,2,2>", 400000) == 80000000.0
+    # another register budget of the family is another kernel (its own machine code): none
+    assert bench.committed_traffic("k_batch<float,512,64,3,4,2,2>", 400000) is None
     # another family, or counters taken on other kernel sources: none
     assert bench.committed_traffic("k_batch<float,512,64,2,4,2,1>", 400000) is None
     assert bench.committed_traffic("k_batch<float,256,32,2,4,2,2>", 100) is None
