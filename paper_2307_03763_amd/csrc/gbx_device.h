@@ -134,6 +134,34 @@ __device__ __forceinline__ void sincos_rev_small(float x, float* s, float* c) {
   *c = __builtin_amdgcn_cosf(x);
 }
 
+// The link delay D = e^{-2 i x} (x = pi f L/c) for 0 <= x <= 0.75, where the short sinc series
+// applies (2 pi f L/c <= 1.5): the Taylor series of sin x to x^17 and cos x to x^16 (first
+// omitted terms below 4e-20 and 1e-18 at 0.75), no reduction, then the double angle:
+// sin(-2x) = -2 sin x cos x, cos 2x = 1 - 2 sin^2 x.
+__device__ __forceinline__ void delay_short(double x, double* sD, double* cD) {
+  const double x2 = x * x;
+  double ps = 1.0 / 355687428096000.0;     // 1/17!
+  ps = fma(ps, x2, -1.0 / 1307674368000.0);  // -1/15!
+  ps = fma(ps, x2, 1.0 / 6227020800.0);    // 1/13!
+  ps = fma(ps, x2, -1.0 / 39916800.0);     // -1/11!
+  ps = fma(ps, x2, 1.0 / 362880.0);        // 1/9!
+  ps = fma(ps, x2, -1.0 / 5040.0);         // -1/7!
+  ps = fma(ps, x2, 1.0 / 120.0);           // 1/5!
+  ps = fma(ps, x2, -1.0 / 6.0);            // -1/3!
+  const double sx = fma(ps * x2, x, x);
+  double pc = 1.0 / 20922789888000.0;      // 1/16!
+  pc = fma(pc, x2, -1.0 / 87178291200.0);  // -1/14!
+  pc = fma(pc, x2, 1.0 / 479001600.0);     // 1/12!
+  pc = fma(pc, x2, -1.0 / 3628800.0);      // -1/10!
+  pc = fma(pc, x2, 1.0 / 40320.0);         // 1/8!
+  pc = fma(pc, x2, -1.0 / 720.0);          // -1/6!
+  pc = fma(pc, x2, 1.0 / 24.0);            // 1/4!
+  pc = fma(pc, x2, -0.5);                  // -1/2!
+  const double cx = fma(pc, x2, 1.0);
+  *sD = -2.0 * sx * cx;
+  *cD = fma(-2.0 * sx, sx, 1.0);
+}
+
 // sin and cos of an angle x in radians: x = n 2 pi + r by a two-part 2 pi (Cody-Waite:
 // the head is 2 pi rounded to double, the tail the next 53 bits; each product is removed with
 // one rounding), then sincos_rev of r / 2 pi.  Absolute error about 5e-16 for |x| up to 1e6.
@@ -323,7 +351,10 @@ __device__ __forceinline__ void slow_sample(const Cand<R>& s, const double* __re
   const R fr = (R)f;
   const R x = fr * (R)(kPi * Lc);  // pi f L / c
   R sD, cD;
-  sincos_rev(-fr * (R)Lc, &sD, &cD);  // D = e^{-2 pi i f L/c}
+  if constexpr (SHORT && sizeof(R) == 8)
+    delay_short(x, &sD, &cD);  // D = e^{-2 pi i f L/c}, from x = pi f L/c
+  else
+    sincos_rev(-fr * (R)Lc, &sD, &cD);
 
   // projections on the arms; the arm vectors of the rigid triangle sum to zero, so the third
   // arm's projections are minus the sum of the other two
