@@ -1,5 +1,6 @@
 """Brute-force time-domain TDI (test infrastructure): the definition the fast/slow model approximates.
-First- and second-generation equal-arm Michelson combinations.
+First- and second-generation Michelson combinations, with equal arms (the analytic orbits) or
+with one light time per arm (any positions, tdi_xyz_positions).
 
 For tiny cases (M <= 2^18 samples) the TDI X, Y, Z are evaluated at every sample time
 directly from the plane-wave field, with every retardation and delay taken exactly, and
@@ -119,6 +120,60 @@ def tdi_xyz(theta, t, P_orb, L, AU, mode="G1", generation=1):
     Y = michelson(2, 3, 1)
     Z = michelson(3, 1, 2)
     return X, Y, Z
+
+
+def tdi_xyz_positions(theta, t, positions, generation=1):
+    """Michelson X, Y, Z with one light time per arm, G1 geometry: every position, arm vector
+    and arm length at the output time t, from positions(t) -> [3, len(t), 3] (m); only the
+    wave's time arguments are retarded, each link by its own light time L_rs(t)/c.  With
+    Lc = arm 12 and Lb = arm 31 (light times at t):
+      X1 = y13 + y31(t-Lb) + y12(t-2Lb) + y21(t-2Lb-Lc) - y12 - y21(t-Lc) - y13(t-2Lc) - y31(t-2Lc-Lb),
+      X2 = X1(t) - X1(t - 2Lb - 2Lc)  (the frozen arms' delays commute),
+    Y and Z by the cyclic relabelling 1 -> 2 -> 3 -> 1."""
+    pol = polarisation(theta)
+    k = pol[0]
+    t = np.asarray(t, dtype=np.float64)
+    x = positions(t)
+
+    def light(r, s):
+        return np.linalg.norm(x[r] - x[s], axis=-1) / C_LIGHT
+
+    def y(r, s, tau):
+        sep = x[r] - x[s]
+        lrs = np.linalg.norm(sep, axis=-1)
+        n = sep / lrs[..., None]
+        kn = n @ k
+        t_recv = t - tau
+        t_emit = t_recv - lrs / C_LIGHT
+        h_emit = _nHn(theta, pol, n, t_emit - (x[s] @ k) / C_LIGHT)
+        h_recv = _nHn(theta, pol, n, t_recv - (x[r] @ k) / C_LIGHT)
+        return (h_emit - h_recv) / (2.0 * (1.0 - kn))
+
+    def michelson(a, b, c, extra):
+        lab, lac = light(a, b), light(a, c)
+        return (y(a, c, extra) + y(c, a, extra + lac) + y(a, b, extra + 2 * lac) + y(b, a, extra + 2 * lac + lab)
+                - y(a, b, extra) - y(b, a, extra + lab) - y(a, c, extra + 2 * lab) - y(c, a, extra + 2 * lab + lac))
+
+    out = []
+    for a, b, c in ((0, 1, 2), (1, 2, 0), (2, 0, 1)):
+        X = michelson(a, b, c, np.zeros_like(t))
+        if generation == 2:
+            X = X - michelson(a, b, c, 2.0 * (light(a, b) + light(a, c)))
+        out.append(X)
+    return tuple(out)
+
+
+def spectrum_positions(theta, M, dt, positions, chunk=1 << 15, generation=1):
+    """Full-length spectra of A, E, T (as spectrum) for the unequal-arm Michelson combinations of
+    tdi_xyz_positions."""
+    series = np.empty((3, M))
+    for a in range(0, M, chunk):
+        t = dt * np.arange(a, min(M, a + chunk), dtype=np.float64)
+        X, Y, Z = tdi_xyz_positions(theta, t, positions, generation)
+        series[0, a:a + len(t)] = (Z - X) / math.sqrt(2.0)
+        series[1, a:a + len(t)] = (X - 2.0 * Y + Z) / math.sqrt(6.0)
+        series[2, a:a + len(t)] = (X + Y + Z) / math.sqrt(3.0)
+    return dt * np.fft.fft(series, axis=1), series
 
 
 def tdi_aet(theta, t, P_orb, L, AU, mode="G1", generation=1):

@@ -161,7 +161,44 @@ inline V3 cross(V3 a, V3 b) {
 // Rigid equilateral triangle of side L, centred on the guiding centre R(t) on a circle
 // of radius AU, plane tilted by 60 degrees to the ecliptic, rotating once per orbit
 // against the orbital sense ("cartwheel").  Guiding-centre phase 0 at t = 0.
+// Numerical orbits (optional): spacecraft positions on the uniform time grid t_j = t0 + j dt,
+// interpolated by the cubic through four neighbouring nodes (Lagrange form; nodes j-1 .. j+2
+// around t, moved inwards at the ends of the grid).  With a grid set, every arm has its own
+// length |x_r - x_s| at the sample time and the TDI takes one delay per arm; without one, the
+// rigid equal-arm triangle below.
+struct OrbitGrid {
+  std::vector<double> pos;  // [n][3 spacecraft][3 coordinates], m
+  int n = 0;
+  double t0 = 0.0, dt = 0.0;
+};
+OrbitGrid g_orbit;
+
+void spacecraft_grid(double t, V3 x[3]) {
+  const double u = (t - g_orbit.t0) / g_orbit.dt;
+  int j = (int)std::floor(u) - 1;
+  if (j < 0) j = 0;
+  if (j > g_orbit.n - 4) j = g_orbit.n - 4;
+  const double s = u - (double)j;
+  const double w[4] = {-(s - 1.0) * (s - 2.0) * (s - 3.0) / 6.0, s * (s - 2.0) * (s - 3.0) / 2.0,
+                       -s * (s - 1.0) * (s - 3.0) / 2.0, s * (s - 1.0) * (s - 2.0) / 6.0};
+  for (int i = 0; i < 3; ++i) {
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int q = 0; q < 4; ++q)
+      for (int k = 0; k < 3; ++k) acc[k] += w[q] * g_orbit.pos[((size_t)(j + q) * 3 + i) * 3 + k];
+    x[i] = v3(acc[0], acc[1], acc[2]);
+  }
+}
+
+inline double dist(V3 a, V3 b) {
+  const V3 d = sub(a, b);
+  return std::sqrt(d.x * d.x + d.y * d.y + d.z * d.z);
+}
+
 void spacecraft(double t, const Params& p, V3 x[3]) {
+  if (g_orbit.n > 0) {
+    spacecraft_grid(t, x);
+    return;
+  }
   const double a = 2.0 * kPi * t / p.P_orb;
   const V3 rhat = v3(std::cos(a), std::sin(a), 0.0);
   const V3 phat = v3(-std::sin(a), std::cos(a), 0.0);
@@ -238,18 +275,19 @@ R sinc(const R& x) {
 // carrier removed: the real link signal is Re[z e^{2 pi i q t / T}].
 template <class R>
 Cx<R> link(const Source<R>& s, const V3 x[3], int r, int snd, double t, const R& dfreq, const Params& p) {
-  const double n[3] = {(x[r].x - x[snd].x) / p.L, (x[r].y - x[snd].y) / p.L, (x[r].z - x[snd].z) / p.L};
+  const double L = g_orbit.n > 0 ? dist(x[r], x[snd]) : p.L;  // this link's arm length
+  const double n[3] = {(x[r].x - x[snd].x) / L, (x[r].y - x[snd].y) / L, (x[r].z - x[snd].z) / L};
   const R kn = s.k[0] * n[0] + s.k[1] * n[1] + s.k[2] * n[2];
   const R f = s.f0 + s.fdot * t;
-  const R u = kPi * f * p.L * (1.0 - kn) / kC;
+  const R u = kPi * f * L * (1.0 - kn) / kC;
   // n.H.n for the complex field H = A+ e+ - i Ax ex
   const Cx<R> nhn = cx<R>(s.Ap * quad(s.ep, n), -(s.Ac * quad(s.ec, n)));
   const double mid[3] = {0.5 * (x[r].x + x[snd].x), 0.5 * (x[r].y + x[snd].y), 0.5 * (x[r].z + x[snd].z)};
   const R kmid = s.k[0] * mid[0] + s.k[1] * mid[1] + s.k[2] * mid[2];
   // Phi(t) - 2 pi q t / T = 2 pi (df t + fdot t^2 / 2) + phi0, then the travel-time phase
   const R phase = 2.0 * kPi * (dfreq * t + 0.5 * s.fdot * t * t) + s.phi0 -
-                  2.0 * kPi * f * (0.5 * p.L + kmid) / kC;
-  const R amp = kPi * f * p.L / kC * sinc(u);
+                  2.0 * kPi * f * (0.5 * L + kmid) / kC;
+  const R amp = kPi * f * L / kC * sinc(u);
   // z = -i amp nhn e^{i phase}
   const Cx<R> e = expi(phase);
   const Cx<R> z = nhn * e;
@@ -267,8 +305,31 @@ void slow_sample(const Source<R>& s, double t, const R& dfreq, const Params& p, 
   const Cx<R> z13 = link(s, x, 0, 2, t, dfreq, p), z31 = link(s, x, 2, 0, t, dfreq, p);
   const Cx<R> z23 = link(s, x, 1, 2, t, dfreq, p), z32 = link(s, x, 2, 1, t, dfreq, p);
   const R f = s.f0 + s.fdot * t;
-  const Cx<R> D = expi(-(2.0 * kPi * f * p.L / kC));  // one-arm delay at the local frequency
   const Cx<R> one = cx<R>(R(1.0) + 0.0 * f, R(0.0) * f);
+  if (g_orbit.n > 0) {
+    // unequal arms, each delay at the local frequency: arm 12 (c), 23 (a), 31 (b).  With the
+    // link phasors frozen at t, X1 = y13 + D_b y31 + D_b^2 y12 + D_b^2 D_c y21 - y12 - D_c y21
+    // - D_c^2 y13 - D_c^2 D_b y31 = (1 - D_c^2)(y13 + D_b y31) - (1 - D_b^2)(y12 + D_c y21);
+    // Y, Z cyclically; the second generation multiplies X by 1 - D_b^2 D_c^2 (X1(t) minus X1
+    // delayed by both arms twice), Y and Z likewise.
+    const Cx<R> Dc = expi(-(2.0 * kPi * f * dist(x[0], x[1]) / kC));
+    const Cx<R> Da = expi(-(2.0 * kPi * f * dist(x[1], x[2]) / kC));
+    const Cx<R> Db = expi(-(2.0 * kPi * f * dist(x[2], x[0]) / kC));
+    const Cx<R> ga = one - Da * Da, gb = one - Db * Db, gc = one - Dc * Dc;
+    Cx<R> X = gc * (z13 + Db * z31) - gb * (z12 + Dc * z21);
+    Cx<R> Y = ga * (z21 + Dc * z12) - gc * (z23 + Da * z32);
+    Cx<R> Z = gb * (z32 + Da * z23) - ga * (z31 + Db * z13);
+    if (p.tdi == 2) {
+      X = (one - (Db * Db) * (Dc * Dc)) * X;
+      Y = (one - (Dc * Dc) * (Da * Da)) * Y;
+      Z = (one - (Da * Da) * (Db * Db)) * Z;
+    }
+    ch[0] = scaled(Z - X, 1.0 / std::sqrt(2.0));
+    ch[1] = scaled((X - scaled(Y, 2.0)) + Z, 1.0 / std::sqrt(6.0));
+    ch[2] = scaled((X + Y) + Z, 1.0 / std::sqrt(3.0));
+    return;
+  }
+  const Cx<R> D = expi(-(2.0 * kPi * f * p.L / kC));  // one-arm delay at the local frequency
   const Cx<R> g = one - D * D;
   // X(t) = y13 + y31(t-L) + y12(t-2L) + y21(t-3L) - y12 - y21(t-L) - y13(t-2L) - y31(t-3L);
   // a delay by L multiplies the slowly varying link phasor by D; Y, Z by cyclic relabelling
@@ -390,6 +451,19 @@ extern "C" {
 
 // Threads the OpenMP loops over candidates would use for nthreads <= 0.
 int gbo_max_threads(void) { return threads(0); }
+
+// Numerical orbits for every later call: positions pos[n][3][3] (spacecraft, xyz; m) at
+// t_j = t0 + j dt (n >= 4, dt > 0); returns 0, or -1 on bad arguments.  gbo_clear_orbit()
+// returns to the analytic rigid triangle.  Not for use while other calls run.
+int gbo_set_orbit(const double* pos, int n, double t0, double dt) {
+  if (!pos || n < 4 || !(dt > 0.0)) return -1;
+  g_orbit.pos.assign(pos, pos + (size_t)n * 9);
+  g_orbit.n = n;
+  g_orbit.t0 = t0;
+  g_orbit.dt = dt;
+  return 0;
+}
+void gbo_clear_orbit(void) { g_orbit = OrbitGrid(); }
 
 // Spacecraft positions x[3][3] (m) at time t.
 void gbo_spacecraft(double t, double P_orb, double L, double AU, double* x_out) {

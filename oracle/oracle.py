@@ -49,6 +49,10 @@ def _load():
         lib.gbo_fisher.argtypes = [_dp, i64, i, i, i, _dp, d, d, d, d, i, _dp]
         lib.gbo_mh_chain.argtypes = [_dp, _dp, _dp, i64, d, _i32p]
         lib.gbo_mh_chain.restype = i64
+        lib.gbo_set_orbit.argtypes = [_dp, i, d, d]
+        lib.gbo_set_orbit.restype = i
+        lib.gbo_clear_orbit.argtypes = []
+        lib.gbo_clear_orbit.restype = None
         _lib = lib
     return _lib
 
@@ -77,6 +81,22 @@ def channels(f: float, L: float = I.ARM_L) -> int:
     """The channel rule of Sec. II: A and E below half the transfer frequency f*/2 = c / (4 pi L),
     A, E and T at and above it."""
     return 3 if f >= 299792458.0 / (4.0 * 3.141592653589793 * L) else 2
+
+
+def set_orbit(pos: np.ndarray, t0: float, dt: float):
+    """Numerical orbits for every later oracle call: positions pos [n, 3, 3] (spacecraft, xyz;
+    m) at t_j = t0 + j dt, interpolated by the cubic through four neighbouring nodes; every arm
+    then has its own length and the TDI one delay per arm.  clear_orbit() returns to the
+    analytic rigid triangle of Geometry."""
+    a = _f64(pos)
+    if a.ndim != 3 or a.shape[1:] != (3, 3):
+        raise ValueError("pos must be [n, 3, 3]")
+    if _load().gbo_set_orbit(_p(a), a.shape[0], float(t0), float(dt)) != 0:
+        raise ValueError("gbo_set_orbit: need n >= 4 and dt > 0")
+
+
+def clear_orbit():
+    _load().gbo_clear_orbit()
 
 
 def max_threads() -> int:

@@ -49,6 +49,45 @@ TABLE1_NAMES = ("f0", "fdot", "sin_beta", "lam", "log10_amp", "cos_iota", "psi",
 # ---------------------------------------------------------------------------------
 # noise model
 # ---------------------------------------------------------------------------------
+def keplerian_orbits(t, P_orb: float = YEAR, L: float = ARM_L, AU_: float = AU) -> np.ndarray:
+    """Spacecraft positions [3, len(t), 3] (m, ecliptic frame) on exact Keplerian ellipses: the
+    orbits whose first-order expansion in the eccentricity is the classic rigid-triangle
+    formula (shared mean longitude 2 pi t / P_orb, perihelion longitudes 2 pi i / 3,
+    e = L / (2 sqrt3 AU), each orbit plane tilted about the axis perpendicular to its apsides
+    by sin eps = sqrt3 e).  Kept to all orders, the arms breathe (about +-0.24% at the default
+    sizes) and the centroid leaves the ecliptic (about 9,000 km): an input for the unequal-arm
+    model, sampled on a grid by orbit_grid."""
+    t = np.asarray(t, dtype=np.float64)
+    lam = 2.0 * math.pi * t / P_orb
+    e = L / (2.0 * math.sqrt(3.0) * AU_)
+    eps = math.asin(math.sqrt(3.0) * e)
+    out = np.empty((3,) + t.shape + (3,))
+    for i in range(3):
+        w = 2.0 * math.pi * i / 3.0
+        M = lam - w
+        E = M.copy()
+        for _ in range(40):                      # Kepler's equation E - e sin E = M (Newton)
+            E = E - (E - e * np.sin(E) - M) / (1.0 - e * np.cos(E))
+        u = AU_ * (np.cos(E) - e)                # along the apsidal line
+        v = AU_ * math.sqrt(1.0 - e * e) * np.sin(E)
+        xp, zp = u * math.cos(eps), -u * math.sin(eps)
+        out[i, ..., 0] = xp * math.cos(w) - v * math.sin(w)
+        out[i, ..., 1] = xp * math.sin(w) + v * math.cos(w)
+        out[i, ..., 2] = zp
+    return out
+
+
+def orbit_grid(positions_fn, T: float, n: int = 4097) -> tuple:
+    """Positions on the uniform grid t_j = t0 + j dt, j < n, covering [-dt, T + dt] (so that the
+    four-point interpolation of the library and of the oracle has a centred stencil at both
+    ends): returns (pos [n, 3, 3] as spacecraft, xyz; t0; dt)."""
+    dt = T / (n - 3)
+    t0 = -dt
+    t = t0 + dt * np.arange(n, dtype=np.float64)
+    x = positions_fn(t)                          # [3, n, 3]
+    return np.ascontiguousarray(np.transpose(x, (1, 0, 2))), t0, dt
+
+
 def psd_single_link(f):
     """Acceleration and optical-metrology noise in fractional-frequency units.
 

@@ -150,6 +150,73 @@ def test_second_generation_matches_time_domain_tdi(oracle_lib, periodic_brutefor
     assert rel(h1[0, 0], ref[0]) > 1e-2
 
 
+@pytest.fixture
+def with_orbit(oracle_lib):
+    """Sets numerical orbits on the oracle for one test and always clears them afterwards."""
+    O = oracle_lib
+
+    def set_(pos, t0, dt):
+        O.set_orbit(pos, t0, dt)
+    yield set_
+    O.clear_orbit()
+
+
+@pytest.mark.parametrize("f_mhz,N,gen", [(3.0, 128, 1), (12.0, 256, 1), (12.0, 256, 2)])
+def test_unequal_arms_match_time_domain_tdi(oracle_lib, with_orbit, f_mhz, N, gen):
+    """Numerical orbits: the exact Keplerian orbits (arms breathing by +-0.24%, centroid off the
+    ecliptic) sampled on a grid.  In the periodic case (orbit period T, fdot = 0, integer f0 T)
+    the oracle's template with one delay per arm must equal the full FFT of the time-domain
+    Michelson combinations built link by link with each link's own light time and the delay
+    sums of the definition (G1 geometry, exact positions, no grid).  The rigid equal-arm model
+    misses the same reference by about 1e-3."""
+    from oracle import bruteforce as BF
+    O = oracle_lib
+    M, dt, T, q = _periodic_case(f_mhz)
+    th = np.array([q / T, 0.0, 0.3, 1.1, 1e-21, 0.7, 0.4, 1.3])
+    posf = lambda t: I.keplerian_orbits(t, T, I.ARM_L, I.AU)
+    X, _ = BF.spectrum_positions(th, M, dt, posf, generation=gen)
+    h_rigid, _ = O.waveform(th, N, 3, O.Geometry(T, P_orb=T, tdi=gen))
+    with_orbit(*I.orbit_grid(posf, T, 4097))
+    h, fb = O.waveform(th, N, 3, O.Geometry(T, P_orb=T, tdi=gen))
+    ref = X[:, int(fb[0]):int(fb[0]) + N]
+    for c in (0, 1):
+        assert rel(h[0, c], ref[c]) < 1e-9, (c, rel(h[0, c], ref[c]))
+    assert np.linalg.norm(h[0, 2] - ref[2]) / np.linalg.norm(ref[0]) < 1e-9
+    assert rel(h_rigid[0, 0], ref[0]) > 3e-4
+
+
+def test_orbit_grid_of_the_rigid_triangle_reproduces_it(oracle_lib, with_orbit):
+    """The analytic rigid triangle sampled on a grid and given as numerical orbits: the
+    unequal-arm path (per-link lengths, one delay per arm, interpolated positions) reproduces
+    the equal-arm template, for both TDI generations and a drifting source."""
+    O = oracle_lib
+    T = I.T1
+    g = O.Geometry(T)
+    posf = lambda t: np.transpose(np.array([O.spacecraft(float(x), g) for x in t]), (1, 0, 2))
+    th = np.array([5.3e-3, 2e-17, 0.4, 2.1, 2e-22, 1.0, 0.3, 2.2])
+    ref1, _ = O.waveform(th, 256, 3, g)
+    ref2, _ = O.waveform(th, 256, 3, O.Geometry(T, tdi=2))
+    with_orbit(*I.orbit_grid(posf, T, 8193))
+    h1, _ = O.waveform(th, 256, 3, g)
+    h2, _ = O.waveform(th, 256, 3, O.Geometry(T, tdi=2))
+    assert rel(h1[0], ref1[0]) < 1e-9
+    assert rel(h2[0], ref2[0]) < 1e-9
+
+
+def test_keplerian_orbits_breathe_and_expand_to_the_classic_formula():
+    """The Keplerian input orbits: arms within 0.3% of L and varying by more than 0.4% over a
+    year; their first-order expansion is the classic formula (differences of order e^2 AU)."""
+    from oracle import bruteforce as BF
+    t = np.linspace(0.0, I.YEAR, 4001)
+    x = I.keplerian_orbits(t)
+    e = I.ARM_L / (2.0 * np.sqrt(3.0) * I.AU)
+    for r, s_ in ((0, 1), (1, 2), (2, 0)):
+        L = np.linalg.norm(x[r] - x[s_], axis=-1) / I.ARM_L
+        assert np.all(np.abs(L - 1.0) < 3e-3) and L.max() - L.min() > 4e-3
+    dev = np.abs(x - BF.orbits(t, I.YEAR, I.ARM_L, I.AU)).max()
+    assert dev < 5.0 * e * e * I.AU
+
+
 def test_parseval_normalisation(oracle_lib, periodic_bruteforce):
     """With a flat PSD S0, <h|h> = 4/(T S0) sum_k |h_k|^2 = (2/S0) dt sum_n x_n^2."""
     O = oracle_lib
