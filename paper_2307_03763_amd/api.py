@@ -21,7 +21,7 @@ GB_OK, GB_EINVAL, GB_EHIP, GB_ENOMEM, GB_EUNSUPPORTED = 0, -1, -2, -3, -4
 GB_FP64, GB_MIXED, GB_PER_WINDOW = 0, 1, 2
 PRECISION = {"fp64": GB_FP64, "mixed": GB_MIXED, "per_window": GB_PER_WINDOW}
 
-EXPORTS = ("gb_create", "gb_destroy", "gb_last_error", "gb_waveform", "gb_channels", "gb_plan_create",
+EXPORTS = ("gb_create", "gb_destroy", "gb_last_error", "gb_waveform", "gb_channels", "gb_set_orbit", "gb_plan_create",
            "gb_plan_destroy", "gb_plan_info", "gb_window_prepare", "gb_loglik", "gb_loglik_grad", "gb_mh_step",
            "gb_autotune", "gb_autotune_windows", "gb_select_variant", "gb_fisher", "gb_kde_logpdf", "gb_add_templates",
            "gb_noise_estimate", "gb_noise_estimate_noalloc", "gb_noise_global", "gb_de_trial", "gb_de_select")
@@ -74,6 +74,8 @@ def lib():
         L.gb_waveform.restype = st
         L.gb_channels.argtypes = [_vp, i64, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
         L.gb_channels.restype = st
+        L.gb_set_orbit.argtypes = [_vp, _vp, ctypes.c_int32, d, d]
+        L.gb_set_orbit.restype = st
         L.gb_plan_create.argtypes = [_vp, ctypes.POINTER(gb_window), i, i, ctypes.POINTER(_vp)]
         L.gb_plan_create.restype = st
         L.gb_plan_destroy.argtypes = [_vp]
@@ -181,6 +183,18 @@ def gb_channels(ctx: int, k0: int, W: int) -> int:
     C = ctypes.c_int32()
     _check(lib().gb_channels(ctx, int(k0), int(W), ctypes.byref(C)), "gb_channels")
     return C.value
+
+
+def gb_set_orbit(ctx: int, pos=None, t0: float = 0.0, dt: float = 0.0):
+    """Numerical orbits for the context: positions pos [n, 3, 3] (spacecraft, xyz; m) at
+    t_j = t0 + j dt (see include/gbx.h); pos None returns to the analytic orbits."""
+    if pos is None:
+        _check(lib().gb_set_orbit(ctx, None, 0, 0.0, 0.0), "gb_set_orbit")
+        return
+    a = np.ascontiguousarray(pos, dtype=np.float64)
+    if a.ndim != 3 or a.shape[1:] != (3, 3):
+        raise ValueError("pos must be [n, 3, 3]")
+    _check(lib().gb_set_orbit(ctx, a.ctypes.data, a.shape[0], float(t0), float(dt)), "gb_set_orbit")
 
 
 def gb_plan_create(ctx: int, table, precision: int) -> int:
@@ -536,6 +550,10 @@ class Context:
         self.T = float(T)
         self.tdi = int(tdi)
         self.handle = gb_create(T, orbit_period, arm_length, au, tdi)
+
+    def set_orbit(self, pos=None, t0: float = 0.0, dt: float = 0.0):
+        """Numerical orbits (gb_set_orbit); no arguments: back to the analytic orbits."""
+        gb_set_orbit(self.handle, pos, t0, dt)
 
     def waveform(self, theta: torch.Tensor, N: int, C: int, precision: int = GB_FP64, stream=None):
         return gb_waveform(self.handle, theta, N, C, precision, stream)

@@ -74,6 +74,58 @@ __global__ void k_orbit_table(double* ob64, float* ob32, int N, double T, double
     v[OB_P2 + k] = dx[1][k] / kC;
     v[OB_P3 + k] = dx[2][k] / kC;
   }
+  v[OB_RZ] = 0.0;
+  v[OB_LT12] = v[OB_LT23] = v[OB_LT31] = L / kC;
+  for (int f = 0; f < OB_FIELDS; ++f) {
+    ob64[f * N + m] = v[f];
+    ob32[f * N + m] = (float)v[f];
+  }
+}
+
+// The same table from numerical orbits: spacecraft positions pos[n][3][3] (m) on the grid
+// t_j = t0 + j dt, interpolated at t_m = T m / N by the cubic through four neighbouring nodes
+// (Lagrange form, nodes j-1 .. j+2 around t, moved inwards at the ends of the grid).  The
+// guiding centre is the centroid; every arm gets its own unit vector and light time.
+__global__ void k_orbit_table_grid(double* ob64, float* ob32, int N, double T, const double* __restrict__ pos,
+                                   int n, double t0, double dt) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= N) return;
+  const double u = (T * (double)m / (double)N - t0) / dt;
+  int j = (int)floor(u) - 1;
+  j = j < 0 ? 0 : (j > n - 4 ? n - 4 : j);
+  const double s = u - (double)j;
+  const double w[4] = {-(s - 1.0) * (s - 2.0) * (s - 3.0) / 6.0, s * (s - 2.0) * (s - 3.0) / 2.0,
+                       -s * (s - 1.0) * (s - 3.0) / 2.0, s * (s - 1.0) * (s - 2.0) / 6.0};
+  double x[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int k = 0; k < 3; ++k) {
+      double acc = 0.0;
+      for (int q = 0; q < 4; ++q) acc += w[q] * pos[((size_t)(j + q) * 3 + i) * 3 + k];
+      x[i][k] = acc;
+    }
+  double v[OB_FIELDS];
+  double cen[3];
+  for (int k = 0; k < 3; ++k) cen[k] = (x[0][k] + x[1][k] + x[2][k]) / 3.0;
+  v[OB_RX] = cen[0] / kC;
+  v[OB_RY] = cen[1] / kC;
+  v[OB_RZ] = cen[2] / kC;
+  const int r[3] = {0, 1, 2}, q[3] = {1, 2, 0};  // arms 12, 23, 31: (x_r - x_q) / |.|
+  const int nf[3] = {OB_N12, OB_N23, OB_N31}, lf[3] = {OB_LT12, OB_LT23, OB_LT31};
+  for (int a = 0; a < 3; ++a) {
+    double d[3], l2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      d[k] = x[r[a]][k] - x[q[a]][k];
+      l2 += d[k] * d[k];
+    }
+    const double l = sqrt(l2);
+    for (int k = 0; k < 3; ++k) v[nf[a] + k] = d[k] / l;
+    v[lf[a]] = l / kC;
+  }
+  for (int k = 0; k < 3; ++k) {
+    v[OB_P1 + k] = (x[0][k] - cen[k]) / kC;
+    v[OB_P2 + k] = (x[1][k] - cen[k]) / kC;
+    v[OB_P3 + k] = (x[2][k] - cen[k]) / kC;
+  }
   for (int f = 0; f < OB_FIELDS; ++f) {
     ob64[f * N + m] = v[f];
     ob32[f * N + m] = (float)v[f];
@@ -163,10 +215,11 @@ struct gb_ctx {
   int n_cu = 256;
   NTab tab[5];
   const Variant* choice[2][5][2][3] = {};  // autotuned variant per precision, N, C, mode
+  int uneq = 0;                              // numerical orbits set (gb_set_orbit)
 };
 
 static const Variant* pick_variant(const gb_ctx* c, int prec, int N, int C, int mode) {
-  const Variant* v = c ? c->choice[prec][n_index(N)][C - 2][mode] : nullptr;
+  const Variant* v = (c && mode <= MODE_GRAD) ? c->choice[prec][n_index(N)][C - 2][mode] : nullptr;
   return v ? v : find_variant(prec, N, C, mode);
 }
 
@@ -247,7 +300,7 @@ extern "C" gb_status gb_waveform(gb_ctx* c, const double* theta, int64_t B, int 
   if (prec != GB_FP64 && prec != GB_MIXED) return fail(GB_EINVAL, "gb_waveform: bad precision %d", (int)prec);
   if (B == 0) return GB_OK;
   if (!theta || !h_out || !first_bin) return fail(GB_EINVAL, "gb_waveform: null array");
-  const Variant* v = pick_variant(c, prec, N, C, MODE_WAVEFORM);
+  const Variant* v = pick_variant(c, prec, N, C, c->uneq ? MODE_WAVEFORM_UNEQ : MODE_WAVEFORM);
   if (!v) return fail(GB_EUNSUPPORTED, "gb_waveform: no variant for N=%d C=%d", N, C);
   BatchArgs a = base_args(c, N, prec);
   a.theta = theta;
@@ -267,6 +320,55 @@ static int paper_channels(const gb_ctx* c, int64_t k0, int32_t W) {
   return f >= kC / (4.0 * kPi * c->cfg.arm_length) ? 3 : 2;
 }
 
+extern "C" gb_status gb_set_orbit(gb_ctx* c, const double* pos, int32_t n_pts, double t0, double dt) {
+  if (!c) return fail(GB_EINVAL, "gb_set_orbit: null context");
+  const double T = c->cfg.T;
+  if (!pos && n_pts == 0) {  // back to the analytic orbits
+    for (int i = 0; i < 5; ++i) {
+      const int N = 64 << i;
+      hipLaunchKernelGGL(k_orbit_table, dim3((N + 63) / 64), dim3(64), 0, 0, c->tab[i].ob64, c->tab[i].ob32, N, T,
+                         c->cfg.orbit_period, c->cfg.arm_length, c->cfg.au);
+      HIPCHK(hipGetLastError());
+    }
+    HIPCHK(hipDeviceSynchronize());
+    c->uneq = 0;
+    return GB_OK;
+  }
+  if (!pos) return fail(GB_EINVAL, "gb_set_orbit: null positions with n_pts = %d", n_pts);
+  if (n_pts < 4 || n_pts > (1 << 24)) return fail(GB_EINVAL, "gb_set_orbit: n_pts = %d outside [4, 2^24]", n_pts);
+  if (!std::isfinite(t0) || !std::isfinite(dt) || !(dt > 0.0))
+    return fail(GB_EINVAL, "gb_set_orbit: t0 and dt must be finite, dt > 0");
+  if (t0 > 0.0 || t0 + (double)(n_pts - 1) * dt < T)
+    return fail(GB_EINVAL, "gb_set_orbit: the grid [%g, %g] s does not cover the observation [0, %g] s", t0,
+                t0 + (double)(n_pts - 1) * dt, T);
+  for (int64_t j = 0; j < n_pts; ++j) {
+    const double* x = pos + 9 * j;
+    for (int k = 0; k < 9; ++k)
+      if (!std::isfinite(x[k])) return fail(GB_EINVAL, "gb_set_orbit: position %lld is not finite", (long long)j);
+    for (int a = 0; a < 3; ++a) {
+      const double* p0 = x + 3 * a;
+      const double* p1 = x + 3 * ((a + 1) % 3);
+      const double l = std::sqrt((p0[0] - p1[0]) * (p0[0] - p1[0]) + (p0[1] - p1[1]) * (p0[1] - p1[1]) +
+                                 (p0[2] - p1[2]) * (p0[2] - p1[2]));
+      if (!(l > 0.0)) return fail(GB_EINVAL, "gb_set_orbit: two spacecraft coincide at node %lld", (long long)j);
+    }
+  }
+  double* d_pos = nullptr;
+  hipError_t e = hipMalloc(&d_pos, sizeof(double) * 9 * (size_t)n_pts);
+  if (e == hipSuccess) e = hipMemcpy(d_pos, pos, sizeof(double) * 9 * (size_t)n_pts, hipMemcpyHostToDevice);
+  for (int i = 0; i < 5 && e == hipSuccess; ++i) {
+    const int N = 64 << i;
+    hipLaunchKernelGGL(k_orbit_table_grid, dim3((N + 63) / 64), dim3(64), 0, 0, c->tab[i].ob64, c->tab[i].ob32, N, T,
+                       d_pos, (int)n_pts, t0, dt);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  (void)hipFree(d_pos);
+  if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? GB_ENOMEM : GB_EHIP, "gb_set_orbit: %s", hipGetErrorString(e));
+  c->uneq = 1;
+  return GB_OK;
+}
+
 extern "C" gb_status gb_channels(const gb_ctx* c, int64_t k0, int32_t W, int32_t* C) {
   if (!c || !C) return fail(GB_EINVAL, "gb_channels: null argument");
   if (W < 1) return fail(GB_EINVAL, "gb_channels: W = %d < 1", W);
@@ -278,8 +380,8 @@ extern "C" gb_status gb_channels(const gb_ctx* c, int64_t k0, int32_t W, int32_t
 namespace {
 struct Bucket {
   int prec, N, C;
-  const Variant* v[3];  // per mode
-  int grid[3];
+  const Variant* v[4];  // per mode: waveform (unused), logL, gradient, logL on numerical orbits
+  int grid[4];
   Tile* d_tiles = nullptr;
   int n_tiles = 0;
   unsigned* d_ctr = nullptr;  // [2]
@@ -369,7 +471,7 @@ extern "C" gb_status gb_plan_create(gb_ctx* c, const gb_window* windows, int n_w
     b.prec = w0.prec;
     b.N = w0.N;
     b.C = w0.C;
-    for (int m = 0; m < 3; ++m) {
+    for (int m = 0; m < 4; ++m) {
       b.v[m] = pick_variant(c, b.prec, b.N, b.C, m);
       b.grid[m] = 0;
     }
@@ -377,8 +479,9 @@ extern "C" gb_status gb_plan_create(gb_ctx* c, const gb_window* windows, int n_w
       gb_plan_destroy(p);
       return fail(GB_EUNSUPPORTED, "no kernel variant for N=%d C=%d", b.N, b.C);
     }
-    // tiles hold a whole number of workgroup passes of every mode's kernel (the counts are powers
-    // of two, so the largest is a multiple of the others)
+    // tiles hold a whole number of workgroup passes of the tuned likelihood and gradient kernels
+    // (the counts are powers of two, so the larger is a multiple of the other); the kernel of
+    // numerical orbits takes the same tiles in passes of its own width
     int cpb = 0;
     for (int m = 1; m < 3; ++m)
       if (b.v[m]) cpb = std::max(cpb, b.v[m]->WPB * 64 / b.v[m]->LPC);
@@ -395,7 +498,7 @@ extern "C" gb_status gb_plan_create(gb_ctx* c, const gb_window* windows, int n_w
       }
     }
     b.n_tiles = (int)tiles.size();
-    for (int m = 1; m < 3; ++m) {
+    for (int m = 1; m < 4; ++m) {
       if (!b.v[m]) continue;
       int nb = 0;
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, b.v[m]->fn, b.v[m]->WPB * 64, lds_bytes(*b.v[m]));
@@ -483,6 +586,12 @@ static gb_status run_batch(gb_plan* p, int mode, const double* d, const double* 
   if (d != p->prep_d || w != p->prep_w)
     return fail(GB_EINVAL, "%s: data/weights differ from the ones passed to gb_window_prepare", who);
   if (mode == MODE_GRAD && !grad) return fail(GB_EINVAL, "%s: null gradient array", who);
+  if (mode == MODE_GRAD && p->ctx->uneq)
+    return fail(GB_EUNSUPPORTED, "%s: no gradient on numerical orbits (gb_set_orbit); likelihoods and templates only",
+                who);
+  // numerical orbits take the likelihood kernels of one light time per arm, chosen at launch so
+  // that plans built before gb_set_orbit follow it
+  if (mode == MODE_LOGLIK && p->ctx->uneq) mode = MODE_LOGLIK_UNEQ;
   // every bucket must have a kernel before any is launched, so a refused call writes nothing
   for (const Bucket& b : p->buckets) {
     if (b.n_tiles == 0 || b.v[mode]) continue;

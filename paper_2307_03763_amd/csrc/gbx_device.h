@@ -31,9 +31,11 @@ constexpr double kC = 299792458.0;
 // orbit table fields, each an array of N samples (structure of arrays)
 enum {
   OB_RX = 0, OB_RY = 1,                          // guiding centre / c (s), FP64 only
-  OB_N12 = 2, OB_N23 = 5, OB_N31 = 8,            // unit arm vectors (x1-x2)/L, (x2-x3)/L, (x3-x1)/L
+  OB_N12 = 2, OB_N23 = 5, OB_N31 = 8,            // unit arm vectors (x1-x2)/|.|, (x2-x3)/|.|, (x3-x1)/|.|
   OB_P1 = 11, OB_P2 = 14, OB_P3 = 17,            // spacecraft offsets from the guiding centre / c (s)
-  OB_FIELDS = 20
+  OB_RZ = 20,                                    // guiding centre z / c (s), FP64; 0 for the analytic orbits
+  OB_LT12 = 21, OB_LT23 = 22, OB_LT31 = 23,      // arm light times |x_r - x_s| / c (s)
+  OB_FIELDS = 24
 };
 
 // Normalisation of channel c: A = (Z - X)/sqrt2, E = (X - 2Y + Z)/sqrt6, T = (X + Y + Z)/sqrt3
@@ -255,7 +257,7 @@ __device__ __forceinline__ R sinc_sel(R u) {
 template <class R>
 struct Cand {
   double f0, fd, df, phi0c;   // f0, fdot, f0 - q/T, phi0 / 2 pi
-  double kxd, kyd;            // k_x, k_y in FP64 for k.R (the only large phase term)
+  double kxd, kyd, kzd;       // k in FP64 for k.R (the only large phase term)
   int64_t q;                  // carrier bin floor(f0 T)
   R k[3], u[3], v[3];         // propagation direction and transverse basis
   cplx<R> ap, ax;             // n.H.n = ap F+ + ax Fx for unit amplitude
@@ -289,6 +291,7 @@ __device__ __forceinline__ Cand<R> make_cand(const double* th, double T) {
   (void)si;
   s.kxd = -cb * cl;
   s.kyd = -cb * sl;
+  s.kzd = -sb;
   s.k[0] = (R)(-cb * cl);
   s.k[1] = (R)(-cb * sl);
   s.k[2] = (R)(-sb);
@@ -421,6 +424,96 @@ __device__ __forceinline__ void slow_sample(const Cand<R>& s, const double* __re
   // frequency either)
   if (TDI2) K = K * mul_mi(scal(mk<R>(cD * cD - sD * sD, (R)2 * cD * sD), (R)4 * sD * cD));
   // the channels without their normalisations (chan_norm)
+  out[0] = K * (Z - X);
+  out[1] = K * (X - scal(Y, (R)2) + Z);
+  if (C == 3) out[C - 1] = K * (X + Y + Z);
+}
+
+// 1 - w^2 for a unit phasor w = e^{-i theta}: 2i sin(theta) w with sin(theta) = -Im w (no
+// cancellation when theta is small).
+template <class R>
+__device__ __forceinline__ cplx<R> one_minus_sq(cplx<R> w) { return mul_i(scal(w, (R)-2 * w.y)); }
+
+// One sample of the slow series with one light time per arm (numerical orbits): the table's arm
+// light times LT_a at the sample, all three arm vectors and the guiding centre's z.  For arm a
+// (12, 23, 31 = index 0, 1, 2), x_a = pi f LT_a and E_a = e^{-i x_a}: its two links carry the
+// amplitude x_a sinc(x_a (1 -+ k.n_a)) and the phase E_a (half the arm's travel time), and its
+// delay is D_a = E_a^2.  With Dc = arm 12, Da = arm 23, Db = arm 31 (the link phasors frozen at
+// the sample time)
+//   X = (1 - Dc^2)(y13 + Db y31) - (1 - Db^2)(y12 + Dc y21),   Y, Z cyclically,
+// and the second generation multiplies X by 1 - Db^2 Dc^2 (Y, Z likewise).  With equal arms
+// this is slow_sample's form.  General sinc and sin/cos throughout (no short series).
+template <class R, int C, bool TDI2>
+__device__ __forceinline__ void slow_sample_uneq(const Cand<R>& s, const double* __restrict__ ob64,
+                                                 const R* __restrict__ obR, int N, int m, double t,
+                                                 cplx<R> out[C]) {
+  constexpr bool BUF = sizeof(R) == 8;  // orbit reads through a buffer resource (ob_at)
+  const double f = s.f0 + s.fd * t;
+  const double kR = s.kxd * ob_at<BUF>(ob64, OB_RX, N, m) + s.kyd * ob_at<BUF>(ob64, OB_RY, N, m) +
+                    s.kzd * ob_at<BUF>(ob64, OB_RZ, N, m);
+  double p = s.df * t + 0.5 * s.fd * t * t + s.phi0c - f * kR;
+  p -= rint(p);
+  R sp, cp;
+  sincos_rev((R)p, &sp, &cp);
+  const R fr = (R)f;
+  R kn[3], un[3], vn[3], Fp[3], Fx[3], xa[3];
+  cplx<R> E[3], D[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int o = OB_N12 + 3 * a;
+    const R n0 = ob_at<BUF>(obR, o + 0, N, m), n1 = ob_at<BUF>(obR, o + 1, N, m), n2 = ob_at<BUF>(obR, o + 2, N, m);
+    kn[a] = s.k[0] * n0 + s.k[1] * n1 + s.k[2] * n2;
+    un[a] = s.u[0] * n0 + s.u[1] * n1 + s.u[2] * n2;
+    vn[a] = s.v[0] * n0 + s.v[1] * n1;
+    Fp[a] = un[a] * un[a] - vn[a] * vn[a];
+    Fx[a] = (R)2 * un[a] * vn[a];
+    const R lt = ob_at<BUF>(obR, OB_LT12 + a, N, m);
+    xa[a] = fr * (R)kPi * lt;
+    R se, ce;
+    sincos_rev((R)-0.5 * fr * lt, &se, &ce);  // E_a = e^{-i pi f LT_a}
+    E[a] = mk<R>(ce, se);
+    D[a] = E[a] * E[a];
+  }
+  R kp[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int o = OB_P1 + 3 * i;
+    kp[i] = s.k[0] * ob_at<BUF>(obR, o + 0, N, m) + s.k[1] * ob_at<BUF>(obR, o + 1, N, m) +
+            s.k[2] * ob_at<BUF>(obR, o + 2, N, m);
+  }
+  // e^{i pi f k.dx_i / c} per spacecraft (the offsets from the centroid sum to zero)
+  cplx<R> ph[3];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    R sc, cc;
+    sincos_rev((R)0.5 * fr * kp[i], &sc, &cc);
+    ph[i] = mk<R>(cc, sc);
+  }
+  ph[2] = conjg(ph[0] * ph[1]);
+  const int opp[3] = {2, 0, 1};  // arm 12 -> spacecraft 3, arm 23 -> 1, arm 31 -> 2
+  cplx<R> P[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const cplx<R> b = mk<R>(s.ap.x * Fp[a] + s.ax.x * Fx[a], s.ap.y * Fp[a] + s.ax.y * Fx[a]);
+    P[a] = (b * ph[opp[a]]) * E[a];
+  }
+  // links: the "1 - k.n" link and the "1 + k.n" link of each arm
+  const cplx<R> y12 = scal(P[0], xa[0] * sinc_r(xa[0] * ((R)1 - kn[0])));
+  const cplx<R> y21 = scal(P[0], xa[0] * sinc_r(xa[0] * ((R)1 + kn[0])));
+  const cplx<R> y23 = scal(P[1], xa[1] * sinc_r(xa[1] * ((R)1 - kn[1])));
+  const cplx<R> y32 = scal(P[1], xa[1] * sinc_r(xa[1] * ((R)1 + kn[1])));
+  const cplx<R> y31 = scal(P[2], xa[2] * sinc_r(xa[2] * ((R)1 - kn[2])));
+  const cplx<R> y13 = scal(P[2], xa[2] * sinc_r(xa[2] * ((R)1 + kn[2])));
+  const cplx<R> gc = one_minus_sq(D[0]), ga = one_minus_sq(D[1]), gb = one_minus_sq(D[2]);
+  cplx<R> X = gc * (y13 + D[2] * y31) - gb * (y12 + D[0] * y21);
+  cplx<R> Y = ga * (y21 + D[0] * y12) - gc * (y23 + D[1] * y32);
+  cplx<R> Z = gb * (y32 + D[1] * y23) - ga * (y31 + D[2] * y13);
+  if (TDI2) {
+    X = one_minus_sq(D[2] * D[0]) * X;
+    Y = one_minus_sq(D[0] * D[1]) * Y;
+    Z = one_minus_sq(D[1] * D[2]) * Z;
+  }
+  const cplx<R> K = mul_mi(mk<R>(cp, sp));  // -i e^{2 pi i p}
   out[0] = K * (Z - X);
   out[1] = K * (X - scal(Y, (R)2) + Z);
   if (C == 3) out[C - 1] = K * (X + Y + Z);

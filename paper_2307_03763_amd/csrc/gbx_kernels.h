@@ -7,7 +7,9 @@
 
 namespace gbx {
 
-enum { MODE_WAVEFORM = 0, MODE_LOGLIK = 1, MODE_GRAD = 2 };
+// kernel modes; the last two are the likelihood and the templates of numerical orbits (one light
+// time per arm), kernels of their own so that the tuned equal-arm kernels keep their registers
+enum { MODE_WAVEFORM = 0, MODE_LOGLIK = 1, MODE_GRAD = 2, MODE_LOGLIK_UNEQ = 3, MODE_WAVEFORM_UNEQ = 4 };
 
 // Window descriptor as the kernels see it (device memory of a plan).
 struct DevWin {
@@ -99,8 +101,9 @@ __device__ __forceinline__ void with_loop_flags(bool tdi2, bool shrt, F&& body) 
 
 // The slow-series samples of one lane, one at a time (keeps the live state of a single sample
 // in registers); TDI2 and SHORT are compile-time choices (with_loop_flags), so that the
-// branches on them are taken once per template, outside the loop.
-template <class R, int N, int LPC, int C, bool TDI2, bool SHORT>
+// branches on them are taken once per template, outside the loop; UNEQ (numerical orbits) is
+// the kernel's own.
+template <class R, int N, int LPC, int C, bool TDI2, bool SHORT, bool UNEQ>
 __device__ __forceinline__ void series_samples(const Cand<R>& s, const BatchArgs& a, int lane, cplx<R>* buf) {
   constexpr int E = N / LPC;
   const R* obR = (const R*)a.obR;
@@ -109,29 +112,39 @@ __device__ __forceinline__ void series_samples(const Cand<R>& s, const BatchArgs
     const int m = lane + LPC * e;
     const double t = a.T * (double)m / (double)N;
     cplx<R> o[C];
-    slow_sample<R, C, TDI2, SHORT>(s, a.ob64, obR, N, m, t, a.Lc, o);
+    if constexpr (UNEQ)
+      slow_sample_uneq<R, C, TDI2>(s, a.ob64, obR, N, m, t, o);
+    else
+      slow_sample<R, C, TDI2, SHORT>(s, a.ob64, obR, N, m, t, a.Lc, o);
 #pragma unroll
     for (int c = 0; c < C; ++c) buf[c * N + m] = o[c];
   }
 }
 
-// Slow series of one template into LDS (all its lanes), then the forward DFT.
-template <class R, int N, int LPC, int C>
+// Slow series of one template into LDS (all its lanes), then the forward DFT.  UNEQ: one light
+// time per arm (slow_sample_uneq, general sinc).
+template <class R, int N, int LPC, int C, bool UNEQ = false>
 __device__ __forceinline__ void template_to_lds(const Cand<R>& s, const BatchArgs& a, int lane, cplx<R>* buf) {
-  with_loop_flags(a.tdi2 != 0, wave_sinc_short<R>(s, a), [&](auto tdi2, auto shrt) {
-    series_samples<R, N, LPC, C, decltype(tdi2)::value, decltype(shrt)::value>(s, a, lane, buf);
-  });
+  if constexpr (UNEQ) {
+    with_loop_flags(a.tdi2 != 0, false, [&](auto tdi2, auto) {
+      series_samples<R, N, LPC, C, decltype(tdi2)::value, false, true>(s, a, lane, buf);
+    });
+  } else {
+    with_loop_flags(a.tdi2 != 0, wave_sinc_short<R>(s, a), [&](auto tdi2, auto shrt) {
+      series_samples<R, N, LPC, C, decltype(tdi2)::value, decltype(shrt)::value, false>(s, a, lane, buf);
+    });
+  }
   slot_sync<LPC>();
   fft_lds<R, N, LPC, C, -1>(buf, lane, (const cplx<R>*)a.tw);
 }
 
 // logL and components of one template against one window.
-template <class R, int N, int LPC, int C, int WPB>
+template <class R, int N, int LPC, int C, int WPB, bool UNEQ>
 __device__ __forceinline__ void process_loglik(const BatchArgs& a, const DevWin& w, int64_t row, bool active,
                                                int lane, cplx<R>* buf, double (*s_red)[16]) {
   constexpr int E = N / LPC;
   const Cand<R> s = make_cand<R>(a.theta + 8 * row, a.T);
-  template_to_lds<R, N, LPC, C>(s, a, lane, buf);
+  template_to_lds<R, N, LPC, C, UNEQ>(s, a, lane, buf);
   const double scale = s.amp * a.T / (2.0 * (double)N);
   double acc[4] = {0.0, 0.0, 0.0, 0.0};  // sum w|d-h|^2, sum w|d|^2, <d|h>, <h|h> over the overlap
   const int64_t off = w.data_off;
@@ -285,7 +298,8 @@ __global__ void __launch_bounds__(WPB * 64, OCC) k_batch(BatchArgs a) {
       const int ci = c0 + slot;
       const bool active = ci < tl.n;
       const int64_t row = w.cand_off + tl.c0 + (active ? ci : 0);
-      if (MODE == MODE_LOGLIK) process_loglik<R, N, LPC, C, WPB>(a, w, row, active, lane, buf, s_red);
+      if (MODE == MODE_LOGLIK || MODE == MODE_LOGLIK_UNEQ)
+        process_loglik<R, N, LPC, C, WPB, MODE == MODE_LOGLIK_UNEQ>(a, w, row, active, lane, buf, s_red);
       if (MODE == MODE_GRAD) process_grad<R, N, LPC, C, WPB>(a, w, row, active, lane, buf, s_red);
     }
   }
@@ -299,8 +313,8 @@ __global__ void __launch_bounds__(WPB * 64, OCC) k_batch(BatchArgs a) {
   }
 }
 
-// Templates on their own bins: one workgroup per CPB templates.
-template <class R, int N, int LPC, int C, int WPB>
+// Templates on their own bins: one workgroup per CPB templates.  UNEQ: numerical orbits.
+template <class R, int N, int LPC, int C, int WPB, bool UNEQ = false>
 __global__ void __launch_bounds__(WPB * 64) k_waveform(BatchArgs a) {
   constexpr int CPB = WPB * 64 / LPC;
   constexpr int E = N / LPC;
@@ -312,7 +326,7 @@ __global__ void __launch_bounds__(WPB * 64) k_waveform(BatchArgs a) {
   const bool active = row0 < a.B;
   const int64_t row = active ? row0 : 0;
   const Cand<R> s = make_cand<R>(a.theta + 8 * row, a.T);
-  template_to_lds<R, N, LPC, C>(s, a, lane, buf);
+  template_to_lds<R, N, LPC, C, UNEQ>(s, a, lane, buf);
   if (!active) return;
   const double scale = s.amp * a.T / (2.0 * (double)N);
   const double nan = __builtin_nan("");

@@ -19,6 +19,12 @@ using namespace gbx;
   Variant { GB_FP64, NN, 128, CC, 2, MODE_LOGLIK, OO, reinterpret_cast<const void*>(&k_batch<double, NN, 128, CC, 2, MODE_LOGLIK, OO>) }
 #define VW(OO) V2(512, 2, OO), V2(512, 3, OO), V2(1024, 2, OO), V2(1024, 3, OO)
 
-static const Variant kTable[] = {VN(2), VN(1), VN(3), VW(2), VW(1), VW(3)};
+// numerical orbits (one light time per arm): one launch shape per (N, C), not tuned
+#define VU(NN, LL, CC) \
+  Variant { GB_FP64, NN, LL, CC, 4, MODE_LOGLIK_UNEQ, 2, reinterpret_cast<const void*>(&k_batch<double, NN, LL, CC, 4, MODE_LOGLIK_UNEQ, 2>) }
+#define VUC(NN, LL) VU(NN, LL, 2), VU(NN, LL, 3)
+
+static const Variant kTable[] = {VN(2), VN(1), VN(3), VW(2), VW(1), VW(3),
+                                 VUC(64, 16), VUC(128, 32), VUC(256, 64), VUC(512, 128), VUC(1024, 256)};
 
 extern "C" VariantList gbx_variants_f64_loglik() { return VariantList{kTable, (int)(sizeof kTable / sizeof kTable[0])}; }

@@ -1,0 +1,124 @@
+"""Numerical orbits (gb_set_orbit) on the GPU against the oracle given the same positions.
+
+The exact Keplerian orbits (arms breathing by +-0.24%, centroid off the ecliptic) are sampled
+on a grid; the library and the oracle each interpolate them with their own code.  Templates
+and likelihoods take one light time per arm.
+
+* FP64 templates within 1e-10 (relative L2) of the oracle's, both TDI generations, every N.
+* FP64 logL within the FP64 bound, mixed logL differences within the mixed model, on windows
+  of both channel counts.
+* The gradient is refused on such a context (GB_EUNSUPPORTED), before any launch.
+* Returning to the analytic orbits restores the equal-arm templates.
+"""
+
+import numpy as np
+import pytest
+
+from paper_2307_03763_amd import api
+from paper_2307_03763_amd import inputs as I
+from tests.gpu_common import banner, delta_logl_error, dev, loglik_tolerance, window_dd
+from tests.test_gpu_parity import MIXED_SLOPE
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture
+def kepler(oracle_lib):
+    """Keplerian positions on a grid over T1, set on the oracle; cleared afterwards."""
+    T = I.T1
+    pos, t0, dt = I.orbit_grid(lambda t: I.keplerian_orbits(t), T, 2049)
+    oracle_lib.set_orbit(pos, t0, dt)
+    yield pos, t0, dt
+    oracle_lib.clear_orbit()
+
+
+@pytest.mark.parametrize("tdi", [1, 2])
+def test_templates_on_numerical_orbits(oracle_lib, kepler, tdi):
+    O = oracle_lib
+    pos, t0, dt = kepler
+    banner(f"numerical orbits: FP64 templates, TDI {tdi}")
+    ctx = api.context_for(I.T1, tdi=tdi)
+    ctx.set_orbit(pos, t0, dt)
+    rng = np.random.default_rng(70 + tdi)
+    g = O.Geometry(I.T1, tdi=tdi)
+    worst = 0.0
+    for N, C, f0 in ((64, 2, 0.8e-3), (128, 2, 3e-3), (256, 3, 11e-3), (512, 3, 18e-3), (1024, 3, 27e-3)):
+        th = I.make_theta([f0 * (1 + 0.01 * k) for k in range(3)], I.fdot_gr(f0, 0.6), 1e-22,
+                          I.random_angles(rng, 3))
+        h, fb = ctx.waveform(dev(th), N, C, api.GB_FP64)
+        ho, fbo = O.waveform(th, N, C, g)
+        assert np.array_equal(fb.cpu().numpy(), fbo)
+        h = h.cpu().numpy()
+        for b in range(3):
+            e = _rel(h[b], ho[b])
+            worst = max(worst, e)
+            assert e < 1e-10, (N, C, b, e)
+    banner(f"  worst relative L2 {worst:.2e}")
+    # back to the analytic orbits: the equal-arm templates again
+    ctx.set_orbit()
+    O.clear_orbit()
+    th = I.make_theta([3e-3], 0.0, 1e-22, I.random_angles(rng, 1))
+    h, _ = ctx.waveform(dev(th), 128, 2, api.GB_FP64)
+    ho, _ = O.waveform(th, 128, 2, g)
+    assert _rel(h.cpu().numpy()[0], ho[0]) < 1e-10
+    ctx.close()
+
+
+def test_likelihoods_on_numerical_orbits(oracle_lib, kepler):
+    O = oracle_lib
+    pos, t0, dt = kepler
+    banner("numerical orbits: FP64 and mixed logL, gradient refused")
+    ctx = api.context_for(I.T1)
+    ctx.set_orbit(pos, t0, dt)
+    wl = I.workload_c3(O.template_fn(), n_win=12, n_cand=40)   # injections from the oracle on these orbits
+    g = O.Geometry(wl.T)
+    d, w, th = dev(wl.data, torch.complex128), dev(wl.weights), dev(wl.theta)
+    dd = window_dd(wl)
+    for prec in (api.GB_FP64, api.GB_MIXED):
+        plan = api.Plan(ctx, wl.window_table(), prec)
+        plan.prepare(d, w)
+        l = plan.loglik(th).cpu().numpy()
+        for i in range(wl.n_win):
+            win = wl.windows[i]
+            a, n = int(wl.cand_off[i]), int(wl.n_cand[i])
+            dw, ww = wl.window_data(i)
+            lo, co = O.loglik(wl.theta[a:a + n], win.k0, win.W, win.N, win.C, dw, ww, g)
+            if prec == api.GB_FP64:
+                tol = loglik_tolerance(dd[i], co[:, 0], co[:, 1])
+                assert np.all(np.abs(l[a:a + n] - lo) <= tol), i
+            else:
+                _, cs = O.loglik(win.sources, win.k0, win.W, win.N, win.C, dw, ww, g)
+                rho = float(np.sqrt(cs[:, 1].max()))
+                e = delta_logl_error(l[a:a + n], lo, l[a], lo[0]).max()
+                assert e <= max(1e-5, MIXED_SLOPE * rho), (i, e, rho)
+        if prec == api.GB_MIXED:
+            with pytest.raises(api.GbxError) as err:
+                plan.loglik_grad(th)
+            assert err.value.status == api.GB_EUNSUPPORTED
+        plan.close()
+    ctx.close()
+
+
+def test_set_orbit_refuses_bad_grids():
+    banner("numerical orbits: bad grids refused on the host")
+    ctx = api.context_for(I.T1)
+    pos, t0, dt = I.orbit_grid(lambda t: I.keplerian_orbits(t), I.T1, 65)
+    for bad in ((pos[:3], t0, dt), (pos, t0, -dt), (pos, dt, dt), (pos[:40], t0, dt)):
+        with pytest.raises(api.GbxError) as err:
+            ctx.set_orbit(*bad)
+        assert err.value.status == api.GB_EINVAL
+    p2 = pos.copy()
+    p2[5, 1] = p2[5, 0]
+    with pytest.raises(api.GbxError):
+        ctx.set_orbit(p2, t0, dt)
+    p2 = pos.copy()
+    p2[7, 2, 1] = np.nan
+    with pytest.raises(api.GbxError):
+        ctx.set_orbit(p2, t0, dt)
+    ctx.close()
