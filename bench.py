@@ -865,6 +865,31 @@ def configs_leg(log, reps: int = 5):
             ", ".join(f"{k} {v['evals_per_s']:.3e}/s" for k, v in r.items() if isinstance(v, dict)))
     for c in ctxs.values():
         c.close()
+    # C3 on numerical orbits: the exact Keplerian orbits (arms breathing by +-0.24%) given as
+    # positions on a grid, one light time per arm in the templates and likelihoods (gb_set_orbit);
+    # injections computed on the same orbits.  Rates only: the flop model is the equal-arm one.
+    t0 = time.time()
+    ctx = api.context_for(I.T1)
+    pos, g0, gdt = I.orbit_grid(lambda t: I.keplerian_orbits(t), I.T1, 4097)
+    ctx.set_orbit(pos, g0, gdt)
+    wl = I.workload_c3(api.template_fn(ctx, api.GB_FP64), n_win=256, n_cand=10000)
+    d = torch.as_tensor(wl.data, device="cuda")
+    w = torch.as_tensor(wl.weights, device="cuda")
+    th = torch.as_tensor(wl.theta, device="cuda")
+    rows = len(wl.theta)
+    logL = torch.empty(rows, dtype=torch.float64, device="cuda")
+    r = {"workload": wl.name + ", on exact Keplerian orbits (one light time per arm)"}
+    for pname, prec in (("fp64", api.GB_FP64), ("mixed", api.GB_MIXED)):
+        p = api.Plan(ctx, wl.window_table(), prec)
+        p.prepare(d, w)
+        ms = timed(lambda: api.gb_loglik(p.handle, d, w, th, logL, None, stream))
+        r[f"{pname}_logl"] = {"evals_per_s": round(rows / (ms * 1e-3), 1), "ms_per_call": round(ms, 4),
+                              "evals_per_call": rows}
+        p.close()
+    ctx.close()
+    res["C3_numerical_orbits"] = r
+    log(f"configs: C3 on numerical orbits in {time.time() - t0:.1f} s: " +
+        ", ".join(f"{k} {v['evals_per_s']:.3e}/s" for k, v in r.items() if isinstance(v, dict)))
     return res
 
 

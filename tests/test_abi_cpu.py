@@ -1,6 +1,8 @@
 """The C-ABI library loads and exports every symbol include/gbx.h declares (no GPU needed)."""
 
 import ctypes
+
+import numpy as np
 import os
 import re
 
@@ -51,6 +53,10 @@ def test_argument_validation_without_device():
     assert L.gb_window_prepare(None, None, None, None) == api.GB_EINVAL
     assert L.gb_plan_info(None, None, None, None) == api.GB_EINVAL
     assert L.gb_autotune_windows(None, None, 0, None, None, None, 1, None, 0) == api.GB_EINVAL
+    assert L.gb_set_orbit(None, None, 0, 0.0, 0.0) == api.GB_EINVAL
+    assert b"null context" in L.gb_last_error()
+    with pytest.raises(ValueError):
+        api.gb_set_orbit(1, np.zeros((8, 3)), 0.0, 1.0)   # shape checked before any call
 
 
 def test_merge_tuning_reports():
