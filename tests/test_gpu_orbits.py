@@ -70,14 +70,18 @@ def test_templates_on_numerical_orbits(oracle_lib, kepler, tdi):
     ctx.close()
 
 
-def test_likelihoods_on_numerical_orbits(oracle_lib, kepler):
+@pytest.mark.parametrize("tdi", [1, 2])
+def test_likelihoods_on_numerical_orbits(oracle_lib, kepler, tdi):
     O = oracle_lib
     pos, t0, dt = kepler
-    banner("numerical orbits: FP64 and mixed logL, gradient refused")
-    ctx = api.context_for(I.T1)
+    banner(f"numerical orbits: FP64 and mixed logL, gradient refused, TDI {tdi}")
+    ctx = api.context_for(I.T1, tdi=tdi)
     ctx.set_orbit(pos, t0, dt)
-    wl = I.workload_c3(O.template_fn(), n_win=12, n_cand=40)   # injections from the oracle on these orbits
-    g = O.Geometry(wl.T)
+    # injections from the oracle on these orbits, noise of the generation's PSD
+    wl = I.workload_c3(None, n_win=12, n_cand=40, noise=False)
+    wl.tdi = tdi
+    wl = I.finalize_data(wl, O.template_fn(tdi=tdi), np.random.default_rng(80 + tdi))
+    g = O.Geometry(wl.T, tdi=tdi)
     d, w, th = dev(wl.data, torch.complex128), dev(wl.weights), dev(wl.theta)
     dd = window_dd(wl)
     for prec in (api.GB_FP64, api.GB_MIXED):
