@@ -115,11 +115,11 @@ gb_status gb_channels(const gb_ctx* ctx, int64_t k0, int32_t W, int32_t* C);
  * arm in the transfer function, and the TDI one delay per arm:
  *   X = (1 - D12^2)(y13 + D31 y31) - (1 - D31^2)(y12 + D12 y21), Y and Z cyclically,
  * times (1 - D31^2 D12^2) for the second generation (and cyclically), with the link phasors
- * taken at the sample time.  Applies to gb_waveform, gb_loglik, gb_mh_step, gb_fisher and
- * gb_add_templates of this context from the next call on, plans already built included (they
- * read the context's tables); not to calls in flight or already captured in a graph.
- * gb_loglik_grad on such a context returns GB_EUNSUPPORTED.  pos = NULL with n_pts = 0 returns
- * to the analytic orbits.  Synchronous; allocates a temporary device copy.  GB_EINVAL:
+ * taken at the sample time.  Applies to gb_waveform, gb_loglik, gb_loglik_grad (mixed
+ * precision, as on the analytic orbits), gb_mh_step, gb_fisher and gb_add_templates of this
+ * context from the next call on, plans already built included (they read the context's tables
+ * and pick the kernels of this model at launch); not to calls in flight or already captured in
+ * a graph.  pos = NULL with n_pts = 0 returns to the analytic orbits.  Synchronous; allocates a temporary device copy.  GB_EINVAL:
  * n_pts outside [4, 2^24], dt <= 0, a grid that does not cover [0, T], positions not finite, two
  * spacecraft at one point. */
 gb_status gb_set_orbit(gb_ctx* ctx, const double* pos, int32_t n_pts, double t0, double dt);

@@ -380,8 +380,8 @@ extern "C" gb_status gb_channels(const gb_ctx* c, int64_t k0, int32_t W, int32_t
 namespace {
 struct Bucket {
   int prec, N, C;
-  const Variant* v[4];  // per mode: waveform (unused), logL, gradient, logL on numerical orbits
-  int grid[4];
+  const Variant* v[6];  // per mode (MODE_*): logL, gradient and their numerical-orbit kernels used
+  int grid[6];
   Tile* d_tiles = nullptr;
   int n_tiles = 0;
   unsigned* d_ctr = nullptr;  // [2]
@@ -471,8 +471,8 @@ extern "C" gb_status gb_plan_create(gb_ctx* c, const gb_window* windows, int n_w
     b.prec = w0.prec;
     b.N = w0.N;
     b.C = w0.C;
-    for (int m = 0; m < 4; ++m) {
-      b.v[m] = pick_variant(c, b.prec, b.N, b.C, m);
+    for (int m = 0; m < 6; ++m) {
+      b.v[m] = (m == MODE_WAVEFORM || m == MODE_WAVEFORM_UNEQ) ? nullptr : pick_variant(c, b.prec, b.N, b.C, m);
       b.grid[m] = 0;
     }
     if (!b.v[MODE_LOGLIK]) {
@@ -498,7 +498,7 @@ extern "C" gb_status gb_plan_create(gb_ctx* c, const gb_window* windows, int n_w
       }
     }
     b.n_tiles = (int)tiles.size();
-    for (int m = 1; m < 4; ++m) {
+    for (int m = 1; m < 6; ++m) {
       if (!b.v[m]) continue;
       int nb = 0;
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, b.v[m]->fn, b.v[m]->WPB * 64, lds_bytes(*b.v[m]));
@@ -586,16 +586,13 @@ static gb_status run_batch(gb_plan* p, int mode, const double* d, const double* 
   if (d != p->prep_d || w != p->prep_w)
     return fail(GB_EINVAL, "%s: data/weights differ from the ones passed to gb_window_prepare", who);
   if (mode == MODE_GRAD && !grad) return fail(GB_EINVAL, "%s: null gradient array", who);
-  if (mode == MODE_GRAD && p->ctx->uneq)
-    return fail(GB_EUNSUPPORTED, "%s: no gradient on numerical orbits (gb_set_orbit); likelihoods and templates only",
-                who);
-  // numerical orbits take the likelihood kernels of one light time per arm, chosen at launch so
-  // that plans built before gb_set_orbit follow it
-  if (mode == MODE_LOGLIK && p->ctx->uneq) mode = MODE_LOGLIK_UNEQ;
+  // numerical orbits take the kernels of one light time per arm, chosen at launch so that plans
+  // built before gb_set_orbit follow it
+  if (p->ctx->uneq) mode = mode == MODE_GRAD ? MODE_GRAD_UNEQ : MODE_LOGLIK_UNEQ;
   // every bucket must have a kernel before any is launched, so a refused call writes nothing
   for (const Bucket& b : p->buckets) {
     if (b.n_tiles == 0 || b.v[mode]) continue;
-    if (mode == MODE_GRAD && b.prec == GB_FP64)
+    if ((mode == MODE_GRAD || mode == MODE_GRAD_UNEQ) && b.prec == GB_FP64)
       return fail(GB_EUNSUPPORTED,
                   "%s: the FP64 gradient is switched off (its kernels faulted on the GPU; cause not yet known); "
                   "use GB_MIXED", who);

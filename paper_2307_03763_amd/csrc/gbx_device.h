@@ -958,4 +958,178 @@ __device__ __forceinline__ void grad_sample_rev(const Cand<R>& s, const CandG<R>
   acc.ptt += t * t * (double)J.y;
 }
 
+// Contribution of slow-series sample m to the gradient on numerical orbits (one light time per
+// arm, the model of slow_sample_uneq).  With the channel cotangents folded onto X, Y, Z (bX, bY,
+// bZ, each times the second-generation factor when it applies) the sample's share of
+// sum_c conj(sbar_c) S_c is J = K' J1, K' = -i e^{2 pi i p}, J1 = bX X + bY Y + bZ Z, and every
+// link term is y = x_a sinc(x_a (1 -+ k.n_a)) b_a ph_o E_a (b_a = ap F+_a + ax Fx_a, ph_o the
+// phase of the spacecraft opposite the arm, E_a = e^{-i x_a}).  The derivatives along the local
+// frequency f, beta and lambda are carried forward through y, the delays D_a = E_a^2, the factors
+// 1 - D_a^2 and 1 - (D_i D_j)^2, and the phase of K' (through f k.R, with dk/dbeta = u and
+// dk/dlambda = cos(beta) v); the linear parts in ap and ax give GU and GV for the closed forms.
+template <class R, int C, bool TDI2>
+__device__ __forceinline__ void grad_sample_uneq(const Cand<R>& s, const CandG<R>& sg,
+                                                 const double* __restrict__ ob64, const R* __restrict__ obR,
+                                                 int N, int m, double t, const cplx<R> sbar[C], GradAcc& acc) {
+  constexpr bool BUF = sizeof(R) == 8;  // orbit reads through a buffer resource (ob_at)
+  const R pi = (R)kPi;
+  const double f = s.f0 + s.fd * t;
+  const double Rx = ob_at<BUF>(ob64, OB_RX, N, m), Ry = ob_at<BUF>(ob64, OB_RY, N, m);
+  const double Rz = ob_at<BUF>(ob64, OB_RZ, N, m);
+  const double kR = s.kxd * Rx + s.kyd * Ry + s.kzd * Rz;
+  double p = s.df * t + 0.5 * s.fd * t * t + s.phi0c - f * kR;
+  p -= rint(p);
+  R sp, cp;
+  sincos_rev((R)p, &sp, &cp);
+  const cplx<R> Kp = mul_mi(mk<R>(cp, sp));  // K' = -i e^{2 pi i p}
+  const R fr = (R)f;
+  const R uR = s.u[0] * (R)Rx + s.u[1] * (R)Ry + s.u[2] * (R)Rz;  // dk/dbeta . R
+  const R vR = s.v[0] * (R)Rx + s.v[1] * (R)Ry;                  // dk/dlambda . R / cos(beta)
+
+  // arms 12, 23, 31 (index 0, 1, 2)
+  R kn[3], un[3], vn[3], wn[3], Fp[3], Fx[3], xa[3], lt[3];
+  cplx<R> E[3], D[3], dD[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int o = OB_N12 + 3 * a;
+    const R n0 = ob_at<BUF>(obR, o + 0, N, m), n1 = ob_at<BUF>(obR, o + 1, N, m), n2 = ob_at<BUF>(obR, o + 2, N, m);
+    kn[a] = s.k[0] * n0 + s.k[1] * n1 + s.k[2] * n2;
+    un[a] = s.u[0] * n0 + s.u[1] * n1 + s.u[2] * n2;
+    vn[a] = s.v[0] * n0 + s.v[1] * n1;
+    wn[a] = sg.wl[0] * n0 + sg.wl[1] * n1;
+    Fp[a] = un[a] * un[a] - vn[a] * vn[a];
+    Fx[a] = (R)2 * un[a] * vn[a];
+    lt[a] = ob_at<BUF>(obR, OB_LT12 + a, N, m);
+    xa[a] = fr * pi * lt[a];
+    R se, ce;
+    sincos_rev((R)-0.5 * fr * lt[a], &se, &ce);
+    E[a] = mk<R>(ce, se);
+    D[a] = E[a] * E[a];
+    dD[a] = mul_mi(scal(D[a], (R)2 * pi * lt[a]));  // dD/df = -2 pi i LT D
+  }
+  // spacecraft 1, 2 (offsets from the centroid; spacecraft 3 is minus their sum)
+  R kp[3], up[3], vp[3];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int o = OB_P1 + 3 * i;
+    const R p0 = ob_at<BUF>(obR, o + 0, N, m), p1 = ob_at<BUF>(obR, o + 1, N, m), p2 = ob_at<BUF>(obR, o + 2, N, m);
+    kp[i] = s.k[0] * p0 + s.k[1] * p1 + s.k[2] * p2;
+    up[i] = s.u[0] * p0 + s.u[1] * p1 + s.u[2] * p2;
+    vp[i] = s.v[0] * p0 + s.v[1] * p1;
+  }
+  kp[2] = -(kp[0] + kp[1]);
+  up[2] = -(up[0] + up[1]);
+  vp[2] = -(vp[0] + vp[1]);
+  cplx<R> ph[3];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    R sc, cc;
+    sincos_rev((R)0.5 * fr * kp[i], &sc, &cc);
+    ph[i] = mk<R>(cc, sc);
+  }
+  ph[2] = conjg(ph[0] * ph[1]);
+  const int opp[3] = {2, 0, 1};  // arm 12 -> spacecraft 3, arm 23 -> 1, arm 31 -> 2
+
+  // link terms y and their derivatives; index 2a: the "1 - k.n" link, 2a+1: the "1 + k.n" link
+  // (arm 12: links 12, 21; arm 23: 23, 32; arm 31: 31, 13); U and V: b_a replaced by F+_a, Fx_a
+  cplx<R> y[6], yf[6], yb[6], yl[6], yU[6], yV[6];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int o = opp[a];
+    const cplx<R> pe = ph[o] * E[a];
+    const cplx<R> b = mk<R>(s.ap.x * Fp[a] + s.ax.x * Fx[a], s.ap.y * Fp[a] + s.ax.y * Fx[a]);
+    const R dFpb = (R)-2 * kn[a] * un[a], dFxb = (R)-2 * kn[a] * vn[a];
+    const R dFpl = (R)-2 * (sg.sb * un[a] * vn[a] + vn[a] * wn[a]);
+    const R dFxl = (R)2 * (un[a] * wn[a] - sg.sb * vn[a] * vn[a]);
+    const cplx<R> bb = mk<R>(s.ap.x * dFpb + s.ax.x * dFxb, s.ap.y * dFpb + s.ax.y * dFxb);
+    const cplx<R> bl = mk<R>(s.ap.x * dFpl + s.ax.x * dFxl, s.ap.y * dFpl + s.ax.y * dFxl);
+    const cplx<R> P = b * pe;
+    // phase rates of ph_o E_a along f, beta, lambda (times i)
+    const R wf = pi * (kp[o] - lt[a]), wb = pi * fr * up[o], wl = pi * fr * sg.cb * vp[o];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const R sgn = q == 0 ? (R)1 : (R)-1;  // u = x (1 - sgn k.n)
+      const R arg = xa[a] * ((R)1 - sgn * kn[a]);
+      R sv, sd;
+      sinc_d(arg, &sv, &sd);
+      const int l = 2 * a + q;
+      const R amp = xa[a] * sv;
+      y[l] = scal(P, amp);
+      yU[l] = scal(pe, amp * Fp[a]);
+      yV[l] = scal(pe, amp * Fx[a]);
+      // f: d(x_a sinc)/df = pi LT (sinc + x_a sinc' (1 - sgn k.n)); the phase adds i wf
+      const R damp_f = pi * lt[a] * (sv + xa[a] * sd * ((R)1 - sgn * kn[a]));
+      yf[l] = scal(P, damp_f) + mul_i(scal(y[l], wf));
+      // beta: the sinc argument moves by -sgn x_a u.n, b_a by bb, the phase by i wb
+      const R damp_b = xa[a] * sd * (-sgn * xa[a] * un[a]);
+      yb[l] = scal(P, damp_b) + scal(bb * pe, amp) + mul_i(scal(y[l], wb));
+      const R damp_l = xa[a] * sd * (-sgn * xa[a] * sg.cb * vn[a]);
+      yl[l] = scal(P, damp_l) + scal(bl * pe, amp) + mul_i(scal(y[l], wl));
+    }
+  }
+  const cplx<R>&y12 = y[0], &y21 = y[1], &y23 = y[2], &y32 = y[3], &y31 = y[4], &y13 = y[5];
+  // X, Y, Z from link terms z (the same combination for y, the derivatives along beta and
+  // lambda, and U, V): X = g0 (z13 + D2 z31) - g2 (z12 + D0 z21) and cyclically
+  const cplx<R> g[3] = {one_minus_sq(D[0]), one_minus_sq(D[1]), one_minus_sq(D[2])};
+  auto xyz = [&](const cplx<R>* z, cplx<R>& X, cplx<R>& Y, cplx<R>& Z) {
+    X = g[0] * (z[5] + D[2] * z[4]) - g[2] * (z[0] + D[0] * z[1]);
+    Y = g[1] * (z[1] + D[0] * z[0]) - g[0] * (z[2] + D[1] * z[3]);
+    Z = g[2] * (z[3] + D[1] * z[2]) - g[1] * (z[4] + D[2] * z[5]);
+  };
+  cplx<R> X, Y, Z, Xf, Yf, Zf, Xb, Yb, Zb, Xl, Yl, Zl, XU, YU, ZU, XV, YV, ZV;
+  xyz(y, X, Y, Z);
+  xyz(yf, Xf, Yf, Zf);
+  xyz(yb, Xb, Yb, Zb);
+  xyz(yl, Xl, Yl, Zl);
+  xyz(yU, XU, YU, ZU);
+  xyz(yV, XV, YV, ZV);
+  // the f-dependence of the delays and of 1 - D^2 inside X, Y, Z: dg = -2 D dD
+  const cplx<R> dg[3] = {scal(D[0] * dD[0], (R)-2), scal(D[1] * dD[1], (R)-2), scal(D[2] * dD[2], (R)-2)};
+  Xf = Xf + dg[0] * (y13 + D[2] * y31) + g[0] * (dD[2] * y31) - dg[2] * (y12 + D[0] * y21) - g[2] * (dD[0] * y21);
+  Yf = Yf + dg[1] * (y21 + D[0] * y12) + g[1] * (dD[0] * y12) - dg[0] * (y23 + D[1] * y32) - g[0] * (dD[1] * y32);
+  Zf = Zf + dg[2] * (y32 + D[1] * y23) + g[2] * (dD[1] * y23) - dg[1] * (y31 + D[2] * y13) - g[1] * (dD[2] * y13);
+  // channel cotangents folded onto X, Y, Z
+  const cplx<R> cA = conjg(sbar[0]), cE = conjg(sbar[1]);
+  const cplx<R> cT = (C == 3) ? conjg(sbar[C - 1]) : mk<R>((R)0, (R)0);
+  cplx<R> bX = cE + cT - cA, bY = cT - scal(cE, (R)2), bZ = cA + cE + cT;
+  cplx<R> dbX = mk<R>((R)0, (R)0), dbY = dbX, dbZ = dbX;
+  if (TDI2) {
+    // X2 = (1 - (D2 D0)^2) X and cyclically: the factor and its f-derivative -2 W dW, with
+    // dW = d(D_i D_j)/df = dD_i D_j + D_i dD_j
+    auto fold = [&](cplx<R>& b, cplx<R>& db, int i, int j) {
+      const cplx<R> W = D[i] * D[j];
+      const cplx<R> dW = dD[i] * D[j] + D[i] * dD[j];
+      db = b * scal(W * dW, (R)-2);
+      b = b * one_minus_sq(W);
+    };
+    fold(bX, dbX, 2, 0);
+    fold(bY, dbY, 0, 1);
+    fold(bZ, dbZ, 1, 2);
+  }
+  const cplx<R> J1 = bX * X + bY * Y + bZ * Z;
+  const cplx<R> J = Kp * J1;
+  const cplx<R> J1f = bX * Xf + bY * Yf + bZ * Zf + dbX * X + dbY * Y + dbZ * Z;
+  const cplx<R> J1b = bX * Xb + bY * Yb + bZ * Zb;
+  const cplx<R> J1l = bX * Xl + bY * Yl + bZ * Zl;
+  const cplx<R> GU = Kp * (bX * XU + bY * YU + bZ * ZU);
+  const cplx<R> GV = Kp * (bX * XV + bY * YV + bZ * ZV);
+  // the phase of K' moves by -2 pi f k.R: along f by -2 pi k.R, beta -2 pi f u.R, lambda
+  // -2 pi f cos(beta) v.R
+  const R twopi = (R)(2.0 * kPi);
+  const R gf = (Kp * J1f).x + J.y * (twopi * (R)kR);
+  const R gb = (Kp * J1b).x + J.y * (twopi * fr * uR);
+  const R gl = (Kp * J1l).x + J.y * (twopi * fr * sg.cb * vR);
+  const double gfd = (double)gf;
+  acc.gf += gfd;
+  acc.gtf += t * gfd;
+  acc.gb += (double)gb;
+  acc.gl += (double)gl;
+  acc.gu_re += (double)GU.x;
+  acc.gu_im += (double)GU.y;
+  acc.gv_re += (double)GV.x;
+  acc.gv_im += (double)GV.y;
+  acc.pt += t * (double)J.y;
+  acc.ptt += t * t * (double)J.y;
+}
+
 }  // namespace gbx

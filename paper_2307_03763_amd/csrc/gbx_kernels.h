@@ -7,9 +7,13 @@
 
 namespace gbx {
 
-// kernel modes; the last two are the likelihood and the templates of numerical orbits (one light
-// time per arm), kernels of their own so that the tuned equal-arm kernels keep their registers
-enum { MODE_WAVEFORM = 0, MODE_LOGLIK = 1, MODE_GRAD = 2, MODE_LOGLIK_UNEQ = 3, MODE_WAVEFORM_UNEQ = 4 };
+// kernel modes; the last three are the likelihood, the templates and the gradient of numerical
+// orbits (one light time per arm), kernels of their own so that the tuned equal-arm kernels keep
+// their registers
+enum {
+  MODE_WAVEFORM = 0, MODE_LOGLIK = 1, MODE_GRAD = 2,
+  MODE_LOGLIK_UNEQ = 3, MODE_WAVEFORM_UNEQ = 4, MODE_GRAD_UNEQ = 5
+};
 
 // Window descriptor as the kernels see it (device memory of a plan).
 struct DevWin {
@@ -187,14 +191,14 @@ __device__ __forceinline__ void process_loglik(const BatchArgs& a, const DevWin&
 // and each lane contracts it with the derivative of its samples (grad_sample_rev).  The
 // amplitude and the three extrinsic angles enter through closed forms; the carrier bin is
 // held fixed.
-template <class R, int N, int LPC, int C, int WPB>
+template <class R, int N, int LPC, int C, int WPB, bool UNEQ>
 __device__ __forceinline__ void process_grad(const BatchArgs& a, const DevWin& w, int64_t row, bool active,
                                              int lane, cplx<R>* buf, double (*s_red)[16]) {
   constexpr int E = N / LPC;
   const double* th = a.theta + 8 * row;
   const Cand<R> s = make_cand<R>(th, a.T);
   const CandG<R> sg = make_cand_grad<R>(th, s.ok);
-  template_to_lds<R, N, LPC, C>(s, a, lane, buf);
+  template_to_lds<R, N, LPC, C, UNEQ>(s, a, lane, buf);
   const double sc0 = a.T / (2.0 * (double)N);
   const double scale = s.amp * sc0;
   // v: 0 sum w|d-h|^2, 1 sum w|d|^2, 2 dlogL/dA, 3 gf, 4 gtf, 5 gb, 6 gl, 7..10 GU, GV, 11 pt, 12 ptt
@@ -240,11 +244,14 @@ __device__ __forceinline__ void process_grad(const BatchArgs& a, const DevWin& w
       cplx<R> sbar[C];
 #pragma unroll
       for (int c = 0; c < C; ++c) sbar[c] = buf[c * N + m];
-      grad_sample_rev<R, C, TDI2, SHORT>(s, sg, a.ob64, obR, N, m, t, a.Lc, sbar, ga);
+      if constexpr (UNEQ)
+        grad_sample_uneq<R, C, TDI2>(s, sg, a.ob64, obR, N, m, t, sbar, ga);
+      else
+        grad_sample_rev<R, C, TDI2, SHORT>(s, sg, a.ob64, obR, N, m, t, a.Lc, sbar, ga);
     }
   };
   // one branch per template, outside the loop
-  with_loop_flags(a.tdi2 != 0, wave_sinc_short<R>(s, a), samples);
+  with_loop_flags(a.tdi2 != 0, UNEQ ? false : wave_sinc_short<R>(s, a), samples);
   slot_reduce<LPC, WPB, 13>(v, s_red);
   if (lane == 0 && active) {
     const double nan = __builtin_nan("");
@@ -300,7 +307,8 @@ __global__ void __launch_bounds__(WPB * 64, OCC) k_batch(BatchArgs a) {
       const int64_t row = w.cand_off + tl.c0 + (active ? ci : 0);
       if (MODE == MODE_LOGLIK || MODE == MODE_LOGLIK_UNEQ)
         process_loglik<R, N, LPC, C, WPB, MODE == MODE_LOGLIK_UNEQ>(a, w, row, active, lane, buf, s_red);
-      if (MODE == MODE_GRAD) process_grad<R, N, LPC, C, WPB>(a, w, row, active, lane, buf, s_red);
+      if (MODE == MODE_GRAD || MODE == MODE_GRAD_UNEQ)
+        process_grad<R, N, LPC, C, WPB, MODE == MODE_GRAD_UNEQ>(a, w, row, active, lane, buf, s_red);
     }
   }
   if (tid == 0) {

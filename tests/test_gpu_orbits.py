@@ -7,7 +7,8 @@ and likelihoods take one light time per arm.
 * FP64 templates within 1e-10 (relative L2) of the oracle's, both TDI generations, every N.
 * FP64 logL within the FP64 bound, mixed logL differences within the mixed model, on windows
   of both channel counts.
-* The gradient is refused on such a context (GB_EUNSUPPORTED), before any launch.
+* Mixed gradients within the bar of the equal-arm gradient (MIXED_NAT of the natural scale)
+  against the oracle's dual-number gradient; the FP64 gradient is refused as on analytic orbits.
 * Returning to the analytic orbits restores the equal-arm templates.
 """
 
@@ -17,6 +18,7 @@ import pytest
 from paper_2307_03763_amd import api
 from paper_2307_03763_amd import inputs as I
 from tests.gpu_common import banner, delta_logl_error, dev, loglik_tolerance, window_dd
+from tests.test_gpu_grad import MIXED_NAT, _scales
 from tests.test_gpu_parity import MIXED_SLOPE
 
 pytestmark = pytest.mark.gpu
@@ -74,7 +76,7 @@ def test_templates_on_numerical_orbits(oracle_lib, kepler, tdi):
 def test_likelihoods_on_numerical_orbits(oracle_lib, kepler, tdi):
     O = oracle_lib
     pos, t0, dt = kepler
-    banner(f"numerical orbits: FP64 and mixed logL, gradient refused, TDI {tdi}")
+    banner(f"numerical orbits: FP64 and mixed logL, mixed gradient, TDI {tdi}")
     ctx = api.context_for(I.T1, tdi=tdi)
     ctx.set_orbit(pos, t0, dt)
     # injections from the oracle on these orbits, noise of the generation's PSD
@@ -102,10 +104,29 @@ def test_likelihoods_on_numerical_orbits(oracle_lib, kepler, tdi):
                 e = delta_logl_error(l[a:a + n], lo, l[a], lo[0]).max()
                 assert e <= max(1e-5, MIXED_SLOPE * rho), (i, e, rho)
         if prec == api.GB_MIXED:
-            with pytest.raises(api.GbxError) as err:
-                plan.loglik_grad(th)
-            assert err.value.status == api.GB_EUNSUPPORTED
+            # the mixed gradient against the oracle's dual-number gradient on the same orbits,
+            # at the bar of the equal-arm gradient (MIXED_NAT of the natural scale)
+            l2, gr = plan.loglik_grad(th)
+            gr = gr.cpu().numpy()
+            worst = 0.0
+            for i in range(0, wl.n_win, 2):
+                win = wl.windows[i]
+                a, n = int(wl.cand_off[i]), min(int(wl.n_cand[i]), 6)
+                dw, ww = wl.window_data(i)
+                _, go = O.loglik_grad(wl.theta[a:a + n], win.k0, win.W, win.N, win.C, dw, ww, g)
+                _, co = O.loglik(wl.theta[a:a + n], win.k0, win.W, win.N, win.C, dw, ww, g)
+                err = np.abs(gr[a:a + n] - go) / _scales(O, wl, i, wl.theta[a:a + n], co[:, 1])
+                worst = max(worst, float(err.max()))
+                assert err.max() <= MIXED_NAT, (i, err.max(axis=0))
+            banner(f"  mixed gradient: worst error / natural scale {worst:.2e}")
         plan.close()
+    # the FP64 gradient stays switched off on these orbits as on the analytic ones
+    plan = api.Plan(ctx, wl.window_table(), api.GB_FP64)
+    plan.prepare(d, w)
+    with pytest.raises(api.GbxError) as err:
+        plan.loglik_grad(th)
+    assert err.value.status == api.GB_EUNSUPPORTED
+    plan.close()
     ctx.close()
 
 
