@@ -866,8 +866,9 @@ def configs_leg(log, reps: int = 5):
     for c in ctxs.values():
         c.close()
     # C3 on numerical orbits: the exact Keplerian orbits (arms breathing by +-0.24%) given as
-    # positions on a grid, one light time per arm in the templates and likelihoods (gb_set_orbit);
-    # injections computed on the same orbits.  Rates only: the flop model is the equal-arm one.
+    # positions on a grid, one light time per arm in the templates, likelihoods and gradients
+    # (gb_set_orbit); injections computed on the same orbits.  Rates only: the flop model is the
+    # equal-arm one.
     t0 = time.time()
     ctx = api.context_for(I.T1)
     pos, g0, gdt = I.orbit_grid(lambda t: I.keplerian_orbits(t), I.T1, 4097)
@@ -885,6 +886,11 @@ def configs_leg(log, reps: int = 5):
         ms = timed(lambda: api.gb_loglik(p.handle, d, w, th, logL, None, stream))
         r[f"{pname}_logl"] = {"evals_per_s": round(rows / (ms * 1e-3), 1), "ms_per_call": round(ms, 4),
                               "evals_per_call": rows}
+        if prec == api.GB_MIXED:
+            grad = torch.empty((rows, 8), dtype=torch.float64, device="cuda")
+            ms = timed(lambda: api.gb_loglik_grad(p.handle, d, w, th, logL, grad, stream))
+            r["mixed_grad"] = {"evals_per_s": round(rows / (ms * 1e-3), 1), "ms_per_call": round(ms, 4),
+                               "evals_per_call": rows}
         p.close()
     ctx.close()
     res["C3_numerical_orbits"] = r
