@@ -87,6 +87,9 @@ def parse():
                          "standard deviation) to this .npz file")
     ap.add_argument("--traffic", nargs=4, metavar=("K_FETCH_DIR", "K_WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="print the profiles/hbm_traffic.txt line from rocprofv3 --pmc outputs and exit")
+    ap.add_argument("--tune-cache", metavar="JSON",
+                    help="reuse (or store) the synthetic autotune report in this cache file, keyed by library "
+                         "build, device and context (api.autotune_cached)")
     ap.add_argument("--tune-from", metavar="BENCH_JSON",
                     help="use the launch shapes that an earlier bench run chose (its output line)")
     ap.add_argument("--trace-summary", nargs=2, metavar=("BENCH_JSON", "TRACE_DIR"),
@@ -158,8 +161,12 @@ def main():
     else:
         # every family on synthetic candidates, then the families of this workload on its own
         # windows, data and candidates (the choice that its plans use)
-        tune = api.merge_tuning(api.gb_autotune(ctx.handle, 3),
-                                api.gb_autotune_windows(ctx.handle, table, d, w, th, 3))
+        if args.tune_cache:
+            generic, hit = api.autotune_cached(ctx, args.tune_cache, 3)
+            log(f"synthetic autotune {'from' if hit else 'stored in'} {args.tune_cache}")
+        else:
+            generic = api.gb_autotune(ctx.handle, 3)
+        tune = api.merge_tuning(generic, api.gb_autotune_windows(ctx.handle, table, d, w, th, 3))
     log(f"autotune {time.time() - t0:.1f}s:\n{tune}")
 
     # ---------------------------------------------------------------- precision policy

@@ -501,6 +501,40 @@ def apply_tuning(ctx: int, report: str) -> int:
     return n
 
 
+def tuning_key(ctx: "Context", device: Optional[str] = None) -> str:
+    """Key of a tuning report: the library build (sha256 of libgbx.so), the device name and the
+    context's settings (observation time, TDI generation) -- what the timings depend on."""
+    import hashlib
+    h = hashlib.sha256(open(LIB_PATH, "rb").read()).hexdigest()[:16]
+    if device is None:
+        device = torch.cuda.get_device_name(torch.cuda.current_device())
+    return f"{h}|{device}|T={ctx.T!r}|tdi={ctx.tdi}"
+
+
+def autotune_cached(ctx: "Context", path: str, reps: int = 3, tune=None, device: Optional[str] = None) -> tuple:
+    """gb_autotune through a cache file (JSON, {key: report}): a report stored under this
+    context's tuning_key is re-applied (apply_tuning) instead of timing again; otherwise the
+    context is tuned (tune(ctx), by default gb_autotune with `reps`) and the report stored.
+    Returns (report, True if it came from the cache).  Reports are plain text, so the file can
+    be shared between processes that run the same build on the same device."""
+    import json
+    key = tuning_key(ctx, device)
+    cache = {}
+    if os.path.exists(path):
+        with open(path) as fh:
+            cache = json.load(fh)
+    if key in cache:
+        apply_tuning(ctx.handle, cache[key])
+        return cache[key], True
+    report = tune(ctx) if tune is not None else gb_autotune(ctx.handle, reps)
+    cache[key] = report
+    tmp = path + ".tmp"
+    with open(tmp, "w") as fh:
+        json.dump(cache, fh, indent=1)
+    os.replace(tmp, path)
+    return report, False
+
+
 # ------------------------------------------------------------------------------------------
 # Destruction during a HIP-graph capture.  gb_destroy and gb_plan_destroy free device memory,
 # and a free while a stream is being captured invalidates the capture.  A capture may see such a

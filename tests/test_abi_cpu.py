@@ -137,3 +137,30 @@ def test_binding_refuses_missized_tensors_before_any_call(monkeypatch):
     # correctly sized host tensors pass the size checks and are then refused as not on the device
     with pytest.raises(TypeError):
         api.gb_loglik(1, d, w, th, one, torch.zeros((rows, 2), dtype=f64))
+
+
+def test_autotune_cache(tmp_path, monkeypatch):
+    """autotune_cached tunes once per (library build, device, T, TDI generation) and re-applies
+    the stored report afterwards; another key tunes again."""
+    from paper_2307_03763_amd import api
+
+    class Ctx:
+        handle, T, tdi = 7, 6.3e7, 1
+    applied, tuned = [], []
+    monkeypatch.setattr(api, "apply_tuning", lambda h, rep: applied.append((h, rep)) or 1)
+    path = str(tmp_path / "tune.json")
+
+    def tune(c):
+        tuned.append(c)
+        return f"report {len(tuned)}"
+    r1, hit1 = api.autotune_cached(Ctx(), path, tune=tune, device="gfx950 A")
+    r2, hit2 = api.autotune_cached(Ctx(), path, tune=tune, device="gfx950 A")
+    assert (r1, hit1, r2, hit2) == ("report 1", False, "report 1", True)
+    assert applied == [(7, "report 1")] and len(tuned) == 1
+    r3, hit3 = api.autotune_cached(Ctx(), path, tune=tune, device="gfx950 B")
+    c2 = Ctx()
+    c2.tdi = 2
+    r4, hit4 = api.autotune_cached(c2, path, tune=tune, device="gfx950 A")
+    assert (hit3, hit4) == (False, False) and len(tuned) == 3
+    import json
+    assert len(json.load(open(path))) == 3
