@@ -560,11 +560,14 @@ __device__ __forceinline__ void stockham_pass(cplx<R>* buf, int lane, int Ns, co
     const int j = lane + LPC * b;
     const int k = j & (Ns - 1);
     const int step = k * (N / (Ns * RADIX));
+    // the first pass (Ns = 1, a compile-time constant once fft_lds is unrolled) has every
+    // twiddle equal to 1: no loads, no products
+    const bool first = Ns == 1;
     cplx<R> w[RADIX];
     w[0] = mk<R>((R)1, (R)0);
 #pragma unroll
     for (int r = 1; r < RADIX; ++r) {
-      const cplx<R> t = tw[r * step];
+      const cplx<R> t = first ? mk<R>((R)1, (R)0) : tw[r * step];
       w[r] = (DIR < 0) ? t : conjg(t);
     }
     const int base = (j - k) * RADIX + k;
@@ -572,7 +575,7 @@ __device__ __forceinline__ void stockham_pass(cplx<R>* buf, int lane, int Ns, co
     for (int c = 0; c < C; ++c) {
       cplx<R> a[RADIX];
 #pragma unroll
-      for (int r = 0; r < RADIX; ++r) a[r] = (r == 0) ? v[c][b][0] : v[c][b][r] * w[r];
+      for (int r = 0; r < RADIX; ++r) a[r] = (r == 0 || first) ? v[c][b][r] : v[c][b][r] * w[r];
       if (RADIX == 2) {
         buf[c * N + base] = a[0] + a[1];
         buf[c * N + base + Ns] = a[0] - a[1];
