@@ -150,7 +150,9 @@ __device__ __forceinline__ void process_loglik(const BatchArgs& a, const DevWin&
   const Cand<R> s = make_cand<R>(a.theta + 8 * row, a.T);
   template_to_lds<R, N, LPC, C, UNEQ>(s, a, lane, buf);
   const double scale = s.amp * a.T / (2.0 * (double)N);
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};  // sum w|d-h|^2, sum w|d|^2, <d|h>, <h|h> over the overlap
+  // <d|h> and <h|h> over the overlap.  The template is zero outside it, so
+  // -<d-h|d-h>/2 = -dd/2 + <d|h> - <h|h>/2 with dd the window's data norm.
+  double acc[2] = {0.0, 0.0};
   const int64_t off = w.data_off;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
@@ -165,21 +167,18 @@ __device__ __forceinline__ void process_loglik(const BatchArgs& a, const DevWin&
         const double hre = (double)hv.x * sc, him = (double)hv.y * sc;
         const int64_t g = off + (int64_t)c * w.W + kk;
         const double dre = a.d[2 * g], dim = a.d[2 * g + 1], wk = a.w[g];
-        const double rre = dre - hre, rim = dim - him;
-        acc[0] += wk * (rre * rre + rim * rim);
-        acc[1] += wk * (dre * dre + dim * dim);
-        acc[2] += wk * (dre * hre + dim * him);
-        acc[3] += wk * (hre * hre + him * him);
+        acc[0] += wk * (dre * hre + dim * him);
+        acc[1] += wk * (hre * hre + him * him);
       }
     }
   }
-  slot_reduce<LPC, WPB, 4>(acc, s_red);
+  slot_reduce<LPC, WPB, 2>(acc, s_red);
   if (lane == 0 && active) {
     const double nan = __builtin_nan("");
-    a.logL[row] = s.ok ? -0.5 * ((w.dd - acc[1]) + acc[0]) : nan;
+    a.logL[row] = s.ok ? (acc[0] - 0.5 * acc[1]) - 0.5 * w.dd : nan;
     if (a.comps) {
-      a.comps[2 * row] = s.ok ? acc[2] : nan;
-      a.comps[2 * row + 1] = s.ok ? acc[3] : nan;
+      a.comps[2 * row] = s.ok ? acc[0] : nan;
+      a.comps[2 * row + 1] = s.ok ? acc[1] : nan;
     }
   }
   slot_sync<LPC>();
@@ -201,10 +200,12 @@ __device__ __forceinline__ void process_grad(const BatchArgs& a, const DevWin& w
   template_to_lds<R, N, LPC, C, UNEQ>(s, a, lane, buf);
   const double sc0 = a.T / (2.0 * (double)N);
   const double scale = s.amp * sc0;
-  // v: 0 sum w|d-h|^2, 1 sum w|d|^2, 2 dlogL/dA, 3 gf, 4 gtf, 5 gb, 6 gl, 7..10 GU, GV, 11 pt, 12 ptt
-  double v[13];
+  // v: 0 dlogL/dA = sum w Re((d-h) conj(h_u)), 1 <h_u|h_u>, 2 gf, 3 gtf, 4 gb, 5 gl, 6..9 GU, GV,
+  // 10 pt, 11 ptt; h = A h_u.  With r = d - h, -<r|r>/2 = -dd/2 + A v0 + A^2 v1 / 2 (the
+  // template is zero outside the overlap).
+  double v[12];
 #pragma unroll
-  for (int i = 0; i < 13; ++i) v[i] = 0.0;
+  for (int i = 0; i < 12; ++i) v[i] = 0.0;
   const int64_t off = w.data_off;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
@@ -223,9 +224,8 @@ __device__ __forceinline__ void process_grad(const BatchArgs& a, const DevWin& w
         const int64_t g = off + (int64_t)c * w.W + kk;
         const double dre = a.d[2 * g], dim = a.d[2 * g + 1], wk = a.w[g];
         const double rre = dre - hre, rim = dim - him;
-        v[0] += wk * (rre * rre + rim * rim);
-        v[1] += wk * (dre * dre + dim * dim);
-        v[2] += wk * (rre * hur + rim * hui);
+        v[0] += wk * (rre * hur + rim * hui);
+        v[1] += wk * (hur * hur + hui * hui);
         cot = mk<R>((R)(scn * wk * rre), (R)(scn * wk * rim));
       }
       buf[c * N + idx] = cot;
@@ -233,7 +233,7 @@ __device__ __forceinline__ void process_grad(const BatchArgs& a, const DevWin& w
   }
   slot_sync<LPC>();
   fft_lds<R, N, LPC, C, +1>(buf, lane, (const cplx<R>*)a.tw);
-  GradAcc& ga = *reinterpret_cast<GradAcc*>(&v[3]);  // v[3..12]: per-sample accumulators
+  GradAcc& ga = *reinterpret_cast<GradAcc*>(&v[2]);  // v[2..11]: per-sample accumulators
   const R* obR = (const R*)a.obR;
   auto samples = [&](auto tdi2, auto shrt) {
     constexpr bool TDI2 = decltype(tdi2)::value, SHORT = decltype(shrt)::value;
@@ -252,7 +252,7 @@ __device__ __forceinline__ void process_grad(const BatchArgs& a, const DevWin& w
   };
   // one branch per template, outside the loop
   with_loop_flags(a.tdi2 != 0, UNEQ ? false : wave_sinc_short<R>(s, a), samples);
-  slot_reduce<LPC, WPB, 13>(v, s_red);
+  slot_reduce<LPC, WPB, 12>(v, s_red);
   if (lane == 0 && active) {
     const double nan = __builtin_nan("");
     double* g = a.grad + 8 * row;
@@ -260,20 +260,20 @@ __device__ __forceinline__ void process_grad(const BatchArgs& a, const DevWin& w
       a.logL[row] = nan;
       for (int i = 0; i < 8; ++i) g[i] = nan;
     } else {
-      a.logL[row] = -0.5 * ((w.dd - v[1]) + v[0]);
+      a.logL[row] = s.amp * (v[0] + 0.5 * s.amp * v[1]) - 0.5 * w.dd;
       double si, ci, s2, c2;
       sincos_rad(th[5], &si, &ci);
       sincos_rad(2.0 * th[6], &s2, &c2);
       const double Ap = 1.0 + ci * ci, Ac = -2.0 * ci;
       const double apx = Ap * c2, apy = Ac * s2, axx = Ap * s2, axy = -Ac * c2;
-      const double gur = v[7], gui = v[8], gvr = v[9], gvi = v[10];
+      const double gur = ga.gu_re, gui = ga.gu_im, gvr = ga.gv_re, gvi = ga.gv_im;
       auto re_lin = [&](double px, double py, double qx, double qy) { return px * gur - py * gui + qx * gvr - qy * gvi; };
       const double dAp = -2.0 * ci * si, dAc = 2.0 * si;
-      g[0] = v[3] - 2.0 * kPi * v[11];
-      g[1] = v[4] - kPi * v[12];
-      g[2] = v[5];
-      g[3] = v[6];
-      g[4] = v[2];
+      g[0] = ga.gf - 2.0 * kPi * ga.pt;
+      g[1] = ga.gtf - kPi * ga.ptt;
+      g[2] = ga.gb;
+      g[3] = ga.gl;
+      g[4] = v[0];
       g[5] = re_lin(dAp * c2, dAc * s2, dAp * s2, -dAc * c2);
       g[6] = re_lin(-2.0 * Ap * s2, 2.0 * Ac * c2, 2.0 * Ap * c2, 2.0 * Ac * s2);
       g[7] = -(apx * gui + apy * gur + axx * gvi + axy * gvr);
