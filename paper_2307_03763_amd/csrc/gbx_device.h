@@ -877,19 +877,18 @@ __device__ __forceinline__ void grad_sample_rev(const Cand<R>& s, const CandG<R>
   Lam[0] = bY * G(s21, s12) - bX * G(s12, s21);
   Lam[1] = bZ * G(s32, s23) - bY * G(s23, s32);
   Lam[2] = bX * G(s13, s31) - bZ * G(s31, s13);
-  cplx<R> Q = mk<R>((R)0, (R)0), QU = Q, QV = Q;
+  // GU = K sum_a F+_a Lam_a E_a and GV = K sum_a Fx_a Lam_a E_a from the per-arm K Lam_a E_a
+  cplx<R> Q = mk<R>((R)0, (R)0), GU = Q, GV = Q;
   cplx<R> KLP[3], KLE[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const cplx<R> LE = Lam[a] * E[a];
     Q = Q + Lam[a] * P[a];
-    QU = QU + scal(LE, Fp[a]);
-    QV = QV + scal(LE, Fx[a]);
-    KLE[a] = K * LE;
+    KLE[a] = K * (Lam[a] * E[a]);
+    GU = GU + scal(KLE[a], Fp[a]);
+    GV = GV + scal(KLE[a], Fx[a]);
     KLP[a] = K * (Lam[a] * P[a]);
   }
   const cplx<R> J = K * Q;
-  const cplx<R> GU = K * QU, GV = K * QV;
 
   // amplitude and phase of K
   const R EQre = (Ep * Q).x;
