@@ -1070,6 +1070,7 @@ def cpu_baseline(wl, seconds, logL_gpu, rho_w, log, grad_gpu=None, grad_acc=None
     threads = O.max_threads()
     order = sorted(range(wl.n_win), key=lambda i: (wl.windows[i].N, wl.windows[i].C))
     sample = order[:: max(1, len(order) // 16)][:16]
+    check = sample   # the accuracy checks below: the same 16 windows whatever the timing sample
     lg = np.asarray(logL_gpu)
 
     def run(n_cand, sample, nthreads=0):
@@ -1102,7 +1103,7 @@ def cpu_baseline(wl, seconds, logL_gpu, rho_w, log, grad_gpu=None, grad_acc=None
     n1 = int(max(16, min(n_cand, 0.1 * seconds / (per * threads * len(sample)))))
     ev_1, spent_1, _ = run(n1, sample, 1)
     errs = {}
-    for i in sample[:: max(1, len(sample) // 16)]:
+    for i in check:
         win = wl.windows[i]
         dd, ww = wl.window_data(i)
         th = wl.window_theta(i)[:64]
@@ -1115,7 +1116,7 @@ def cpu_baseline(wl, seconds, logL_gpu, rho_w, log, grad_gpu=None, grad_acc=None
         # mixed gradients of 4 rows in each of 16 sampled windows against the oracle gradient, in
         # units of sqrt(F_ii) (the oracle's Fisher matrix at the row)
         e_f, norm = [], []
-        for i in sample[:: max(1, len(sample) // 16)][:16]:
+        for i in check:
             win = wl.windows[i]
             dd, ww = wl.window_data(i)
             a = int(wl.cand_off[i])
