@@ -961,20 +961,24 @@ __device__ __forceinline__ void grad_sample_rev(const Cand<R>& s, const CandG<R>
 }
 
 // Contribution of slow-series sample m to the gradient on numerical orbits (one light time per
-// arm, the model of slow_sample_uneq).  With the channel cotangents folded onto X, Y, Z (bX, bY,
-// bZ, each times the second-generation factor when it applies) the sample's share of
-// sum_c conj(sbar_c) S_c is J = K' J1, K' = -i e^{2 pi i p}, J1 = bX X + bY Y + bZ Z, and every
-// link term is y = x_a sinc(x_a (1 -+ k.n_a)) b_a ph_o E_a (b_a = ap F+_a + ax Fx_a, ph_o the
-// phase of the spacecraft opposite the arm, E_a = e^{-i x_a}).  The derivatives along the local
-// frequency f, beta and lambda are carried forward through y, the delays D_a = E_a^2, the factors
-// 1 - D_a^2 and 1 - (D_i D_j)^2, and the phase of K' (through f k.R, with dk/dbeta = u and
-// dk/dlambda = cos(beta) v); the linear parts in ap and ax give GU and GV for the closed forms.
+// arm, the model of slow_sample_uneq), by hand-written reverse mode.  Every link term is
+// y_l = x_a sinc(x_a (1 -+ k.n_a)) b_a ph_o E_a (b_a = ap F+_a + ax Fx_a, ph_o the phase of the
+// spacecraft opposite the arm, E_a = e^{-i x_a}).  The channel cotangents, folded onto X, Y, Z
+// and multiplied by K' = -i e^{2 pi i p} (and by the second-generation factors 1 - (D_i D_j)^2
+// when they apply), give one complex coefficient k_l per link, so that the sample's share of
+// sum_c conj(sbar_c) S_c is J = sum_l k_l y_l.  Its derivatives along the local frequency f,
+// beta and lambda then need only the per-link derivatives of y_l (amplitude, projections,
+// phases of ph_o E_a) contracted with k_l, plus, along f, the partial derivatives of J in the
+// delays D_a = E_a^2 (in the coefficients 1 - D_a^2, the explicit delays and the
+// second-generation factors) times dD_a/df = -2 pi i LT_a D_a, and the phase of K' (through
+// f k.R, with dk/dbeta = u and dk/dlambda = cos(beta) v).  GU and GV are J with b_a replaced by
+// F+_a and Fx_a.
 template <class R, int C, bool TDI2>
 __device__ __forceinline__ void grad_sample_uneq(const Cand<R>& s, const CandG<R>& sg,
                                                  const double* __restrict__ ob64, const R* __restrict__ obR,
                                                  int N, int m, double t, const cplx<R> sbar[C], GradAcc& acc) {
   constexpr bool BUF = sizeof(R) == 8;  // orbit reads through a buffer resource (ob_at)
-  const R pi = (R)kPi;
+  const R pi = (R)kPi, twopi = (R)(2.0 * kPi);
   const double f = s.f0 + s.fd * t;
   const double Rx = ob_at<BUF>(ob64, OB_RX, N, m), Ry = ob_at<BUF>(ob64, OB_RY, N, m);
   const double Rz = ob_at<BUF>(ob64, OB_RZ, N, m);
@@ -990,7 +994,7 @@ __device__ __forceinline__ void grad_sample_uneq(const Cand<R>& s, const CandG<R
 
   // arms 12, 23, 31 (index 0, 1, 2)
   R kn[3], un[3], vn[3], wn[3], Fp[3], Fx[3], xa[3], lt[3];
-  cplx<R> E[3], D[3], dD[3];
+  cplx<R> E[3], D[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const int o = OB_N12 + 3 * a;
@@ -1007,7 +1011,6 @@ __device__ __forceinline__ void grad_sample_uneq(const Cand<R>& s, const CandG<R
     sincos_rev((R)-0.5 * fr * lt[a], &se, &ce);
     E[a] = mk<R>(ce, se);
     D[a] = E[a] * E[a];
-    dD[a] = mul_mi(scal(D[a], (R)2 * pi * lt[a]));  // dD/df = -2 pi i LT D
   }
   // spacecraft 1, 2 (offsets from the centroid; spacecraft 3 is minus their sum)
   R kp[3], up[3], vp[3];
@@ -1032,9 +1035,34 @@ __device__ __forceinline__ void grad_sample_uneq(const Cand<R>& s, const CandG<R
   ph[2] = conjg(ph[0] * ph[1]);
   const int opp[3] = {2, 0, 1};  // arm 12 -> spacecraft 3, arm 23 -> 1, arm 31 -> 2
 
-  // link terms y and their derivatives; index 2a: the "1 - k.n" link, 2a+1: the "1 + k.n" link
-  // (arm 12: links 12, 21; arm 23: 23, 32; arm 31: 31, 13); U and V: b_a replaced by F+_a, Fx_a
-  cplx<R> y[6], yf[6], yb[6], yl[6], yU[6], yV[6];
+  // channel cotangents folded onto X, Y, Z, times K'; second generation: X2 = (1 - W_X^2) X with
+  // W_X = D2 D0, W_Y = D0 D1, W_Z = D1 D2
+  const cplx<R> cA = conjg(sbar[0]), cE = conjg(sbar[1]);
+  const cplx<R> cT = (C == 3) ? conjg(sbar[C - 1]) : mk<R>((R)0, (R)0);
+  const cplx<R> b3[3] = {Kp * (cE + cT - cA), Kp * (cT - scal(cE, (R)2)), Kp * (cA + cE + cT)};
+  cplx<R> W[3], bf[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) bf[i] = b3[i];
+  if (TDI2) {
+    W[0] = D[2] * D[0];
+    W[1] = D[0] * D[1];
+    W[2] = D[1] * D[2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) bf[i] = b3[i] * one_minus_sq(W[i]);
+  }
+  // link coefficients from X = g0 (y13 + D2 y31) - g2 (y12 + D0 y21) and cyclically
+  // (g_a = 1 - D_a^2; links 12, 21, 23, 32, 31, 13 at index 0..5)
+  const cplx<R> g[3] = {one_minus_sq(D[0]), one_minus_sq(D[1]), one_minus_sq(D[2])};
+  const cplx<R> A0 = bf[0] * g[0], A2 = bf[0] * g[2], B0 = bf[1] * g[0];
+  const cplx<R> B1 = bf[1] * g[1], C1 = bf[2] * g[1], C2 = bf[2] * g[2];
+  const cplx<R> k[6] = {B1 * D[0] - A2, B1 - A2 * D[0], C2 * D[1] - B0,
+                        C2 - B0 * D[1], A0 * D[2] - C1, A0 - C1 * D[2]};
+
+  // per arm: kap = sum over its two links of k_l x_a sinc (J's share is kap P_a), and the
+  // same sums with the derivatives of x_a sinc along f, beta, lambda
+  R gf = (R)0, gb = (R)0, gl = (R)0, Jy = (R)0;
+  cplx<R> GU = mk<R>((R)0, (R)0), GV = GU;
+  cplx<R> y[6];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const int o = opp[a];
@@ -1046,8 +1074,9 @@ __device__ __forceinline__ void grad_sample_uneq(const Cand<R>& s, const CandG<R
     const cplx<R> bb = mk<R>(s.ap.x * dFpb + s.ax.x * dFxb, s.ap.y * dFpb + s.ax.y * dFxb);
     const cplx<R> bl = mk<R>(s.ap.x * dFpl + s.ax.x * dFxl, s.ap.y * dFpl + s.ax.y * dFxl);
     const cplx<R> P = b * pe;
-    // phase rates of ph_o E_a along f, beta, lambda (times i)
+    // phase rates of ph_o E_a along f, beta, lambda
     const R wf = pi * (kp[o] - lt[a]), wb = pi * fr * up[o], wl = pi * fr * sg.cb * vp[o];
+    cplx<R> kap = mk<R>((R)0, (R)0), phf = kap, phb = kap, phl = kap;
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const R sgn = q == 0 ? (R)1 : (R)-1;  // u = x (1 - sgn k.n)
@@ -1057,70 +1086,49 @@ __device__ __forceinline__ void grad_sample_uneq(const Cand<R>& s, const CandG<R
       const int l = 2 * a + q;
       const R amp = xa[a] * sv;
       y[l] = scal(P, amp);
-      yU[l] = scal(pe, amp * Fp[a]);
-      yV[l] = scal(pe, amp * Fx[a]);
-      // f: d(x_a sinc)/df = pi LT (sinc + x_a sinc' (1 - sgn k.n)); the phase adds i wf
+      // f: d(x_a sinc)/df = pi LT (sinc + x_a sinc' (1 - sgn k.n)); beta: the sinc argument
+      // moves by -sgn x_a u.n; lambda: by -sgn x_a cos(beta) v.n
       const R damp_f = pi * lt[a] * (sv + xa[a] * sd * ((R)1 - sgn * kn[a]));
-      yf[l] = scal(P, damp_f) + mul_i(scal(y[l], wf));
-      // beta: the sinc argument moves by -sgn x_a u.n, b_a by bb, the phase by i wb
       const R damp_b = xa[a] * sd * (-sgn * xa[a] * un[a]);
-      yb[l] = scal(P, damp_b) + scal(bb * pe, amp) + mul_i(scal(y[l], wb));
       const R damp_l = xa[a] * sd * (-sgn * xa[a] * sg.cb * vn[a]);
-      yl[l] = scal(P, damp_l) + scal(bl * pe, amp) + mul_i(scal(y[l], wl));
+      kap = kap + scal(k[l], amp);
+      phf = phf + scal(k[l], damp_f);
+      phb = phb + scal(k[l], damp_b);
+      phl = phl + scal(k[l], damp_l);
     }
+    const cplx<R> kP = kap * P, kpe = kap * pe;
+    // Re(i w z) = -w Im(z) for the phase rates
+    Jy += kP.y;
+    gf += (P * phf).x - wf * kP.y;
+    gb += (P * phb).x + (kpe * bb).x - wb * kP.y;
+    gl += (P * phl).x + (kpe * bl).x - wl * kP.y;
+    GU = GU + scal(kpe, Fp[a]);
+    GV = GV + scal(kpe, Fx[a]);
   }
-  const cplx<R>&y12 = y[0], &y21 = y[1], &y23 = y[2], &y32 = y[3], &y31 = y[4], &y13 = y[5];
-  // X, Y, Z from link terms z (the same combination for y, the derivatives along beta and
-  // lambda, and U, V): X = g0 (z13 + D2 z31) - g2 (z12 + D0 z21) and cyclically
-  const cplx<R> g[3] = {one_minus_sq(D[0]), one_minus_sq(D[1]), one_minus_sq(D[2])};
-  auto xyz = [&](const cplx<R>* z, cplx<R>& X, cplx<R>& Y, cplx<R>& Z) {
-    X = g[0] * (z[5] + D[2] * z[4]) - g[2] * (z[0] + D[0] * z[1]);
-    Y = g[1] * (z[1] + D[0] * z[0]) - g[0] * (z[2] + D[1] * z[3]);
-    Z = g[2] * (z[3] + D[1] * z[2]) - g[1] * (z[4] + D[2] * z[5]);
-  };
-  cplx<R> X, Y, Z, Xf, Yf, Zf, Xb, Yb, Zb, Xl, Yl, Zl, XU, YU, ZU, XV, YV, ZV;
-  xyz(y, X, Y, Z);
-  xyz(yf, Xf, Yf, Zf);
-  xyz(yb, Xb, Yb, Zb);
-  xyz(yl, Xl, Yl, Zl);
-  xyz(yU, XU, YU, ZU);
-  xyz(yV, XV, YV, ZV);
-  // the f-dependence of the delays and of 1 - D^2 inside X, Y, Z: dg = -2 D dD
-  const cplx<R> dg[3] = {scal(D[0] * dD[0], (R)-2), scal(D[1] * dD[1], (R)-2), scal(D[2] * dD[2], (R)-2)};
-  Xf = Xf + dg[0] * (y13 + D[2] * y31) + g[0] * (dD[2] * y31) - dg[2] * (y12 + D[0] * y21) - g[2] * (dD[0] * y21);
-  Yf = Yf + dg[1] * (y21 + D[0] * y12) + g[1] * (dD[0] * y12) - dg[0] * (y23 + D[1] * y32) - g[0] * (dD[1] * y32);
-  Zf = Zf + dg[2] * (y32 + D[1] * y23) + g[2] * (dD[1] * y23) - dg[1] * (y31 + D[2] * y13) - g[1] * (dD[2] * y13);
-  // channel cotangents folded onto X, Y, Z
-  const cplx<R> cA = conjg(sbar[0]), cE = conjg(sbar[1]);
-  const cplx<R> cT = (C == 3) ? conjg(sbar[C - 1]) : mk<R>((R)0, (R)0);
-  cplx<R> bX = cE + cT - cA, bY = cT - scal(cE, (R)2), bZ = cA + cE + cT;
-  cplx<R> dbX = mk<R>((R)0, (R)0), dbY = dbX, dbZ = dbX;
+  // along f through the delays: dJ[a] = dJ/dD_a with the link terms held
+  const cplx<R> SX0 = y[5] + D[2] * y[4], SX2 = y[0] + D[0] * y[1];
+  const cplx<R> SY1 = y[1] + D[0] * y[0], SY0 = y[2] + D[1] * y[3];
+  const cplx<R> SZ2 = y[3] + D[1] * y[2], SZ1 = y[4] + D[2] * y[5];
+  cplx<R> dJ[3];
+  dJ[0] = bf[0] * (scal(D[0] * SX0, (R)-2) - g[2] * y[1]) + bf[1] * (g[1] * y[0] + scal(D[0] * SY0, (R)2));
+  dJ[1] = bf[1] * (scal(D[1] * SY1, (R)-2) - g[0] * y[3]) + bf[2] * (g[2] * y[2] + scal(D[1] * SZ1, (R)2));
+  dJ[2] = bf[2] * (scal(D[2] * SZ2, (R)-2) - g[1] * y[5]) + bf[0] * (g[0] * y[4] + scal(D[2] * SX2, (R)2));
   if (TDI2) {
-    // X2 = (1 - (D2 D0)^2) X and cyclically: the factor and its f-derivative -2 W dW, with
-    // dW = d(D_i D_j)/df = dD_i D_j + D_i dD_j
-    auto fold = [&](cplx<R>& b, cplx<R>& db, int i, int j) {
-      const cplx<R> W = D[i] * D[j];
-      const cplx<R> dW = dD[i] * D[j] + D[i] * dD[j];
-      db = b * scal(W * dW, (R)-2);
-      b = b * one_minus_sq(W);
-    };
-    fold(bX, dbX, 2, 0);
-    fold(bY, dbY, 0, 1);
-    fold(bZ, dbZ, 1, 2);
+    // d(1 - W^2)/dD_a = -2 W dW/dD_a
+    const cplx<R> X = g[0] * SX0 - g[2] * SX2, Y = g[1] * SY1 - g[0] * SY0, Z = g[2] * SZ2 - g[1] * SZ1;
+    const cplx<R> hX = scal(W[0] * (b3[0] * X), (R)-2), hY = scal(W[1] * (b3[1] * Y), (R)-2);
+    const cplx<R> hZ = scal(W[2] * (b3[2] * Z), (R)-2);
+    dJ[0] = dJ[0] + hX * D[2] + hY * D[1];
+    dJ[1] = dJ[1] + hY * D[0] + hZ * D[2];
+    dJ[2] = dJ[2] + hX * D[0] + hZ * D[1];
   }
-  const cplx<R> J1 = bX * X + bY * Y + bZ * Z;
-  const cplx<R> J = Kp * J1;
-  const cplx<R> J1f = bX * Xf + bY * Yf + bZ * Zf + dbX * X + dbY * Y + dbZ * Z;
-  const cplx<R> J1b = bX * Xb + bY * Yb + bZ * Zb;
-  const cplx<R> J1l = bX * Xl + bY * Yl + bZ * Zl;
-  const cplx<R> GU = Kp * (bX * XU + bY * YU + bZ * ZU);
-  const cplx<R> GV = Kp * (bX * XV + bY * YV + bZ * ZV);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) gf += (dJ[a] * mul_mi(scal(D[a], twopi * lt[a]))).x;  // dD/df = -2 pi i LT D
   // the phase of K' moves by -2 pi f k.R: along f by -2 pi k.R, beta -2 pi f u.R, lambda
   // -2 pi f cos(beta) v.R
-  const R twopi = (R)(2.0 * kPi);
-  const R gf = (Kp * J1f).x + J.y * (twopi * (R)kR);
-  const R gb = (Kp * J1b).x + J.y * (twopi * fr * uR);
-  const R gl = (Kp * J1l).x + J.y * (twopi * fr * sg.cb * vR);
+  gf += Jy * (twopi * (R)kR);
+  gb += Jy * (twopi * fr * uR);
+  gl += Jy * (twopi * fr * sg.cb * vR);
   const double gfd = (double)gf;
   acc.gf += gfd;
   acc.gtf += t * gfd;
@@ -1130,8 +1138,8 @@ __device__ __forceinline__ void grad_sample_uneq(const Cand<R>& s, const CandG<R
   acc.gu_im += (double)GU.y;
   acc.gv_re += (double)GV.x;
   acc.gv_im += (double)GV.y;
-  acc.pt += t * (double)J.y;
-  acc.ptt += t * t * (double)J.y;
+  acc.pt += t * (double)Jy;
+  acc.ptt += t * t * (double)Jy;
 }
 
 }  // namespace gbx
