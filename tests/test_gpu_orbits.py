@@ -9,6 +9,8 @@ and likelihoods take one light time per arm.
   of both channel counts.
 * Mixed gradients within the bar of the equal-arm gradient (MIXED_NAT of the natural scale)
   against the oracle's dual-number gradient; the FP64 gradient is refused as on analytic orbits.
+* The general link sinc up to its quotient form above about 38 mHz (templates at 35 mHz,
+  likelihoods and gradients at 25-55 mHz).
 * Returning to the analytic orbits restores the equal-arm templates.
 """
 
@@ -18,7 +20,7 @@ import pytest
 from paper_2307_03763_amd import api
 from paper_2307_03763_amd import inputs as I
 from tests.gpu_common import banner, delta_logl_error, dev, loglik_tolerance, window_dd
-from tests.test_gpu_grad import MIXED_NAT, _scales
+from tests.test_gpu_grad import MIXED_NAT, _scales, _workload
 from tests.test_gpu_parity import MIXED_SLOPE
 
 pytestmark = pytest.mark.gpu
@@ -50,7 +52,8 @@ def test_templates_on_numerical_orbits(oracle_lib, kepler, tdi):
     rng = np.random.default_rng(70 + tdi)
     g = O.Geometry(I.T1, tdi=tdi)
     worst = 0.0
-    for N, C, f0 in ((64, 2, 0.8e-3), (128, 2, 3e-3), (256, 3, 11e-3), (512, 3, 18e-3), (1024, 3, 27e-3)):
+    for N, C, f0 in ((64, 2, 0.8e-3), (128, 2, 3e-3), (256, 3, 11e-3), (512, 3, 18e-3), (1024, 3, 27e-3),
+                     (1024, 3, 35e-3)):
         th = I.make_theta([f0 * (1 + 0.01 * k) for k in range(3)], I.fdot_gr(f0, 0.6), 1e-22,
                           I.random_angles(rng, 3))
         h, fb = ctx.waveform(dev(th), N, C, api.GB_FP64)
@@ -127,6 +130,56 @@ def test_likelihoods_on_numerical_orbits(oracle_lib, kepler, tdi):
         plan.loglik_grad(th)
     assert err.value.status == api.GB_EUNSUPPORTED
     plan.close()
+    ctx.close()
+
+
+def test_high_frequency_on_numerical_orbits(oracle_lib, kepler):
+    """Windows at 25-55 mHz on the same orbits, where the link arguments reach the quotient form
+    of the sinc above about 38 mHz: FP64 and mixed logL and the mixed gradient against the
+    oracle."""
+    O = oracle_lib
+    pos, t0, dt = kepler
+    banner("numerical orbits: 25-55 mHz, FP64 and mixed logL, mixed gradient")
+    wl = _workload(O, 3, f_lo=25e-3, f_span=30e-3)   # injections from the oracle on these orbits
+    f = np.array([w.sources[0, 0] for w in wl.windows])
+    assert np.all(f > 20e-3) and np.any(f > 40e-3), f
+    ctx = api.context_for(wl.T)
+    ctx.set_orbit(pos, t0, dt)
+    g = O.Geometry(wl.T)
+    d, w, th = dev(wl.data, torch.complex128), dev(wl.weights), dev(wl.theta)
+    dd = window_dd(wl)
+    for prec in (api.GB_FP64, api.GB_MIXED):
+        plan = api.Plan(ctx, wl.window_table(), prec)
+        plan.prepare(d, w)
+        l = plan.loglik(th).cpu().numpy()
+        for i in range(wl.n_win):
+            win = wl.windows[i]
+            a, n = int(wl.cand_off[i]), int(wl.n_cand[i])
+            dw, ww = wl.window_data(i)
+            lo, co = O.loglik(wl.theta[a:a + n], win.k0, win.W, win.N, win.C, dw, ww, g)
+            if prec == api.GB_FP64:
+                tol = loglik_tolerance(dd[i], co[:, 0], co[:, 1])
+                assert np.all(np.abs(l[a:a + n] - lo) <= tol), i
+            else:
+                _, cs = O.loglik(win.sources, win.k0, win.W, win.N, win.C, dw, ww, g)
+                rho = float(np.sqrt(cs[:, 1].max()))
+                e = delta_logl_error(l[a:a + n], lo, l[a], lo[0]).max()
+                assert e <= max(1e-5, MIXED_SLOPE * rho), (i, e, rho)
+        if prec == api.GB_MIXED:
+            _, gr = plan.loglik_grad(th)
+            gr = gr.cpu().numpy()
+            worst = 0.0
+            for i in range(wl.n_win):
+                win = wl.windows[i]
+                a, n = int(wl.cand_off[i]), int(wl.n_cand[i])
+                dw, ww = wl.window_data(i)
+                _, go = O.loglik_grad(wl.theta[a:a + n], win.k0, win.W, win.N, win.C, dw, ww, g)
+                _, co = O.loglik(wl.theta[a:a + n], win.k0, win.W, win.N, win.C, dw, ww, g)
+                err = np.abs(gr[a:a + n] - go) / _scales(O, wl, i, wl.theta[a:a + n], co[:, 1])
+                worst = max(worst, float(err.max()))
+                assert err.max() <= MIXED_NAT, (i, err.max(axis=0))
+            banner(f"  mixed gradient: worst error / natural scale {worst:.2e}")
+        plan.close()
     ctx.close()
 
 
