@@ -133,19 +133,23 @@ def test_likelihoods_on_numerical_orbits(oracle_lib, kepler, tdi):
     ctx.close()
 
 
-def test_high_frequency_on_numerical_orbits(oracle_lib, kepler):
+@pytest.mark.parametrize("tdi", [1, 2])
+def test_high_frequency_on_numerical_orbits(oracle_lib, kepler, tdi):
     """Windows at 25-55 mHz on the same orbits, where the link arguments reach the quotient form
     of the sinc above about 38 mHz: FP64 and mixed logL and the mixed gradient against the
-    oracle."""
+    oracle, both TDI generations."""
     O = oracle_lib
     pos, t0, dt = kepler
-    banner("numerical orbits: 25-55 mHz, FP64 and mixed logL, mixed gradient")
+    banner(f"numerical orbits: 25-55 mHz, FP64 and mixed logL, mixed gradient, TDI {tdi}")
     wl = _workload(O, 3, f_lo=25e-3, f_span=30e-3)   # injections from the oracle on these orbits
+    if tdi == 2:
+        wl.tdi = 2
+        wl = I.finalize_data(wl, O.template_fn(tdi=2), np.random.default_rng(90))
     f = np.array([w.sources[0, 0] for w in wl.windows])
     assert np.all(f > 20e-3) and np.any(f > 40e-3), f
-    ctx = api.context_for(wl.T)
+    ctx = api.context_for(wl.T, tdi=tdi)
     ctx.set_orbit(pos, t0, dt)
-    g = O.Geometry(wl.T)
+    g = O.Geometry(wl.T, tdi=tdi)
     d, w, th = dev(wl.data, torch.complex128), dev(wl.weights), dev(wl.theta)
     dd = window_dd(wl)
     for prec in (api.GB_FP64, api.GB_MIXED):
