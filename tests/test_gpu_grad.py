@@ -180,6 +180,56 @@ def test_gradient_ragged_mixed(oracle_lib, c3_grad):
     assert worst.max() <= MIXED_NAT
 
 
+def test_gradient_edge_cases(oracle_lib):
+    """Mixed gradients on the edge windows of the likelihood tests: N = 1024 with C = 3 and
+    W = 4096, an empty window, a window of one bin and one of N = 64.  A template entirely outside
+    its window has logL = -<d|d>/2 and a gradient of exactly zero; a zero amplitude leaves only
+    dlogL/dA = <d|h_u> (the other components exactly zero); NaN parameters and a negative
+    amplitude give NaN rows; every other row matches the oracle at the mixed bar."""
+    banner("gradient edge cases (mixed)")
+    O = oracle_lib
+    T = I.T1
+    rng = np.random.default_rng(17)
+    specs = [(int(12e-3 * T) - 2048, 4096, 1024, 3), (int(2e-3 * T), 100, 128, 2),
+             (int(5e-3 * T), 1, 256, 2), (int(1e-3 * T) - 32, 64, 64, 2)]
+    ncand = [6, 0, 5, 7]
+    wins, thetas = [], []
+    for (k0, W, N, C), n in zip(specs, ncand):
+        f = (k0 + W / 2) / T
+        th = I.make_theta(np.full(n, f) + rng.uniform(-20, 20, n) / T, 1e-17, 1e-22, I.random_angles(rng, n))
+        wins.append(I.WindowSpec(k0, W, N, C, k0 / T, (k0 + W) / T, th[:1] if n else np.zeros((0, 8))))
+        thetas.append(th)
+    thetas[2][1, 0] = (specs[2][0] + 5000) / T   # far outside its window
+    thetas[2][2, 4] = 0.0                          # zero amplitude
+    thetas[3][2, 2] = np.nan
+    thetas[3][4, 4] = -1e-22
+    wl = I._concat(wins, thetas, "grad edge", T)
+    I.finalize_data(wl, O.template_fn(), np.random.default_rng(18))
+    l, g, _, _ = _run(wl, api.GB_MIXED)
+    g_or = O.Geometry(T)
+    worst = 0.0
+    for i in range(wl.n_win):
+        w = wl.windows[i]
+        d, ww = wl.window_data(i)
+        a, n = int(wl.cand_off[i]), int(wl.n_cand[i])
+        if n == 0:
+            continue
+        th = wl.window_theta(i)
+        ok = np.isfinite(th).all(axis=1) & (th[:, 4] >= 0)
+        assert np.all(np.isnan(l[a:a + n][~ok])) and np.all(np.isnan(g[a:a + n][~ok]))
+        _, go = O.loglik_grad(th[ok], w.k0, w.W, w.N, w.C, d, ww, g_or)
+        _, co = O.loglik(th[ok], w.k0, w.W, w.N, w.C, d, ww, g_or)
+        sc = _scales(O, wl, i, th[ok], co[:, 1])
+        err = np.abs(g[a:a + n][ok] - go) / np.where(sc > 0, sc, 1.0)
+        worst = max(worst, float(err.max()))
+        assert err.max() <= MIXED_NAT, (i, err.max(axis=0))
+    dd = float(np.sum(wl.window_data(2)[1] * np.abs(wl.window_data(2)[0]) ** 2))
+    a = int(wl.cand_off[2])
+    assert abs(l[a + 1] + 0.5 * dd) <= 1e-12 * dd and np.all(g[a + 1] == 0.0)
+    assert np.all(g[a + 2][[0, 1, 2, 3, 5, 6, 7]] == 0.0) and g[a + 2][4] != 0.0
+    banner(f"  worst scaled error {worst:.1e}")
+
+
 def test_fp64_gradient_is_refused(c3_grad):
     """The FP64 gradient is switched off: the call returns GB_EUNSUPPORTED and launches nothing."""
     banner("fp64 gradient refused")
