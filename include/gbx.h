@@ -101,7 +101,7 @@ gb_status gb_waveform(gb_ctx* ctx, const double* theta, int64_t B, int N, int C,
 
 /* The channel count the rule of Sec. II gives a window: the T channel is used at and above half
  * the transfer frequency, f >= f* / 2 = c / (4 pi L) (9.55 mHz for L = 2.5e9 m, the context's arm
- * length), judged at the window's centre f = (k0 + W/2) / T; *C = 3 there and 2 below.  Callers
+ * length), decided at the window's centre f = (k0 + W/2) / T; *C = 3 there and 2 below.  Callers
  * that pass C = 0 to gb_plan_create lay out their data with this count.  GB_EINVAL: null
  * pointers, W < 1. */
 gb_status gb_channels(const gb_ctx* ctx, int64_t k0, int32_t W, int32_t* C);
