@@ -183,6 +183,33 @@ __device__ __forceinline__ void sincos_rev(float x, float* s, float* c) {
   *c = __builtin_amdgcn_cosf(x);
 }
 
+// sin and cos of 2 pi x for an FP64 argument x in revolutions, in precision R, reduced to the
+// nearest quarter turn in FP64.  In FP32 the reduced r (|r| <= 1/8) is rounded; its sine comes
+// from the Taylor series to t^9 at t = 2 pi r (next term below 3e-9), so it keeps its relative
+// accuracy near zero, and its cosine (at least 0.7) from the hardware.  After the rotation by
+// the quarter turns each component is accurate relative to its own size near its zeros.
+// Rounding x to FP32 first (as sincos_rev does) leaves an absolute error of about 2e-7 there,
+// which the TDI factors 1 - D^2 and 1 - D^4 of the link delay turn into a relative template
+// error of that size over their value: near their nulls (f near c / 2L, and c / 4L for the
+// second generation) it grows without bound.
+__device__ __forceinline__ void sincos_rev_red(double x, double* s, double* c) { sincos_rev(x, s, c); }
+__device__ __forceinline__ void sincos_rev_red(double x, float* s, float* c) {
+  const double n = rint(4.0 * x);
+  const float r = (float)(x - 0.25 * n);
+  const float t = r * 6.28318530717958647692f;
+  const float t2 = t * t;
+  float ps = 1.0f / 362880.0f;              // 1/9!
+  ps = ps * t2 - 1.0f / 5040.0f;            // -1/7!
+  ps = ps * t2 + 1.0f / 120.0f;             // 1/5!
+  ps = ps * t2 - 1.0f / 6.0f;               // -1/3!
+  const float sr = t + t * (t2 * ps);
+  const float cr = __builtin_amdgcn_cosf(r);
+  // rotate by the n quarter turns (n mod 4 of a two's-complement integer)
+  const int q = (int)n & 3;
+  *s = q == 0 ? sr : q == 1 ? cr : q == 2 ? -sr : -cr;
+  *c = q == 0 ? cr : q == 1 ? -sr : q == 2 ? -cr : sr;
+}
+
 // sin(u)/u.  For |u| <= 2 the Taylor series in u^2 (next term below 2e-18 in FP64 and 2e-10
 // in FP32 there), the quotient beyond (frequencies above c / (pi L)).
 __device__ __forceinline__ double sinc_r(double u) {
@@ -356,8 +383,10 @@ __device__ __forceinline__ void slow_sample(const Cand<R>& s, const double* __re
   R sD, cD;
   if constexpr (SHORT && sizeof(R) == 8)
     delay_short(x, &sD, &cD);  // D = e^{-2 pi i f L/c}, from x = pi f L/c
-  else
+  else if constexpr (SHORT)
     sincos_rev(-fr * (R)Lc, &sD, &cD);
+  else
+    sincos_rev_red(-f * Lc, &sD, &cD);  // up to the transfer nulls of the TDI factors
 
   // projections on the arms; the arm vectors of the rigid triangle sum to zero, so the third
   // arm's projections are minus the sum of the other two
@@ -788,7 +817,12 @@ __device__ __forceinline__ void grad_sample_rev(const Cand<R>& s, const CandG<R>
   const R fr = (R)f, Lr = (R)Lc;
   R sp, cp, sDm, cDm;
   sincos_rev((R)p, &sp, &cp);
-  sincos_rev(-fr * Lr, &sDm, &cDm);  // D = e^{-i phi_D}: (cDm, sDm), sDm = -sin(phi_D)
+  // D = e^{-i phi_D}: (cDm, sDm), sDm = -sin(phi_D); beyond the short series' range the argument
+  // is reduced in FP64 (the TDI factors' nulls)
+  if constexpr (SHORT)
+    sincos_rev(-fr * Lr, &sDm, &cDm);
+  else
+    sincos_rev_red(-f * Lc, &sDm, &cDm);
   const cplx<R> D = mk<R>(cDm, sDm);
   const R phiD = fr * (R)(2.0 * kPi * Lc);
   const R x = fr * (R)(kPi * Lc);

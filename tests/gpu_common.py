@@ -56,3 +56,46 @@ def delta_logl_error(l_gpu, l_or, ref_gpu, ref_or):
     dg = l_gpu - ref_gpu
     do = l_or - ref_or
     return np.abs(dg - do) / np.maximum(1.0, np.abs(do))
+
+
+def check_logl_and_grad(O, ctx, wl: I.Workload, g):
+    """FP64 logL within the FP64 bound, mixed logL differences within the mixed model (slope
+    times the loudest injection's SNR), and the mixed gradient within the bar of the natural
+    scale, all against the oracle with geometry g, on every window of wl under context ctx.
+    Returns the gradient's worst error over the natural scale."""
+    from tests.test_gpu_grad import MIXED_NAT, _scales
+    from tests.test_gpu_parity import MIXED_SLOPE
+    d, w, th = dev(wl.data, torch.complex128), dev(wl.weights), dev(wl.theta)
+    dd = window_dd(wl)
+    worst = 0.0
+    for prec in (api.GB_FP64, api.GB_MIXED):
+        plan = api.Plan(ctx, wl.window_table(), prec)
+        plan.prepare(d, w)
+        l = plan.loglik(th).cpu().numpy()
+        for i in range(wl.n_win):
+            win = wl.windows[i]
+            a, n = int(wl.cand_off[i]), int(wl.n_cand[i])
+            dw, ww = wl.window_data(i)
+            lo, co = O.loglik(wl.theta[a:a + n], win.k0, win.W, win.N, win.C, dw, ww, g)
+            if prec == api.GB_FP64:
+                tol = loglik_tolerance(dd[i], co[:, 0], co[:, 1])
+                assert np.all(np.abs(l[a:a + n] - lo) <= tol), i
+            else:
+                _, cs = O.loglik(win.sources, win.k0, win.W, win.N, win.C, dw, ww, g)
+                rho = float(np.sqrt(cs[:, 1].max()))
+                e = delta_logl_error(l[a:a + n], lo, l[a], lo[0]).max()
+                assert e <= max(1e-5, MIXED_SLOPE * rho), (i, e, rho)
+        if prec == api.GB_MIXED:
+            _, gr = plan.loglik_grad(th)
+            gr = gr.cpu().numpy()
+            for i in range(wl.n_win):
+                win = wl.windows[i]
+                a, n = int(wl.cand_off[i]), int(wl.n_cand[i])
+                dw, ww = wl.window_data(i)
+                _, go = O.loglik_grad(wl.theta[a:a + n], win.k0, win.W, win.N, win.C, dw, ww, g)
+                _, co = O.loglik(wl.theta[a:a + n], win.k0, win.W, win.N, win.C, dw, ww, g)
+                err = np.abs(gr[a:a + n] - go) / _scales(O, wl, i, wl.theta[a:a + n], co[:, 1])
+                worst = max(worst, float(err.max()))
+                assert err.max() <= MIXED_NAT, (i, err.max(axis=0))
+        plan.close()
+    return worst

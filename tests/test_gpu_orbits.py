@@ -19,7 +19,7 @@ import pytest
 
 from paper_2307_03763_amd import api
 from paper_2307_03763_amd import inputs as I
-from tests.gpu_common import banner, delta_logl_error, dev, loglik_tolerance, window_dd
+from tests.gpu_common import banner, check_logl_and_grad, delta_logl_error, dev, loglik_tolerance, window_dd
 from tests.test_gpu_grad import MIXED_NAT, _scales, _workload
 from tests.test_gpu_parity import MIXED_SLOPE
 
@@ -149,41 +149,8 @@ def test_high_frequency_on_numerical_orbits(oracle_lib, kepler, tdi):
     assert np.all(f > 20e-3) and np.any(f > 40e-3), f
     ctx = api.context_for(wl.T, tdi=tdi)
     ctx.set_orbit(pos, t0, dt)
-    g = O.Geometry(wl.T, tdi=tdi)
-    d, w, th = dev(wl.data, torch.complex128), dev(wl.weights), dev(wl.theta)
-    dd = window_dd(wl)
-    for prec in (api.GB_FP64, api.GB_MIXED):
-        plan = api.Plan(ctx, wl.window_table(), prec)
-        plan.prepare(d, w)
-        l = plan.loglik(th).cpu().numpy()
-        for i in range(wl.n_win):
-            win = wl.windows[i]
-            a, n = int(wl.cand_off[i]), int(wl.n_cand[i])
-            dw, ww = wl.window_data(i)
-            lo, co = O.loglik(wl.theta[a:a + n], win.k0, win.W, win.N, win.C, dw, ww, g)
-            if prec == api.GB_FP64:
-                tol = loglik_tolerance(dd[i], co[:, 0], co[:, 1])
-                assert np.all(np.abs(l[a:a + n] - lo) <= tol), i
-            else:
-                _, cs = O.loglik(win.sources, win.k0, win.W, win.N, win.C, dw, ww, g)
-                rho = float(np.sqrt(cs[:, 1].max()))
-                e = delta_logl_error(l[a:a + n], lo, l[a], lo[0]).max()
-                assert e <= max(1e-5, MIXED_SLOPE * rho), (i, e, rho)
-        if prec == api.GB_MIXED:
-            _, gr = plan.loglik_grad(th)
-            gr = gr.cpu().numpy()
-            worst = 0.0
-            for i in range(wl.n_win):
-                win = wl.windows[i]
-                a, n = int(wl.cand_off[i]), int(wl.n_cand[i])
-                dw, ww = wl.window_data(i)
-                _, go = O.loglik_grad(wl.theta[a:a + n], win.k0, win.W, win.N, win.C, dw, ww, g)
-                _, co = O.loglik(wl.theta[a:a + n], win.k0, win.W, win.N, win.C, dw, ww, g)
-                err = np.abs(gr[a:a + n] - go) / _scales(O, wl, i, wl.theta[a:a + n], co[:, 1])
-                worst = max(worst, float(err.max()))
-                assert err.max() <= MIXED_NAT, (i, err.max(axis=0))
-            banner(f"  mixed gradient: worst error / natural scale {worst:.2e}")
-        plan.close()
+    worst = check_logl_and_grad(O, ctx, wl, O.Geometry(wl.T, tdi=tdi))
+    banner(f"  mixed gradient: worst error / natural scale {worst:.2e}")
     ctx.close()
 
 

@@ -10,8 +10,8 @@ import torch
 
 from paper_2307_03763_amd import api
 from paper_2307_03763_amd import inputs as I
-from tests.gpu_common import banner, delta_logl_error, dev, loglik_tolerance, rel_l2, window_dd
-from tests.test_gpu_grad import MIXED_NAT, _scales
+from tests.gpu_common import banner, check_logl_and_grad, delta_logl_error, dev, loglik_tolerance, rel_l2, window_dd
+from tests.test_gpu_grad import MIXED_NAT, _scales, _workload
 from tests.test_gpu_parity import MIXED_SLOPE
 
 pytestmark = pytest.mark.gpu
@@ -97,4 +97,21 @@ def test_tdi2_gradient_mixed(oracle_lib, tdi2_batch):
     banner("  worst scaled error per parameter: " + " ".join(f"{x:.1e}" for x in worst))
     assert worst.max() <= MIXED_NAT
     plan.close()
+    ctx.close()
+
+
+def test_tdi2_high_frequency(oracle_lib):
+    """Second generation on windows at 30-60 mHz, where the link arguments reach the quotient
+    form of the sinc above about 38 mHz: FP64 and mixed logL and the mixed gradient against the
+    oracle."""
+    O = oracle_lib
+    banner("second generation at 30-60 mHz: FP64 and mixed logL, mixed gradient")
+    wl = _workload(O, 3, f_lo=30e-3, f_span=30e-3)
+    wl.tdi = 2
+    wl = I.finalize_data(wl, O.template_fn(tdi=2), np.random.default_rng(78))
+    f = np.array([w.sources[0, 0] for w in wl.windows])
+    assert np.any(f > 40e-3), f
+    ctx = api.context_for(wl.T, tdi=2)
+    worst = check_logl_and_grad(O, ctx, wl, O.Geometry(wl.T, tdi=2))
+    banner(f"  mixed gradient: worst error / natural scale {worst:.2e}")
     ctx.close()
